@@ -1,0 +1,197 @@
+"""O2: exact pure-DDMC chain -- oracle, test infrastructure only.
+
+In pure DDMC every state (cell, bin) is a state of a finite continuous-time
+Markov chain whose rates are the leakage coefficients of eqs. (10) and (11)
+(Sec. 2.2); the walk of Sec. 2.3 (eqs. 15-16: the smallest of independent
+exponential distances) samples its absorption at the domain boundary.  So the
+expected escape spectrum, the expected number of leakage events and the
+moments of the escape time are solutions of sparse linear systems:
+
+  P = rates / K (jump matrix),  v = (I - P)^-T pi0  (expected visits),
+  p(face, bin) = sum_s v_s r_esc(s -> face, bin) / K_s,
+  E[steps] = sum_s v_s,  E[T] = sum_s v_s / K_s  (c = 1),
+  (I - P) m1 = tau, E[T^2] = 2 sum_s v_s tau_s m1_s, with tau_s = 1 / K_s.
+
+With bulk velocity a spatial move draws x uniformly in the bin, maps it to the
+neighbour's frame (Sec. 2.5) and re-bins it; the exact transition weights are
+the overlaps of the shifted bin with the neighbour's bins (parts outside the
+grid go to the edge bins).  An escaping packet's lab-frame frequency is
+x + mu u_n with x uniform in its bin and mu uniform in (0, 1].
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from . import tables as tb
+
+
+@dataclasses.dataclass
+class ChainResult:
+    spectrum: np.ndarray      # (n_escape_faces, nb + 2) escape probability per face and lab bin
+    faces: list               # face ids of the rows of spectrum
+    steps: float              # E[number of leakage events]
+    steps2: float             # E[steps^2]
+    t_mean: float             # E[escape time] (length / c)
+    t2: float                 # E[escape time^2]
+    visits: np.ndarray        # expected visits per state (nc, nb)
+    total: float              # sum of all escape probabilities (should be 1)
+
+    @property
+    def t_var(self):
+        return self.t2 - self.t_mean ** 2
+
+    @property
+    def steps_var(self):
+        return self.steps2 - self.steps ** 2
+
+    def spectrum_total(self):
+        return self.spectrum.sum(axis=0)
+
+
+def _overlap_matrix(edges, lo, hi):
+    """Fraction of [lo, hi] falling in each bin of ``edges``; the parts below/above the
+    grid are added to the first/last bin.  Returns (bin indices, weights)."""
+    nb = len(edges) - 1
+    w = hi - lo
+    jlo = max(0, int(np.searchsorted(edges, lo, side="right")) - 1)
+    jhi = min(nb - 1, int(np.searchsorted(edges, hi, side="left")) - 1)
+    jlo = min(jlo, nb - 1)
+    jhi = max(jhi, 0)
+    idx, wt = [], []
+    for j in range(jlo, jhi + 1):
+        a = max(lo, edges[j]) if j > 0 else lo
+        b = min(hi, edges[j + 1]) if j < nb - 1 else hi
+        if b > a:
+            idx.append(j)
+            wt.append((b - a) / w)
+    if not idx:   # degenerate: entirely outside the grid
+        idx = [0 if hi <= edges[0] else nb - 1]
+        wt = [1.0]
+    wt = np.asarray(wt)
+    return np.asarray(idx), wt / wt.sum()
+
+
+def _ramp_area(t):
+    t = np.maximum(t, 0.0)
+    return 0.5 * t * t
+
+
+def lab_bin_probs(edges, lo, hi, u):
+    """P(x + mu u in lab bin b) for x ~ U[lo, hi], mu ~ U(0, 1]; b over the nb+2 lab
+    slots (0 = below the grid, nb+1 = above)."""
+    nb = len(edges) - 1
+    out = np.zeros(nb + 2)
+    if abs(u) < 1e-300:
+        cdf = np.clip((edges - lo) / (hi - lo), 0.0, 1.0)
+    else:
+        a2, b2 = (0.0, u) if u > 0 else (u, 0.0)
+        area = (hi - lo) * (b2 - a2)
+        y = edges
+        cdf = (_ramp_area(y - lo - a2) - _ramp_area(y - hi - a2) - _ramp_area(y - lo - b2)
+               + _ramp_area(y - hi - b2)) / area
+        cdf = np.where(y >= hi + b2, 1.0, np.where(y <= lo + a2, 0.0, np.clip(cdf, 0.0, 1.0)))
+        cdf = np.maximum.accumulate(cdf)
+    out[0] = cdf[0]
+    out[1:nb + 1] = np.diff(cdf)
+    out[nb + 1] = 1.0 - cdf[-1]
+    return out
+
+
+def solve(m, tabs=None) -> ChainResult:
+    """Exact expected results of pure DDMC on medium ``m``."""
+    t = tabs if tabs is not None else tb.build(m)
+    if not np.all(t.thick):
+        raise ValueError("the exact chain covers pure DDMC only (every state thick)")
+    nc, nb, nf = t.nc, t.nb, t.nf
+    ns = nc * nb
+    K = t.K.reshape(ns)
+    edges = t.bin_edges
+    rows, cols, vals = [], [], []
+    sidx = np.arange(ns).reshape(nc, nb)
+    # frequency moves
+    for dj, r in ((-1, t.rate_dn), (1, t.rate_up)):
+        mask = r > 0
+        s_from = sidx[mask]
+        s_to = s_from + dj
+        rows.append(s_from)
+        cols.append(s_to)
+        vals.append(r[mask])
+    esc_faces = sorted({f for f in range(nf) if np.any(t.nbr[:, f] == tb.NBR_VACUUM)})
+    face_row = {f: i for i, f in enumerate(esc_faces)}
+    es, ef, eb, er = [], [], [], []   # escape channels: (state, face row, lab slot, rate)
+    lo_e, hi_e = edges[:-1], edges[1:]
+    for f in range(nf):
+        static_f = (t.rho[:, f] == 1.0) & (t.shift[:, f] == 0.0) & (t.nbr[:, f] >= 0)
+        if np.any(static_f):
+            cs = np.nonzero(static_f)[0]
+            r = t.rate_face[cs, :, f]
+            mask = r > 0
+            src_s = (cs[:, None] * nb + np.arange(nb)[None, :])[mask]
+            dst_s = (t.nbr[cs, f][:, None] * nb + np.arange(nb)[None, :])[mask]
+            rows.append(src_s)
+            cols.append(dst_s)
+            vals.append(r[mask])
+        vac_static = (t.nbr[:, f] == tb.NBR_VACUUM) & ((t.u_n[:, f] == 0.0) | (not t.moving))
+        if np.any(vac_static):
+            cs = np.nonzero(vac_static)[0]
+            jj = np.arange(nb)
+            es.append((cs[:, None] * nb + jj[None, :]).ravel())
+            ef.append(np.full(len(cs) * nb, face_row[f]))
+            eb.append(np.tile(jj + 1, len(cs)))
+            er.append(t.rate_face[cs, :, f].ravel())
+        for c in range(nc):
+            n = t.nbr[c, f]
+            r = t.rate_face[c, :, f]
+            if n == tb.NBR_NONE or static_f[c] or vac_static[c]:
+                continue
+            if n == tb.NBR_VACUUM:
+                u = t.u_n[c, f] if t.moving else 0.0
+                for j in range(nb):
+                    if r[j] <= 0:
+                        continue
+                    pb = lab_bin_probs(edges, lo_e[j], hi_e[j], u)
+                    nzb = np.nonzero(pb)[0]
+                    es.append(np.full(len(nzb), c * nb + j))
+                    ef.append(np.full(len(nzb), face_row[f]))
+                    eb.append(nzb)
+                    er.append(r[j] * pb[nzb])
+                continue
+            rho, sh = t.rho[c, f], t.shift[c, f]
+            for j in range(nb):
+                if r[j] <= 0:
+                    continue
+                if rho == 1.0 and sh == 0.0:
+                    rows.append(np.array([c * nb + j]))
+                    cols.append(np.array([n * nb + j]))
+                    vals.append(np.array([r[j]]))
+                else:
+                    idx, wt = _overlap_matrix(edges, rho * lo_e[j] + sh, rho * hi_e[j] + sh)
+                    rows.append(np.full(len(idx), c * nb + j))
+                    cols.append(n * nb + idx)
+                    vals.append(r[j] * wt)
+    rows = np.concatenate(rows)
+    cols = np.concatenate(cols)
+    vals = np.concatenate(vals) / K[rows]
+    P = sp.csr_matrix((vals, (rows, cols)), shape=(ns, ns))
+    A = (sp.identity(ns, format="csr") - P).tocsc()
+    lu = spla.splu(A)
+    pi0 = np.zeros(ns)
+    for st, pr in tb.locate_sources(m):
+        pi0[st] += pr
+    v = lu.solve(pi0, trans="T")
+    tau = 1.0 / K
+    m1 = lu.solve(tau)
+    n1 = lu.solve(np.ones(ns))
+    es, ef, eb, er = (np.concatenate(z) for z in (es, ef, eb, er))
+    spec = np.bincount(ef * (nb + 2) + eb, weights=(v / K)[es] * er,
+                       minlength=len(esc_faces) * (nb + 2)).reshape(len(esc_faces), nb + 2)
+    steps = float(v.sum())
+    steps2 = float(v @ (2.0 * n1 - 1.0))
+    t_mean = float(v @ tau)
+    t2 = float(2.0 * v @ (tau * m1))
+    return ChainResult(spectrum=spec, faces=esc_faces, steps=steps, steps2=steps2, t_mean=t_mean,
+                       t2=t2, visits=v.reshape(nc, nb), total=float(spec.sum()))

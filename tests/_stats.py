@@ -1,0 +1,67 @@
+"""Test statistics for Monte Carlo spectra (per-bin z within 3 sigma, chi^2, L1).
+
+Rules: spectra are compared as escape fractions over the lab slots; bins whose
+expected count is below 10 are merged into their neighbours; the per-bin sigma
+against an exact expectation is sqrt(p (1 - p) / N), against another Monte
+Carlo sample sqrt(s1^2 + s2^2).  Pass: at least 99 % of bins with |z| <= 3,
+chi^2 p-value >= 1e-3 and L1 <= the stated bound.
+"""
+import numpy as np
+from scipy import stats
+
+
+def _merge(expected_counts, *arrays, min_count=10.0):
+    """Greedy left-to-right merge of consecutive bins until each group expects >= min_count."""
+    groups, cur, acc = [], [], 0.0
+    for i, e in enumerate(expected_counts):
+        cur.append(i)
+        acc += e
+        if acc >= min_count:
+            groups.append(cur)
+            cur, acc = [], 0.0
+    if cur:
+        if groups:
+            groups[-1].extend(cur)
+        else:
+            groups.append(cur)
+    return [np.array([a[g].sum() for g in groups]) for a in arrays]
+
+
+def compare_exact(counts, p, n=None):
+    """counts: observed integer counts per slot; p: exact probabilities per slot."""
+    counts = np.asarray(counts, dtype=np.float64).ravel()
+    p = np.asarray(p, dtype=np.float64).ravel()
+    N = counts.sum() if n is None else n
+    c, q = _merge(p * N, counts, p)
+    f = c / N
+    sig = np.sqrt(np.maximum(q * (1 - q), 1e-300) / N)
+    z = (f - q) / sig
+    chi2 = float(np.sum((c - q * N) ** 2 / np.maximum(q * N, 1e-300)))
+    dof = max(len(c) - 1, 1)
+    return {"z": z, "frac_within_3sigma": float(np.mean(np.abs(z) <= 3)), "max_abs_z": float(np.abs(z).max()),
+            "chi2": chi2, "dof": dof, "p_value": float(stats.chi2.sf(chi2, dof)),
+            "L1": float(np.abs(counts / N - p).sum()),
+            "expected_noise_L1": float(np.sum(np.sqrt(2 / np.pi * p * (1 - p) / N)))}
+
+
+def compare_two_samples(c1, c2):
+    c1 = np.asarray(c1, dtype=np.float64).ravel()
+    c2 = np.asarray(c2, dtype=np.float64).ravel()
+    n1, n2 = c1.sum(), c2.sum()
+    pooled = (c1 + c2) / (n1 + n2)
+    a, b, q = _merge(pooled * min(n1, n2), c1, c2, pooled)
+    f1, f2 = a / n1, b / n2
+    sig = np.sqrt(q * (1 - q) * (1 / n1 + 1 / n2))
+    z = (f1 - f2) / np.maximum(sig, 1e-300)
+    chi2 = float(np.sum(z ** 2))
+    dof = max(len(a) - 1, 1)
+    return {"z": z, "frac_within_3sigma": float(np.mean(np.abs(z) <= 3)), "max_abs_z": float(np.abs(z).max()),
+            "chi2": chi2, "dof": dof, "p_value": float(stats.chi2.sf(chi2, dof)),
+            "L1": float(np.abs(c1 / n1 - c2 / n2).sum())}
+
+
+def assert_spectrum_matches(res, l1_max=None):
+    assert res["frac_within_3sigma"] >= 0.99 or res["max_abs_z"] <= 3.0, res
+    assert res["p_value"] >= 1e-3, res
+    if l1_max is not None:
+        assert res["L1"] <= l1_max, res
