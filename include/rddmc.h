@@ -1,0 +1,269 @@
+/*
+ * rddmc.h -- C ABI of the MI355X (gfx950) resonant discrete diffusion Monte Carlo
+ * (rDDMC) Lyman-alpha transport library.
+ *
+ * The method is that of Smith, Tsang, Bromm & Milosavljevic (2017), "Discrete
+ * diffusion Lyman alpha radiative transfer": photon packets random-walk on a joint
+ * (spatial cell) x (frequency bin) grid.  In every step a packet leaks to one face
+ * neighbour (spatial Fick leakage, eq. 10, or the thin/vacuum-face rate of the
+ * hybrid section) or to one neighbouring frequency bin (Fokker-Planck leakage,
+ * eq. 11), chosen as the smallest of exponential distances (eqs. 15-16); the
+ * bin-averaged opacities come from the Voigt expansion of eqs. 12-14.  Packets are
+ * removed at the domain boundary (Sec. 2.3) and their escape frequency, face and
+ * time are tallied.
+ *
+ * Conventions for every call
+ *   - Host pointers are read only during the call; nothing is retained.
+ *   - Device pointers are caller-owned (e.g. torch tensors); the library never
+ *     allocates or frees device memory.  Buffers are sized with the *_bytes queries.
+ *   - Every device operation is enqueued on the caller's stream; results are valid
+ *     after that stream is synchronised.  rddmc_build_leakage and rddmc_tally also
+ *     synchronise the stream themselves (they stage small host data).
+ *   - Errors are returned as rddmc_status; no exceptions cross the ABI.  A
+ *     human-readable message for the calling thread is rddmc_last_error().
+ *   - Output is a pure function of (batch, seed, packet range): packets are keyed
+ *     by their (cloud, packet id) and every tally is an exact integer sum, so
+ *     results are bit-identical for any launch shape, shard split or resume.
+ *
+ * Units: lengths in units of the domain length scale (slab half-width, sphere
+ * radius, or one cell for Cartesian grids); times in length / c; frequencies in
+ * the dimensionless comoving x = (nu - nu0)/dnu_D of each cell (Sec. 2.1);
+ * velocities in km/s; temperatures in K.
+ */
+#ifndef RDDMC_H
+#define RDDMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RDDMC_ABI_VERSION 1
+
+typedef enum {
+    RDDMC_OK = 0,
+    RDDMC_EINVAL = -1,        /* malformed grid, non-finite or negative input, tau_threshold in (0,2) */
+    RDDMC_ESIZE = -2,         /* a caller buffer is smaller than the *_bytes query requires */
+    RDDMC_EUNSUPPORTED = -3,  /* a feature combination this build does not implement */
+    RDDMC_ENUMERIC = -4,      /* a table entry came out non-finite or non-positive */
+    RDDMC_EHIP = -5           /* a HIP runtime call failed */
+} rddmc_status;
+
+enum { RDDMC_SLAB = 0, RDDMC_SPHERE = 1, RDDMC_CART3D = 2 };
+
+/* rddmc_medium.flags */
+#define RDDMC_FLAG_DIRICHLET  (1u << 0)  /* vacuum faces: 2/(3 k dz^2) instead of eq. 10 with 2 lambda */
+#define RDDMC_FLAG_KEEP_RATES (1u << 1)  /* also store the FP64 rates (for table parity checks) */
+
+#define RDDMC_TIME_BINS 128              /* log10-uniform escape-time bins over [1e-3, 1e6] */
+#define RDDMC_STEP_BINS 64               /* floor(log2(steps per packet)) buckets */
+
+/*
+ * One cloud (medium + grid + sources).  Sec. 2.2 (grid, eqs. 10-14), Sec. 2.3
+ * (sources and packets), Sec. 2.5 (bulk velocity).
+ *   geometry     RDDMC_SLAB: 1D Cartesian cells along z; RDDMC_SPHERE: radial shells;
+ *                RDDMC_CART3D: nx*ny*nz cells, linear index (iz*ny + iy)*nx + ix.
+ *   n_cells      {n,1,1} for 1D geometries, {nx,ny,nz} for 3D.
+ *   faces[d]     n_cells[d]+1 strictly increasing face coordinates per axis (1D uses
+ *                faces[0] only; a sphere's faces[0][0] must be >= 0).
+ *   bin_edges    n_bins+1 strictly increasing comoving frequency edges.
+ *   k0, temp     per cell line-centre opacity [1/length] (> 0) and temperature [K] (> 0).
+ *   vel          NULL for a static medium; else per cell: slab v_z, sphere v_r (one value
+ *                per cell), Cartesian (vx,vy,vz) (three values per cell) [km/s].
+ *   tau_threshold  0 selects pure DDMC (every state diffusive); > 0 (must be >= 2, the
+ *                hybrid section's validity bound) makes states with k_ij dz_i below it
+ *                continuous Monte Carlo states.  (Hybrid states: see RDDMC_EUNSUPPORTED.)
+ *   f_mu         Doppler averaging factor of eq. 20 (1/2 for isotropic escape).
+ *   lambda       extrapolation distance of the vacuum/thin-face rate (0.7104).
+ *   n_src, src_pos, src_x  source positions (3 doubles each: slab z; sphere r; Cartesian
+ *                x,y,z) and comoving frequencies.  A source exactly on an interior face
+ *                or bin edge is split with probability 1/2 between its two neighbours;
+ *                packets are shared equally between sources.
+ *   n_packets    packets emitted by this cloud (initial flash, equal weights, t = 0).
+ */
+typedef struct {
+    int32_t geometry;
+    int32_t n_cells[3];
+    int32_t n_bins;
+    uint32_t flags;
+    const double *faces[3];
+    const double *bin_edges;
+    const double *k0;
+    const double *temp;
+    const double *vel;
+    double tau_threshold;
+    double f_mu;
+    double lambda;
+    int32_t n_src;
+    int32_t reserved0;
+    const double *src_pos;
+    const double *src_x;
+    uint64_t n_packets;
+} rddmc_medium;
+
+/* A batch of independent clouds transported together (one persistent launch). */
+typedef struct {
+    int32_t n_clouds;
+    int32_t reserved0;
+    const rddmc_medium *clouds;
+} rddmc_batch;
+
+/*
+ * Transport run parameters.
+ *   seed         Philox4x32-10 key (Salmon et al. 2011); every packet's stream is keyed
+ *                by (seed, cloud, packet id) and indexed by its step count.
+ *   first, count packets first .. first+count-1 of the batch's flattened packet space
+ *                (cloud 0's packets, then cloud 1's, ...); count = 0 means "to the end".
+ *   max_steps    per-packet step cap (>= 1); capped packets are counted, not dropped.
+ *   block, grid  threads per block (multiple of 64, <= 1024) and blocks; 0 = automatic.
+ *   chunk        steps between refills of finished lanes (0 = automatic).
+ */
+typedef struct {
+    uint64_t seed;
+    uint64_t first;
+    uint64_t count;
+    uint64_t max_steps;
+    int32_t block;
+    int32_t grid;
+    int32_t chunk;
+    int32_t reserved0;
+} rddmc_run;
+
+/* Per-cloud summary filled by rddmc_tally (FP64 host-side normalisation of the exact
+ * integer tallies). */
+typedef struct {
+    uint64_t launched;       /* packets emitted in the tallied runs                      */
+    uint64_t escaped;        /* packets that left the domain                             */
+    uint64_t capped;         /* packets stopped by max_steps                             */
+    uint64_t steps_total;    /* leakage events (DDMC steps) summed over packets          */
+    uint64_t steps_max;      /* largest per-packet step count                            */
+    double   steps_mean;     /* steps_total / (escaped + capped)                         */
+    double   t_mean;         /* mean escape time of escaped packets [length / c]         */
+    double   t_var;          /* variance of the escape time                              */
+    int32_t  n_rows;         /* spectrum rows (escape faces): slab 2, sphere 1, 3D 6     */
+    int32_t  n_slots;        /* n_bins + 2 (slot 0 below the grid, slot n_bins+1 above) */
+} rddmc_cloud_stats;
+
+/*
+ * Tally read-back.  For cloud c (in batch order) the caller provides
+ *   spectrum[c]   int64 [n_rows * (n_bins + 2)] escape counts per face row and lab slot,
+ *   time_hist[c]  int64 [RDDMC_TIME_BINS + 2],
+ *   step_hist[c]  int64 [RDDMC_STEP_BINS],
+ *   stats[c].
+ * Any pointer array may be NULL to skip that output.
+ */
+typedef struct {
+    int64_t **spectrum;
+    int64_t **time_hist;
+    int64_t **step_hist;
+    rddmc_cloud_stats *stats;
+} rddmc_tally_out;
+
+/* ---- queries ------------------------------------------------------------------------- */
+
+/* ABI version compiled into the library. */
+int32_t rddmc_abi_version(void);
+
+/* Thread-local message for the last non-OK status returned on this thread. */
+const char *rddmc_last_error(void);
+
+/* Device bytes needed for the leakage tables of a batch (includes a copy of the inputs). */
+rddmc_status rddmc_table_bytes(const rddmc_batch *batch, size_t *bytes);
+
+/* Device bytes for the integer tallies of a batch (caller zeroes them with
+ * rddmc_tally_reset or any fill before the first run; runs accumulate). */
+rddmc_status rddmc_tally_bytes(const rddmc_batch *batch, size_t *bytes);
+
+/* Device bytes for the transport work area (queue counter). */
+rddmc_status rddmc_work_bytes(const rddmc_batch *batch, size_t *bytes);
+
+/* ---- the path ------------------------------------------------------------------------ */
+
+/*
+ * rddmc_build_leakage -- Sec. 2.2 (eqs. 10, 11, 12-14), the hybrid section's thin/vacuum
+ * face rate and the comoving-frame shift of eq. 20.  For every state (cell i, bin j) the
+ * GPU computes in FP64:
+ *   k_ij = k0_i [calH(a_i, x_j+) - calH(a_i, x_j-)] / dx_j            (eqs. 13-14)
+ *   face rates (A_f/dV_i) 2 / (3 (k_ij w_i + k'_nb w_nb))            (eq. 10; A/dV = 1/w
+ *            for Cartesian cells, r_f^2/((r_+^3 - r_-^3)/3) for shells), with k'_nb the
+ *            neighbour's opacity averaged over the Doppler-shifted image of bin j;
+ *            vacuum faces (A_f/dV_i) 2 / (3 (k_ij w_i + 2 lambda));
+ *   frequency rates 1 / (dx_j (dx_j/k_ij + dx_j'/k_ij'))             (eq. 11), zero past
+ *            the first and last bin (reflecting frequency edges);
+ * and stores, per state, a 16-byte hot record {ln2/K (f32), high words of the u64
+ * categorical thresholds D = P(lower bin) 2^64 and S = (1 - P(spatial)) 2^64} plus cold
+ * arrays (their low words, the face split, k_ij, Doppler maps).
+ *   batch        host description, read during the call.
+ *   d_tables     device buffer of >= rddmc_table_bytes bytes, 256-byte aligned.
+ *   stream       hipStream_t (NULL = default stream); the call synchronises it.
+ * Errors: EINVAL (bad grid or inputs), ESIZE (buffer), ENUMERIC (non-finite table entry),
+ * EUNSUPPORTED (mixed geometries in one batch, 3D, or hybrid states), EHIP.
+ */
+rddmc_status rddmc_build_leakage(const rddmc_batch *batch, void *d_tables, size_t table_bytes,
+                                 void *stream);
+
+/*
+ * rddmc_transport -- the walk of Sec. 2.3 (eqs. 15-16), emission as an initial flash
+ * (Sec. 2.3), Doppler re-binning across faces (Sec. 2.5) and removal at the boundary.
+ * A persistent kernel: every lane carries one packet; every run.chunk steps finished
+ * lanes take new packet ids from a work counter.  One Philox4x32-10 block serves two
+ * steps; each step takes one 32-bit word for the exponential path length (time advances
+ * in FP64 by dl = -ln(xi)/K) and one as the high word of a u64 uniform compared with the
+ * categorical thresholds (lower bin / upper bin / spatial leak); the low word, the face
+ * choice and re-binning draws come from an auxiliary block only when needed.  This is
+ * the same law as the smallest of independent exponentials, exact to 2^-64 in every
+ * event probability.  Escapes add to the integer tallies with device atomics.
+ *   batch        the same host description passed to rddmc_build_leakage.
+ *   d_tables     tables written by rddmc_build_leakage for that batch.
+ *   run          run parameters (see rddmc_run).
+ *   d_tally      >= rddmc_tally_bytes bytes; accumulated into (not cleared).
+ *   d_work       >= rddmc_work_bytes bytes; cleared by the call (with a kernel).
+ *   stream       hipStream_t; asynchronous.
+ * Errors: EINVAL (run parameters), ESIZE, EHIP.
+ */
+rddmc_status rddmc_transport(const rddmc_batch *batch, const void *d_tables, const rddmc_run *run,
+                             void *d_tally, size_t tally_bytes, void *d_work, size_t work_bytes,
+                             void *stream);
+
+/* Zero a tally buffer with a kernel on the stream (safe under stream capture). */
+rddmc_status rddmc_tally_reset(const rddmc_batch *batch, void *d_tally, size_t tally_bytes,
+                               void *stream);
+
+/*
+ * rddmc_tally -- copy the exact integer tallies of every cloud to the caller's host
+ * arrays and derive the FP64 summaries (mean steps, mean and variance of the escape
+ * time from the int64 fixed-point sums).  Synchronises the stream.
+ * Errors: EINVAL (NULL out), ESIZE, EHIP.
+ */
+rddmc_status rddmc_tally(const rddmc_batch *batch, const void *d_tally, size_t tally_bytes,
+                         rddmc_tally_out *out, void *stream);
+
+/* ---- validation helpers (same kernels, exposed for parity tests) ---------------------- */
+
+/*
+ * Copy back, for cloud `cloud`, the per-state arrays the builder computed:
+ *   k         [n_states]          FP64 bin-averaged opacity (eq. 14)
+ *   rates     [n_states * (nf+2)] FP64 face rates (nf = 2 for 1D, 6 for 3D), then the
+ *             lower and upper frequency rates; only with RDDMC_FLAG_KEEP_RATES (else EINVAL)
+ *   hot       [n_states * 16 bytes] hot records {ln2/K f32, D>>32 u32, S>>32 u32, 0}
+ *   lo_words  [n_states * 8 bytes] {D & 0xffffffff, S & 0xffffffff}
+ * where D = P(lower bin) * 2^64 and S = (1 - P(spatial)) * 2^64 (rounded).  Any pointer
+ * may be NULL.  Synchronises the stream.
+ */
+rddmc_status rddmc_read_tables(const rddmc_batch *batch, const void *d_tables, int32_t cloud,
+                               double *k, double *rates, void *hot, void *lo_words, void *stream);
+
+/*
+ * Fill d_out[4*n] with Philox4x32-10 blocks for counters (c0 + i, c1, c2, c3), i < n, under
+ * key (k0, k1) -- the generator the walk uses, for known-answer tests.
+ */
+rddmc_status rddmc_philox_fill(uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1, uint32_t c2,
+                               uint32_t c3, uint64_t n, uint32_t *d_out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RDDMC_H */

@@ -1,0 +1,452 @@
+// C ABI of the rDDMC library: argument validation, table/tally layout, host staging of
+// the small per-cloud inputs, and kernel launches.  No transport arithmetic runs here.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "rddmc_internal.h"
+
+using namespace rddmc;
+
+namespace {
+
+thread_local std::string g_err;
+
+rddmc_status fail(rddmc_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+rddmc_status hip_fail(hipError_t e, const char *what)
+{
+    return fail(RDDMC_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+constexpr uint64_t kAlign = 256;
+uint64_t align_up(uint64_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
+
+bool finite_all(const double *p, size_t n)
+{
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+bool increasing(const double *p, size_t n)
+{
+    for (size_t i = 0; i + 1 < n; ++i)
+        if (!(p[i] < p[i + 1])) return false;
+    return true;
+}
+
+// Emission states of one source coordinate: the containing cell, or both cells (1/2
+// each) when the coordinate lies exactly on an interior face.
+bool split_coord(const double *f, int n, double v, std::vector<std::pair<int, double>> &out)
+{
+    out.clear();
+    if (!(v >= f[0] && v <= f[n])) return false;
+    for (int e = 0; e <= n; ++e) {
+        if (f[e] == v) {
+            if (e == 0) out.push_back({0, 1.0});
+            else if (e == n) out.push_back({n - 1, 1.0});
+            else {
+                out.push_back({e - 1, 0.5});
+                out.push_back({e, 0.5});
+            }
+            return true;
+        }
+    }
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        int mid = (lo + hi) / 2;
+        if (v >= f[mid]) lo = mid; else hi = mid;
+    }
+    out.push_back({lo, 1.0});
+    return true;
+}
+
+struct Layout {
+    DevHeader h{};
+    std::vector<DevCloud> clouds;
+    std::vector<uint64_t> prefix;
+    std::vector<std::vector<int32_t>> src_state;
+    std::vector<std::vector<double>> src_cdf;
+    uint64_t table_bytes = 0;
+    uint64_t tally_words = 0;
+    bool any_moving = false;
+};
+
+rddmc_status validate_cloud(const rddmc_medium &m, int idx)
+{
+    if (m.geometry != RDDMC_SLAB && m.geometry != RDDMC_SPHERE && m.geometry != RDDMC_CART3D)
+        return fail(RDDMC_EINVAL, "cloud %d: unknown geometry %d", idx, m.geometry);
+    const int nd = m.geometry == RDDMC_CART3D ? 3 : 1;
+    for (int d = 0; d < 3; ++d) {
+        if (m.n_cells[d] < 1) return fail(RDDMC_EINVAL, "cloud %d: n_cells[%d] < 1", idx, d);
+        if (d >= nd && m.n_cells[d] != 1)
+            return fail(RDDMC_EINVAL, "cloud %d: 1D geometry needs n_cells = {n,1,1}", idx);
+    }
+    if (m.n_bins < 1) return fail(RDDMC_EINVAL, "cloud %d: n_bins < 1", idx);
+    for (int d = 0; d < nd; ++d) {
+        if (!m.faces[d]) return fail(RDDMC_EINVAL, "cloud %d: faces[%d] is NULL", idx, d);
+        if (!finite_all(m.faces[d], m.n_cells[d] + 1) || !increasing(m.faces[d], m.n_cells[d] + 1))
+            return fail(RDDMC_EINVAL, "cloud %d: faces[%d] not finite and strictly increasing", idx, d);
+    }
+    if (m.geometry == RDDMC_SPHERE && m.faces[0][0] < 0.0)
+        return fail(RDDMC_EINVAL, "cloud %d: negative sphere radius", idx);
+    if (!m.bin_edges || !finite_all(m.bin_edges, m.n_bins + 1) || !increasing(m.bin_edges, m.n_bins + 1))
+        return fail(RDDMC_EINVAL, "cloud %d: bin edges not finite and strictly increasing", idx);
+    const int64_t nc = (int64_t)m.n_cells[0] * m.n_cells[1] * m.n_cells[2];
+    if (!m.k0 || !m.temp) return fail(RDDMC_EINVAL, "cloud %d: k0/temp NULL", idx);
+    for (int64_t c = 0; c < nc; ++c) {
+        if (!(m.k0[c] > 0.0) || !std::isfinite(m.k0[c]))
+            return fail(RDDMC_EINVAL, "cloud %d: k0[%lld] must be finite and > 0", idx, (long long)c);
+        if (!(m.temp[c] > 0.0) || !std::isfinite(m.temp[c]))
+            return fail(RDDMC_EINVAL, "cloud %d: temp[%lld] must be finite and > 0", idx, (long long)c);
+    }
+    if (m.vel && !finite_all(m.vel, (size_t)nc * (m.geometry == RDDMC_CART3D ? 3 : 1)))
+        return fail(RDDMC_EINVAL, "cloud %d: non-finite velocity", idx);
+    if (!(m.tau_threshold == 0.0 || m.tau_threshold >= 2.0) || !std::isfinite(m.tau_threshold))
+        return fail(RDDMC_EINVAL, "cloud %d: tau_threshold must be 0 (pure DDMC) or >= 2", idx);
+    if (!(m.f_mu >= 0.0 && m.f_mu <= 1.0)) return fail(RDDMC_EINVAL, "cloud %d: f_mu outside [0,1]", idx);
+    if (!(m.lambda > 0.0) || !std::isfinite(m.lambda)) return fail(RDDMC_EINVAL, "cloud %d: lambda <= 0", idx);
+    if (m.n_src < 1 || !m.src_pos || !m.src_x) return fail(RDDMC_EINVAL, "cloud %d: no sources", idx);
+    if (m.n_packets >= (1ull << 32)) return fail(RDDMC_EINVAL, "cloud %d: n_packets >= 2^32", idx);
+    return RDDMC_OK;
+}
+
+rddmc_status make_layout(const rddmc_batch *b, Layout &L)
+{
+    if (!b || b->n_clouds < 1 || !b->clouds) return fail(RDDMC_EINVAL, "empty batch");
+    const int n = b->n_clouds;
+    L.clouds.assign(n, DevCloud{});
+    L.prefix.assign(n + 1, 0);
+    L.src_state.assign(n, {});
+    L.src_cdf.assign(n, {});
+    const int geom = b->clouds[0].geometry;
+    uint64_t off = 0;
+    L.h.n_clouds = n;
+    L.h.geometry = geom;
+    off = align_up(sizeof(DevHeader));
+    L.h.off_clouds = off;
+    off = align_up(off + sizeof(DevCloud) * n);
+    L.h.off_prefix = off;
+    off = align_up(off + sizeof(uint64_t) * (n + 1));
+    uint64_t tally = 0;
+    for (int ci = 0; ci < n; ++ci) {
+        const rddmc_medium &m = b->clouds[ci];
+        rddmc_status st = validate_cloud(m, ci);
+        if (st != RDDMC_OK) return st;
+        if (m.geometry != geom) return fail(RDDMC_EUNSUPPORTED, "mixed geometries in one batch");
+        if (m.geometry == RDDMC_CART3D) return fail(RDDMC_EUNSUPPORTED, "3D Cartesian transport is not built yet");
+        DevCloud &c = L.clouds[ci];
+        c.geometry = m.geometry;
+        c.nb = m.n_bins;
+        c.n[0] = m.n_cells[0];
+        c.n[1] = m.n_cells[1];
+        c.n[2] = m.n_cells[2];
+        c.nc = m.n_cells[0] * m.n_cells[1] * m.n_cells[2];
+        c.nf = m.geometry == RDDMC_CART3D ? 6 : 2;
+        c.n_rows = m.geometry == RDDMC_SLAB ? 2 : (m.geometry == RDDMC_SPHERE ? 1 : 6);
+        c.keep_rates = (m.flags & RDDMC_FLAG_KEEP_RATES) ? 1 : 0;
+        c.dirichlet = (m.flags & RDDMC_FLAG_DIRICHLET) ? 1 : 0;
+        c.moving = 0;
+        if (m.vel) {
+            const size_t nv = (size_t)c.nc * (m.geometry == RDDMC_CART3D ? 3 : 1);
+            for (size_t i = 0; i < nv; ++i)
+                if (m.vel[i] != 0.0) c.moving = 1;
+        }
+        L.any_moving |= c.moving != 0;
+        c.n_packets = m.n_packets;
+        c.packet_base = L.prefix[ci];
+        L.prefix[ci + 1] = L.prefix[ci] + m.n_packets;
+        c.n_states = (uint64_t)c.nc * c.nb;
+        c.tau_th = m.tau_threshold;
+        c.f_mu = m.f_mu;
+        c.lambda = m.lambda;
+        // sources -> (state, probability)
+        std::map<int32_t, double> acc;
+        std::vector<std::pair<int, double>> bins, cx, cy, cz;
+        for (int s = 0; s < m.n_src; ++s) {
+            if (!split_coord(m.bin_edges, m.n_bins, m.src_x[s], bins))
+                return fail(RDDMC_EINVAL, "cloud %d: source %d frequency outside the grid", ci, s);
+            const double *p = m.src_pos + 3 * s;
+            if (!split_coord(m.faces[0], m.n_cells[0], p[0], cx))
+                return fail(RDDMC_EINVAL, "cloud %d: source %d outside the grid", ci, s);
+            for (auto &a : cx)
+                for (auto &bb : bins)
+                    acc[a.first * m.n_bins + bb.first] += a.second * bb.second / m.n_src;
+        }
+        double cum = 0.0;
+        for (auto &kv : acc) {
+            cum += kv.second;
+            L.src_state[ci].push_back(kv.first);
+            L.src_cdf[ci].push_back(cum);
+        }
+        L.src_cdf[ci].back() = 1.0;
+        c.n_src = (int32_t)L.src_state[ci].size();
+        // table regions
+        auto take = [&](uint64_t bytes) {
+            const uint64_t o = off;
+            off = align_up(off + bytes);
+            return o;
+        };
+        c.off_edges = take(8ull * (c.nb + 1));
+        for (int d = 0; d < 3; ++d) c.off_faces[d] = take(8ull * (c.n[d] + 1));
+        c.off_k0 = take(8ull * c.nc);
+        c.off_T = take(8ull * c.nc);
+        c.off_vel = take(8ull * c.nc * (m.geometry == RDDMC_CART3D ? 3 : 1));
+        c.off_src_state = take(4ull * c.n_src);
+        c.off_src_cdf = take(8ull * c.n_src);
+        c.off_k = take(8ull * c.n_states);
+        c.off_hot = take(sizeof(HotRecord) * c.n_states);
+        c.off_lo_words = take(8ull * c.n_states);
+        c.off_face_split = take(4ull * c.n_states * (c.nf - 1));
+        c.off_rates = c.keep_rates ? take(8ull * c.n_states * (c.nf + 2)) : 0;
+        c.off_map = take(8ull * 3 * c.nc * c.nf);
+        c.tally_off = tally;
+        c.tally_words = kTallyHeader + (uint64_t)c.n_rows * (c.nb + 2) + (RDDMC_TIME_BINS + 2) + RDDMC_STEP_BINS;
+        tally += c.tally_words;
+    }
+    L.h.total_packets = L.prefix[n];
+    L.table_bytes = off;
+    L.tally_words = tally;
+    return RDDMC_OK;
+}
+
+void put(std::vector<uint8_t> &buf, uint64_t off, const void *src, size_t bytes)
+{
+    if (bytes) std::memcpy(buf.data() + off, src, bytes);
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t rddmc_abi_version(void) { return RDDMC_ABI_VERSION; }
+
+const char *rddmc_last_error(void) { return g_err.c_str(); }
+
+rddmc_status rddmc_table_bytes(const rddmc_batch *batch, size_t *bytes)
+{
+    if (!bytes) return fail(RDDMC_EINVAL, "bytes is NULL");
+    Layout L;
+    rddmc_status st = make_layout(batch, L);
+    if (st != RDDMC_OK) return st;
+    *bytes = L.table_bytes;
+    return RDDMC_OK;
+}
+
+rddmc_status rddmc_tally_bytes(const rddmc_batch *batch, size_t *bytes)
+{
+    if (!bytes) return fail(RDDMC_EINVAL, "bytes is NULL");
+    Layout L;
+    rddmc_status st = make_layout(batch, L);
+    if (st != RDDMC_OK) return st;
+    *bytes = L.tally_words * 8;
+    return RDDMC_OK;
+}
+
+rddmc_status rddmc_work_bytes(const rddmc_batch *batch, size_t *bytes)
+{
+    if (!bytes) return fail(RDDMC_EINVAL, "bytes is NULL");
+    Layout L;
+    rddmc_status st = make_layout(batch, L);
+    if (st != RDDMC_OK) return st;
+    *bytes = 256;
+    return RDDMC_OK;
+}
+
+rddmc_status rddmc_build_leakage(const rddmc_batch *batch, void *d_tables, size_t table_bytes, void *stream)
+{
+    Layout L;
+    rddmc_status st = make_layout(batch, L);
+    if (st != RDDMC_OK) return st;
+    if (!d_tables) return fail(RDDMC_EINVAL, "d_tables is NULL");
+    if ((uintptr_t)d_tables % kAlign) return fail(RDDMC_EINVAL, "d_tables must be 256-byte aligned");
+    if (table_bytes < L.table_bytes)
+        return fail(RDDMC_ESIZE, "table buffer %zu < required %llu", table_bytes, (unsigned long long)L.table_bytes);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    // Stage the header, descriptors and prefix, then each cloud's input copies (a
+    // contiguous region per cloud).  Derived arrays are written by the kernels.
+    hipError_t e;
+    std::vector<std::vector<uint8_t>> bufs;
+    {
+        const uint64_t hdr_end = L.clouds[0].off_edges;
+        bufs.emplace_back(hdr_end, 0);
+        auto &buf = bufs.back();
+        put(buf, 0, &L.h, sizeof L.h);
+        put(buf, L.h.off_clouds, L.clouds.data(), sizeof(DevCloud) * L.clouds.size());
+        put(buf, L.h.off_prefix, L.prefix.data(), 8 * L.prefix.size());
+        if ((e = hipMemcpyAsync(d_tables, buf.data(), hdr_end, hipMemcpyHostToDevice, s)) != hipSuccess)
+            return hip_fail(e, "hipMemcpyAsync(header)");
+    }
+    for (int ci = 0; ci < L.h.n_clouds; ++ci) {
+        const rddmc_medium &m = batch->clouds[ci];
+        const DevCloud &c = L.clouds[ci];
+        const uint64_t a = c.off_edges, z = c.off_src_cdf + 8ull * c.n_src;
+        bufs.emplace_back(z - a, 0);
+        auto &buf = bufs.back();
+        put(buf, c.off_edges - a, m.bin_edges, 8ull * (c.nb + 1));
+        for (int d = 0; d < 3; ++d) {
+            if (m.faces[d] && (d == 0 || c.geometry == RDDMC_CART3D)) {
+                put(buf, c.off_faces[d] - a, m.faces[d], 8ull * (c.n[d] + 1));
+            } else {
+                const double unit[2] = {0.0, 1.0};
+                put(buf, c.off_faces[d] - a, unit, 16);
+            }
+        }
+        put(buf, c.off_k0 - a, m.k0, 8ull * c.nc);
+        put(buf, c.off_T - a, m.temp, 8ull * c.nc);
+        if (m.vel) put(buf, c.off_vel - a, m.vel, 8ull * c.nc * (c.geometry == RDDMC_CART3D ? 3 : 1));
+        put(buf, c.off_src_state - a, L.src_state[ci].data(), 4ull * c.n_src);
+        put(buf, c.off_src_cdf - a, L.src_cdf[ci].data(), 8ull * c.n_src);
+        if ((e = hipMemcpyAsync(static_cast<uint8_t *>(d_tables) + a, buf.data(), z - a, hipMemcpyHostToDevice,
+                                s)) != hipSuccess)
+            return hip_fail(e, "hipMemcpyAsync(inputs)");
+    }
+    for (int ci = 0; ci < L.h.n_clouds; ++ci)
+        if ((e = launch_build(L.clouds[ci], ci, static_cast<uint8_t *>(d_tables), s)) != hipSuccess)
+            return hip_fail(e, "build kernels");
+    uint32_t flags = 0;
+    if ((e = hipMemcpyAsync(&flags, &reinterpret_cast<DevHeader *>(d_tables)->error_flags, 4,
+                            hipMemcpyDeviceToHost, s)) != hipSuccess)
+        return hip_fail(e, "hipMemcpyAsync(flags)");
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    if (flags & BE_NONFINITE) return fail(RDDMC_ENUMERIC, "a leakage table entry is non-finite or non-positive");
+    if (flags & BE_THIN)
+        return fail(RDDMC_EUNSUPPORTED, "thin (continuous Monte Carlo) states are not built yet; use tau_threshold = 0");
+    return RDDMC_OK;
+}
+
+rddmc_status rddmc_tally_reset(const rddmc_batch *batch, void *d_tally, size_t tally_bytes, void *stream)
+{
+    Layout L;
+    rddmc_status st = make_layout(batch, L);
+    if (st != RDDMC_OK) return st;
+    if (!d_tally) return fail(RDDMC_EINVAL, "d_tally is NULL");
+    if (tally_bytes < L.tally_words * 8) return fail(RDDMC_ESIZE, "tally buffer too small");
+    hipError_t e = launch_zero(d_tally, L.tally_words, reinterpret_cast<hipStream_t>(stream));
+    return e == hipSuccess ? RDDMC_OK : hip_fail(e, "zero kernel");
+}
+
+rddmc_status rddmc_transport(const rddmc_batch *batch, const void *d_tables, const rddmc_run *run,
+                             void *d_tally, size_t tally_bytes, void *d_work, size_t work_bytes, void *stream)
+{
+    Layout L;
+    rddmc_status st = make_layout(batch, L);
+    if (st != RDDMC_OK) return st;
+    if (!d_tables || !run || !d_tally || !d_work) return fail(RDDMC_EINVAL, "NULL argument");
+    if (tally_bytes < L.tally_words * 8) return fail(RDDMC_ESIZE, "tally buffer too small");
+    if (work_bytes < 256) return fail(RDDMC_ESIZE, "work buffer too small");
+    if (run->max_steps < 1) return fail(RDDMC_EINVAL, "max_steps must be >= 1");
+    if (run->block < 0 || run->block > 1024 || (run->block % 64) != 0)
+        return fail(RDDMC_EINVAL, "block must be a multiple of 64 in [64, 1024] (or 0)");
+    if (run->block > 256) return fail(RDDMC_EINVAL, "the walk kernel is built for blocks of at most 256 lanes");
+    if (run->grid < 0 || run->chunk < 0) return fail(RDDMC_EINVAL, "negative grid or chunk");
+    const uint64_t total = L.h.total_packets;
+    if (run->first > total) return fail(RDDMC_EINVAL, "first beyond the batch's packets");
+    const uint64_t count = run->count ? run->count : total - run->first;
+    if (count > total - run->first) return fail(RDDMC_EINVAL, "first + count beyond the batch's packets");
+    if (count == 0) return RDDMC_OK;
+    hipError_t e = launch_walk(static_cast<const uint8_t *>(d_tables), L.h, L.clouds.data(), *run, run->first,
+                               count, static_cast<unsigned long long *>(d_tally),
+                               static_cast<unsigned long long *>(d_work), reinterpret_cast<hipStream_t>(stream));
+    return e == hipSuccess ? RDDMC_OK : hip_fail(e, "walk kernel");
+}
+
+rddmc_status rddmc_tally(const rddmc_batch *batch, const void *d_tally, size_t tally_bytes, rddmc_tally_out *out,
+                         void *stream)
+{
+    Layout L;
+    rddmc_status st = make_layout(batch, L);
+    if (st != RDDMC_OK) return st;
+    if (!d_tally || !out) return fail(RDDMC_EINVAL, "NULL argument");
+    if (tally_bytes < L.tally_words * 8) return fail(RDDMC_ESIZE, "tally buffer too small");
+    std::vector<uint64_t> h(L.tally_words);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e = hipMemcpyAsync(h.data(), d_tally, L.tally_words * 8, hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(tally)");
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    for (int ci = 0; ci < L.h.n_clouds; ++ci) {
+        const DevCloud &c = L.clouds[ci];
+        const uint64_t *w = h.data() + c.tally_off;
+        const uint64_t nspec = (uint64_t)c.n_rows * (c.nb + 2);
+        if (out->spectrum && out->spectrum[ci]) std::memcpy(out->spectrum[ci], w + kTallyHeader, 8 * nspec);
+        if (out->time_hist && out->time_hist[ci])
+            std::memcpy(out->time_hist[ci], w + kTallyHeader + nspec, 8 * (RDDMC_TIME_BINS + 2));
+        if (out->step_hist && out->step_hist[ci])
+            std::memcpy(out->step_hist[ci], w + kTallyHeader + nspec + RDDMC_TIME_BINS + 2, 8 * RDDMC_STEP_BINS);
+        if (out->stats) {
+            rddmc_cloud_stats &z = out->stats[ci];
+            z.launched = w[TW_LAUNCHED];
+            z.escaped = w[TW_ESCAPED];
+            z.capped = w[TW_CAPPED];
+            z.steps_total = w[TW_STEPS];
+            z.steps_max = w[TW_STEPS_MAX];
+            const double done = (double)(z.escaped + z.capped);
+            z.steps_mean = done > 0 ? (double)z.steps_total / done : 0.0;
+            const double ne = (double)z.escaped;
+            const double tsum = (double)w[TW_TSUM] / kTimeFix;
+            const long double t2 = ((long double)w[TW_T2_HI] * 18446744073709551616.0L + (long double)w[TW_T2_LO]) /
+                                   (long double)kTimeFix;
+            z.t_mean = ne > 0 ? tsum / ne : 0.0;
+            z.t_var = ne > 0 ? (double)(t2 / (long double)ne) - z.t_mean * z.t_mean : 0.0;
+            z.n_rows = c.n_rows;
+            z.n_slots = c.nb + 2;
+        }
+    }
+    return RDDMC_OK;
+}
+
+rddmc_status rddmc_read_tables(const rddmc_batch *batch, const void *d_tables, int32_t cloud, double *k,
+                               double *rates, void *hot, void *lo_words, void *stream)
+{
+    Layout L;
+    rddmc_status st = make_layout(batch, L);
+    if (st != RDDMC_OK) return st;
+    if (!d_tables) return fail(RDDMC_EINVAL, "d_tables is NULL");
+    if (cloud < 0 || cloud >= L.h.n_clouds) return fail(RDDMC_EINVAL, "cloud index out of range");
+    const DevCloud &c = L.clouds[cloud];
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const uint8_t *base = static_cast<const uint8_t *>(d_tables);
+    hipError_t e;
+    if (k && (e = hipMemcpyAsync(k, base + c.off_k, 8 * c.n_states, hipMemcpyDeviceToHost, s)) != hipSuccess)
+        return hip_fail(e, "read k");
+    if (rates) {
+        if (!c.keep_rates) return fail(RDDMC_EINVAL, "rates were not kept (RDDMC_FLAG_KEEP_RATES)");
+        if ((e = hipMemcpyAsync(rates, base + c.off_rates, 8 * c.n_states * (c.nf + 2), hipMemcpyDeviceToHost, s)) !=
+            hipSuccess)
+            return hip_fail(e, "read rates");
+    }
+    if (hot && (e = hipMemcpyAsync(hot, base + c.off_hot, sizeof(HotRecord) * c.n_states, hipMemcpyDeviceToHost,
+                                   s)) != hipSuccess)
+        return hip_fail(e, "read hot");
+    if (lo_words && (e = hipMemcpyAsync(lo_words, base + c.off_lo_words, 8 * c.n_states, hipMemcpyDeviceToHost,
+                                        s)) != hipSuccess)
+        return hip_fail(e, "read lo words");
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    return RDDMC_OK;
+}
+
+rddmc_status rddmc_philox_fill(uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                               uint64_t n, uint32_t *d_out, void *stream)
+{
+    if (!d_out && n) return fail(RDDMC_EINVAL, "d_out is NULL");
+    hipError_t e = launch_philox_fill(k0, k1, c0, c1, c2, c3, n, d_out, reinterpret_cast<hipStream_t>(stream));
+    return e == hipSuccess ? RDDMC_OK : hip_fail(e, "philox kernel");
+}
+
+}  // extern "C"

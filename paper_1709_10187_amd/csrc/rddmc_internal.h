@@ -1,0 +1,90 @@
+// Internal layout shared by the library's translation units (host and device).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/rddmc.h"
+
+namespace rddmc {
+
+constexpr int kMaxFaces = 6;
+constexpr double kTimeFix = 1048576.0;          // escape-time fixed point: 2^-20 length/c per unit
+constexpr int kTallyHeader = 16;                // int64 words before the spectrum
+
+// Tally header words (per cloud)
+enum TallyWord {
+    TW_ESCAPED = 0,
+    TW_CAPPED = 1,
+    TW_STEPS = 2,
+    TW_STEPS_MAX = 3,
+    TW_TSUM = 4,      // sum of round(t * 2^20)
+    TW_T2_LO = 5,     // 128-bit sum of round(t^2 * 2^20): low word
+    TW_T2_HI = 6,     //                                   high word
+    TW_LAUNCHED = 7,
+};
+
+// The per-state record every DDMC step reads: one 16-byte load.  With
+// D = P(lower bin) * 2^64 and S = (P(lower bin) + P(upper bin)) * 2^64 (u64), a uniform
+// u64 U selects: U < D -> lower bin, D <= U < S -> upper bin, U >= S -> spatial leak.
+// Only the high words of D and S live here; the low words (needed only when the high
+// word of U ties with one of them, probability ~2^-31) live in the cold `lo_words` array.
+struct alignas(16) HotRecord {
+    float ln2_over_K;      // ln(2) / K, K = total leakage rate of the state [1/length]
+    uint32_t d_hi;         // high word of D
+    uint32_t s_hi;         // high word of S
+    uint32_t spare;
+};
+static_assert(sizeof(HotRecord) == 16, "hot record must be 16 bytes");
+
+// Device-resident per-cloud descriptor.  Offsets are bytes from the table base.
+struct alignas(16) DevCloud {
+    int32_t geometry, nb, nc, nf;
+    int32_t n[3];
+    int32_t moving;
+    int32_t n_src, keep_rates, n_rows, dirichlet;
+    uint64_t n_packets;
+    uint64_t packet_base;        // flattened index of this cloud's first packet
+    uint64_t n_states;
+    uint64_t off_edges;          // f64 [nb+1]
+    uint64_t off_faces[3];       // f64 [n[d]+1]
+    uint64_t off_k0, off_T, off_vel;   // f64 [nc], [nc], [nc * (1 or 3)]
+    uint64_t off_src_state;      // i32 [n_src]
+    uint64_t off_src_cdf;        // f64 [n_src]
+    uint64_t off_k;              // f64 [n_states]   eq. 14
+    uint64_t off_hot;            // HotRecord [n_states]
+    uint64_t off_lo_words;       // u32x2 [n_states]: low words of D and S
+    uint64_t off_face_split;     // u32 [n_states * (nf-1)]  P(face f | spatial) CDF * 2^31
+    uint64_t off_rates;          // f64 [n_states * (nf+2)]  (only with keep_rates)
+    uint64_t off_map;            // f64 [nc * nf * 3]: rho, shift, u_n per (cell, face)
+    uint64_t tally_off;          // int64 word offset of this cloud's tally block
+    uint64_t tally_words;
+    double tau_th, f_mu, lambda;
+};
+
+struct alignas(16) DevHeader {
+    int32_t n_clouds;
+    int32_t geometry;            // common geometry of the batch
+    uint64_t total_packets;
+    uint64_t off_clouds;         // DevCloud [n_clouds]
+    uint64_t off_prefix;         // u64 [n_clouds+1] flattened packet prefix
+    uint32_t error_flags;        // set by the build kernels (see BuildError)
+    uint32_t pad;
+};
+
+enum BuildError : uint32_t {
+    BE_NONFINITE = 1u,
+    BE_THIN = 2u,
+};
+
+// ---- launchers (defined in the .hip translation units) ------------------------------
+hipError_t launch_build(const DevCloud &c, int cloud_index, uint8_t *d_tables, hipStream_t s);
+hipError_t launch_walk(const uint8_t *d_tables, const DevHeader &h, const DevCloud *host_clouds,
+                       const rddmc_run &run, uint64_t first, uint64_t count,
+                       unsigned long long *d_tally, unsigned long long *d_work, hipStream_t s);
+hipError_t launch_zero(void *d, size_t words64, hipStream_t s);
+hipError_t launch_philox_fill(uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1, uint32_t c2,
+                              uint32_t c3, uint64_t n, uint32_t *d_out, hipStream_t s);
+int device_cu_count();
+
+}  // namespace rddmc

@@ -1,0 +1,338 @@
+// Persistent rDDMC walk (Sec. 2.3, eqs. 15-16; Sec. 2.5 for moving media).
+//
+// Every lane carries one packet in registers: cloud, packet id, cell, bin, FP64 clock
+// and step count.  A step reads the state's 16-byte hot record and two 32-bit words of
+// a Philox4x32-10 block keyed by (seed) and counted by (step pair, packet, cloud); one
+// block serves two consecutive steps:
+//   time word  -> exponential path length dl = -ln(xi) / K (xi in (0,1), f32 log2),
+//   event word -> high word of a u64 uniform U compared with the state's categorical
+//                 thresholds D = P(lower bin) 2^64 and S = (1 - P(spatial)) 2^64.
+// When the high word decides (all but ~2^-31 of steps) the step is a frequency move;
+// otherwise an auxiliary block supplies U's low word, the face choice and any
+// re-binning draws.  This samples the same law as taking the smallest of independent
+// exponential distances for every possible leak: the minimum is Exp(K) and the winner
+// is X with probability k_X / K, independently -- exact to 2^-64 per event, which
+// matters because spatial leaks from line-core bins have probabilities ~1e-10.
+//
+// Every `chunk` steps the wave refills lanes whose packet has finished from a global
+// counter (one atomic per wave).  Escapes and step-capped packets add to exact int64
+// tallies with device atomics; results depend only on (seed, cloud, packet id).
+#include <hip/hip_runtime.h>
+
+#include "philox.h"
+#include "rddmc_internal.h"
+
+namespace rddmc {
+
+namespace {
+
+struct WalkArgs {
+    uint64_t first;        // first flattened packet index of this run
+    uint64_t count;        // number of packets in this run
+    uint64_t max_steps;
+    uint32_t key0, key1;
+    int32_t chunk;
+    int32_t n_clouds;
+};
+
+// Domain tags in the second counter word (high bits of the step index never reach them).
+constexpr uint32_t kDomAux = 0x80000000u;   // extra draws inside step k (re-binning, escape)
+constexpr uint32_t kDomEmit = 0xC0000000u;  // emission draw
+
+__device__ __forceinline__ double u01_open_low(uint32_t r)
+{   // (r + 0.5) / 2^32 in (0, 1)
+    return ((double)r + 0.5) * 2.3283064365386962890625e-10;
+}
+
+__device__ __forceinline__ int locate_bin(const double *e, int nb, double x)
+{   // j with e[j] <= x < e[j+1]; -1 below the grid, nb at or above the top edge
+    if (x < e[0]) return -1;
+    if (x >= e[nb]) return nb;
+    int lo = 0, hi = nb;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (x >= e[mid]) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int time_bin(double t)
+{
+    if (!(t >= 1e-3)) return 0;
+    const double u = (log10(t) + 3.0) * (RDDMC_TIME_BINS / 9.0);
+    if (u >= (double)RDDMC_TIME_BINS) return RDDMC_TIME_BINS + 1;
+    return 1 + (int)u;
+}
+
+__device__ __forceinline__ int step_bin(uint64_t n)
+{
+    return n <= 1 ? 0 : 63 - __clzll((long long)n);
+}
+
+__device__ void tally_finish(unsigned long long *tally, const DevCloud &c, bool escaped, int row,
+                             int slot, double t, uint64_t steps)
+{
+    unsigned long long *w = tally + c.tally_off;
+    if (escaped) {
+        atomicAdd(&w[TW_ESCAPED], 1ull);
+        atomicAdd(&w[kTallyHeader + (uint64_t)row * (c.nb + 2) + slot], 1ull);
+        const unsigned long long tf = (unsigned long long)rint(t * kTimeFix);
+        atomicAdd(&w[TW_TSUM], tf);
+        const unsigned long long t2 = (unsigned long long)rint(t * t * kTimeFix);
+        const unsigned long long old = atomicAdd(&w[TW_T2_LO], t2);
+        if (old + t2 < old) atomicAdd(&w[TW_T2_HI], 1ull);
+        const uint64_t spec_words = (uint64_t)c.n_rows * (c.nb + 2);
+        atomicAdd(&w[kTallyHeader + spec_words + time_bin(t)], 1ull);
+    } else {
+        atomicAdd(&w[TW_CAPPED], 1ull);
+    }
+    const uint64_t spec_words = (uint64_t)c.n_rows * (c.nb + 2);
+    atomicAdd(&w[kTallyHeader + spec_words + RDDMC_TIME_BINS + 2 + step_bin(steps)], 1ull);
+    atomicAdd(&w[TW_STEPS], (unsigned long long)steps);
+    atomicMax(&w[TW_STEPS_MAX], (unsigned long long)steps);
+}
+
+__device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src)
+{
+    const uint32_t lo = __shfl((int)(uint32_t)v, src);
+    const uint32_t hi = __shfl((int)(uint32_t)(v >> 32), src);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Per-lane packet state of the 1D walk.
+struct Packet1D {
+    int cl, nb, nc, geom;
+    uint32_t pid;
+    int i, j;
+    double t;
+    uint64_t steps;
+    const uint4 *hot;          // HotRecord viewed as 4 words
+    bool active;
+};
+
+// Rare path of a step: the high word tied with a threshold (resolved with an auxiliary
+// low word) or the step is a spatial leak.  Returns false when the packet escaped.
+template <bool MOVING>
+__device__ __forceinline__ bool slow_step(Packet1D &p, uint32_t ew, uint32_t d_hi, uint32_t s_hi,
+                                       const uint8_t *__restrict__ tb, const DevCloud *__restrict__ clouds,
+                                       const WalkArgs &a, unsigned long long *__restrict__ tally)
+{
+    const DevCloud &c = clouds[p.cl];
+    const int s = p.i * p.nb + p.j;
+    const u32x4 aux = philox4x32_10((uint32_t)p.steps, kDomAux | (uint32_t)(p.steps >> 32), p.pid,
+                                    (uint32_t)p.cl, a.key0, a.key1);
+    const uint2 lw = reinterpret_cast<const uint2 *>(tb + c.off_lo_words)[s];
+    const uint64_t U = ((uint64_t)ew << 32) | aux.x;
+    const uint64_t D = ((uint64_t)d_hi << 32) | lw.x;
+    const uint64_t S = ((uint64_t)s_hi << 32) | lw.y;
+    if (U < D) { --p.j; ++p.steps; return true; }
+    if (U < S) { ++p.j; ++p.steps; return true; }
+    // spatial leak: face 0 (lower / inner) or face 1 (upper / outer)
+    const uint32_t fs = reinterpret_cast<const uint32_t *>(tb + c.off_face_split)[s];
+    const int face = ((aux.y & 0x7fffffffu) < fs) ? 0 : 1;
+    const int ni = face ? p.i + 1 : p.i - 1;
+    const double *e = reinterpret_cast<const double *>(tb + c.off_edges);
+    const double *map = reinterpret_cast<const double *>(tb + c.off_map) + 3 * (p.i * 2 + face);
+    ++p.steps;
+    if (ni < 0 || ni >= p.nc) {
+        int slot = p.j + 1;
+        if (MOVING && map[2] != 0.0) {   // lab frame: x uniform in the bin, outward mu uniform
+            const double x = e[p.j] + (e[p.j + 1] - e[p.j]) * u01_open_low(aux.z);
+            slot = locate_bin(e, p.nb, x + u01_open_low(aux.w) * map[2]) + 1;
+        }
+        tally_finish(tally, c, true, (p.geom == RDDMC_SLAB) ? face : 0, slot, p.t, p.steps);
+        p.active = false;
+        return false;
+    }
+    if (MOVING && (map[0] != 1.0 || map[1] != 0.0)) {   // comoving re-binning (eq. 20)
+        const double x = e[p.j] + (e[p.j + 1] - e[p.j]) * u01_open_low(aux.z);
+        const int jn = locate_bin(e, p.nb, map[0] * x + map[1]);
+        p.j = jn < 0 ? 0 : (jn > p.nb - 1 ? p.nb - 1 : jn);
+    }
+    p.i = ni;
+    return true;
+}
+
+// One step with the words (tw: path length, ew: event high word) and the state's record.
+// Returns -1 / +1 for a frequency move decided on the fast path, 0 otherwise.
+template <bool MOVING>
+__device__ __forceinline__ int one_step(Packet1D &p, uint32_t tw, uint32_t ew, uint4 rec,
+                                        const uint8_t *__restrict__ tb, const DevCloud *__restrict__ clouds,
+                                        const WalkArgs &a, unsigned long long *__restrict__ tally)
+{
+    const float xi = ((float)tw + 0.5f) * 2.3283064365386963e-10f;
+    p.t += (double)(-__log2f(xi) * __uint_as_float(rec.x));
+    if (__builtin_expect(ew < rec.z && ew != rec.y, 1)) {
+        const int d = (ew < rec.y) ? -1 : 1;
+        p.j += d;
+        ++p.steps;
+        return d;
+    }
+    slow_step<MOVING>(p, ew, rec.y, rec.z, tb, clouds, a, tally);
+    return 0;
+}
+
+// 1D walk (slab or sphere), pure DDMC; MOVING enables Doppler re-binning and lab-frame
+// escape frequencies.  One Philox block per pair of steps: (x, y) for the even step and
+// (z, w) for the odd one; all active lanes of a wave are at even step counts between pairs.
+template <bool MOVING>
+__global__ __launch_bounds__(256) void walk1d(const uint8_t *__restrict__ tb, WalkArgs a,
+                                              unsigned long long *__restrict__ tally,
+                                              unsigned long long *__restrict__ work)
+{
+    const DevHeader *H = reinterpret_cast<const DevHeader *>(tb);
+    const DevCloud *clouds = reinterpret_cast<const DevCloud *>(tb + H->off_clouds);
+    const uint64_t *prefix = reinterpret_cast<const uint64_t *>(tb + H->off_prefix);
+    const int lane = threadIdx.x & 63;
+
+    Packet1D p;
+    p.active = false;
+    p.cl = 0; p.nb = 1; p.nc = 1; p.geom = 0; p.pid = 0; p.i = 0; p.j = 0; p.t = 0.0; p.steps = 0;
+    p.hot = nullptr;
+    int last_state = 0;
+    bool exhausted = false;       // wave-uniform: the queue is empty
+
+    for (;;) {
+        // ---- refill finished lanes (one atomic per wave) -----------------------------
+        if (!exhausted) {
+            const uint64_t need = __ballot(!p.active);
+            if (need) {
+                const int leader = __ffsll((unsigned long long)need) - 1;
+                const int cnt = __popcll(need);
+                uint64_t base = 0;
+                if (lane == leader) base = atomicAdd(work, (unsigned long long)cnt);
+                base = shfl_u64(base, leader);
+                if (base + cnt >= a.count) exhausted = true;
+                if (!p.active) {
+                    const int rank = __popcll(need & ((1ull << lane) - 1ull));
+                    const uint64_t q = base + rank;
+                    if (q < a.count) {
+                        const uint64_t g = a.first + q;
+                        int lo = 0, hi = a.n_clouds;      // prefix[lo] <= g < prefix[hi]
+                        while (hi - lo > 1) {
+                            const int mid = (lo + hi) >> 1;
+                            if (g >= prefix[mid]) lo = mid; else hi = mid;
+                        }
+                        p.cl = lo;
+                        const DevCloud &c = clouds[lo];
+                        p.pid = (uint32_t)(g - prefix[lo]);
+                        p.nb = c.nb;
+                        p.nc = c.nc;
+                        p.geom = c.geometry;
+                        p.hot = reinterpret_cast<const uint4 *>(tb + c.off_hot);
+                        last_state = (int)c.n_states - 1;
+                        // emission (Sec. 2.3): a source state drawn by its probability
+                        const u32x4 r = philox4x32_10(0u, kDomEmit, p.pid, (uint32_t)lo, a.key0, a.key1);
+                        const double u = u01_open_low(r.x);
+                        const int32_t *ss = reinterpret_cast<const int32_t *>(tb + c.off_src_state);
+                        const double *cdf = reinterpret_cast<const double *>(tb + c.off_src_cdf);
+                        int k = 0;
+                        while (k < c.n_src - 1 && u >= cdf[k]) ++k;
+                        const int32_t st = ss[k];
+                        p.i = st / p.nb;
+                        p.j = st - p.i * p.nb;
+                        p.t = 0.0;
+                        p.steps = 0;
+                        p.active = true;
+                        atomicAdd(&tally[c.tally_off + TW_LAUNCHED], 1ull);
+                    }
+                }
+            }
+        }
+        if (!__any(p.active)) break;
+
+        // ---- walk up to `chunk` pairs of steps ---------------------------------------
+        const uint64_t left = p.active ? (a.max_steps - p.steps) : 0ull;
+        const uint64_t pairs = (left + 1) >> 1;
+        const int budget = pairs < (uint64_t)a.chunk ? (int)pairs : a.chunk;
+        for (int k = 0; k < budget; ++k) {
+            const int s = p.i * p.nb + p.j;
+            const uint4 rm = p.hot[s > 0 ? s - 1 : 0];
+            const uint4 r0 = p.hot[s];
+            const uint4 rp = p.hot[s < last_state ? s + 1 : last_state];
+            const uint64_t pair = p.steps >> 1;
+            const u32x4 r = philox4x32_10((uint32_t)pair, (uint32_t)(pair >> 32), p.pid, (uint32_t)p.cl,
+                                          a.key0, a.key1);
+            const int d = one_step<MOVING>(p, r.x, r.y, r0, tb, clouds, a, tally);
+            if (!p.active || p.steps >= a.max_steps) break;
+            uint4 rb;
+            if (d < 0) rb = rm;
+            else if (d > 0) rb = rp;
+            else rb = p.hot[p.i * p.nb + p.j];
+            one_step<MOVING>(p, r.z, r.w, rb, tb, clouds, a, tally);
+            if (!p.active) break;
+        }
+        if (p.active && p.steps >= a.max_steps) {
+            tally_finish(tally, clouds[p.cl], false, 0, 0, p.t, p.steps);
+            p.active = false;
+        }
+    }
+}
+
+__global__ void philox_fill_kernel(uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1, uint32_t c2,
+                                   uint32_t c3, uint64_t n, uint32_t *out)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const u32x4 r = philox4x32_10(c0 + (uint32_t)i, c1, c2, c3, k0, k1);
+    out[4 * i + 0] = r.x;
+    out[4 * i + 1] = r.y;
+    out[4 * i + 2] = r.z;
+    out[4 * i + 3] = r.w;
+}
+
+__global__ void reset_work(unsigned long long *work)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) work[0] = 0ull;
+}
+
+}  // namespace
+
+int device_cu_count()
+{
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 256;
+    return n > 0 ? n : 256;
+}
+
+hipError_t launch_walk(const uint8_t *d_tables, const DevHeader &h, const DevCloud *host_clouds,
+                       const rddmc_run &run, uint64_t first, uint64_t count,
+                       unsigned long long *d_tally, unsigned long long *d_work, hipStream_t s)
+{
+    WalkArgs a;
+    a.first = first;
+    a.count = count;
+    a.max_steps = run.max_steps;
+    a.key0 = (uint32_t)run.seed;
+    a.key1 = (uint32_t)(run.seed >> 32);
+    a.chunk = run.chunk > 0 ? (run.chunk + 1) / 2 : 32;   // in pairs of steps
+    a.n_clouds = h.n_clouds;
+    const int block = run.block > 0 ? run.block : 256;
+    int grid = run.grid;
+    if (grid <= 0) {
+        const uint64_t lanes = count;
+        const uint64_t want = (lanes + block - 1) / block;
+        const uint64_t cap = (uint64_t)device_cu_count() * 8;   // 8 blocks of 256 per CU
+        grid = (int)(want < cap ? want : cap);
+        if (grid < 1) grid = 1;
+    }
+    bool moving = false;
+    for (int c = 0; c < h.n_clouds; ++c) moving |= host_clouds[c].moving != 0;
+    reset_work<<<1, 64, 0, s>>>(d_work);
+    if (moving)
+        walk1d<true><<<grid, block, 0, s>>>(d_tables, a, d_tally, d_work);
+    else
+        walk1d<false><<<grid, block, 0, s>>>(d_tables, a, d_tally, d_work);
+    return hipGetLastError();
+}
+
+hipError_t launch_philox_fill(uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1, uint32_t c2,
+                              uint32_t c3, uint64_t n, uint32_t *d_out, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    philox_fill_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(k0, k1, c0, c1, c2, c3, n, d_out);
+    return hipGetLastError();
+}
+
+}  // namespace rddmc

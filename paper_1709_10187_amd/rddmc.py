@@ -1,0 +1,290 @@
+"""Python binding of the rDDMC C ABI (include/rddmc.h): argument marshalling only.
+
+Every step of the transport runs in the HIP library ``librddmc.so``; PyTorch supplies
+device memory and the stream.  The library must have been built (``build()`` in
+``paper_1709_10187_amd.build``); if it is missing, loading raises -- there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+from . import media as _media
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librddmc.so")
+
+TIME_BINS = 128
+STEP_BINS = 64
+STATUS = {0: "OK", -1: "EINVAL", -2: "ESIZE", -3: "EUNSUPPORTED", -4: "ENUMERIC", -5: "EHIP"}
+FLAG_DIRICHLET = 1 << 0
+FLAG_KEEP_RATES = 1 << 1
+
+
+class RddmcError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Medium_t(C.Structure):
+    _fields_ = [("geometry", C.c_int32), ("n_cells", C.c_int32 * 3), ("n_bins", C.c_int32),
+                ("flags", C.c_uint32), ("faces", C.c_void_p * 3), ("bin_edges", C.c_void_p),
+                ("k0", C.c_void_p), ("temp", C.c_void_p), ("vel", C.c_void_p),
+                ("tau_threshold", C.c_double), ("f_mu", C.c_double), ("lambda_", C.c_double),
+                ("n_src", C.c_int32), ("reserved0", C.c_int32), ("src_pos", C.c_void_p),
+                ("src_x", C.c_void_p), ("n_packets", C.c_uint64)]
+
+
+class Batch_t(C.Structure):
+    _fields_ = [("n_clouds", C.c_int32), ("reserved0", C.c_int32), ("clouds", C.POINTER(Medium_t))]
+
+
+class Run_t(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("first", C.c_uint64), ("count", C.c_uint64),
+                ("max_steps", C.c_uint64), ("block", C.c_int32), ("grid", C.c_int32),
+                ("chunk", C.c_int32), ("reserved0", C.c_int32)]
+
+
+class CloudStats_t(C.Structure):
+    _fields_ = [("launched", C.c_uint64), ("escaped", C.c_uint64), ("capped", C.c_uint64),
+                ("steps_total", C.c_uint64), ("steps_max", C.c_uint64), ("steps_mean", C.c_double),
+                ("t_mean", C.c_double), ("t_var", C.c_double), ("n_rows", C.c_int32),
+                ("n_slots", C.c_int32)]
+
+
+class TallyOut_t(C.Structure):
+    _fields_ = [("spectrum", C.POINTER(C.c_void_p)), ("time_hist", C.POINTER(C.c_void_p)),
+                ("step_hist", C.POINTER(C.c_void_p)), ("stats", C.POINTER(CloudStats_t))]
+
+
+EXPORTS = ["rddmc_abi_version", "rddmc_last_error", "rddmc_table_bytes", "rddmc_tally_bytes",
+           "rddmc_work_bytes", "rddmc_build_leakage", "rddmc_transport", "rddmc_tally_reset",
+           "rddmc_tally", "rddmc_read_tables", "rddmc_philox_fill"]
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load librddmc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_1709_10187_amd.build`")
+    lib = C.CDLL(path)
+    vp, sz = C.c_void_p, C.c_size_t
+    lib.rddmc_abi_version.restype = C.c_int32
+    lib.rddmc_last_error.restype = C.c_char_p
+    for name in ("rddmc_table_bytes", "rddmc_tally_bytes", "rddmc_work_bytes"):
+        getattr(lib, name).argtypes = [C.POINTER(Batch_t), C.POINTER(sz)]
+        getattr(lib, name).restype = C.c_int
+    lib.rddmc_build_leakage.argtypes = [C.POINTER(Batch_t), vp, sz, vp]
+    lib.rddmc_transport.argtypes = [C.POINTER(Batch_t), vp, C.POINTER(Run_t), vp, sz, vp, sz, vp]
+    lib.rddmc_tally_reset.argtypes = [C.POINTER(Batch_t), vp, sz, vp]
+    lib.rddmc_tally.argtypes = [C.POINTER(Batch_t), vp, sz, C.POINTER(TallyOut_t), vp]
+    lib.rddmc_read_tables.argtypes = [C.POINTER(Batch_t), vp, C.c_int32, vp, vp, vp, vp, vp]
+    lib.rddmc_philox_fill.argtypes = [C.c_uint32] * 6 + [C.c_uint64, vp, vp]
+    for name in ("rddmc_build_leakage", "rddmc_transport", "rddmc_tally_reset", "rddmc_tally",
+                 "rddmc_read_tables", "rddmc_philox_fill"):
+        getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise RddmcError(rc, _lib.rddmc_last_error().decode())
+
+
+class Batch:
+    """ctypes view of a list of ``media.Medium`` (keeps the numpy inputs alive)."""
+
+    def __init__(self, meds: Sequence[_media.Medium], keep_rates: bool = False):
+        self.meds = list(meds)
+        self._keep = []
+        arr = (Medium_t * len(self.meds))()
+        for i, m in enumerate(self.meds):
+            s = arr[i]
+            s.geometry = m.geometry
+            for d in range(3):
+                s.n_cells[d] = int(m.n_cells[d])
+            s.n_bins = m.n_bins
+            s.flags = int(m.flags) | (FLAG_KEEP_RATES if keep_rates else 0)
+            for d in range(3):
+                s.faces[d] = self._ptr(m.faces[d])
+            s.bin_edges = self._ptr(m.bin_edges)
+            s.k0 = self._ptr(m.k0)
+            s.temp = self._ptr(m.temp)
+            s.vel = self._ptr(m.vel) if m.vel is not None else None
+            s.tau_threshold = m.tau_threshold
+            s.f_mu = m.f_mu
+            s.lambda_ = m.lam
+            s.n_src = len(m.src_x)
+            s.src_pos = self._ptr(np.asarray(m.src_pos, dtype=np.float64).reshape(-1, 3))
+            s.src_x = self._ptr(m.src_x)
+            s.n_packets = int(m.n_packets)
+        self._arr = arr
+        self.c = Batch_t(len(self.meds), 0, arr)
+
+    def _ptr(self, a):
+        a = np.ascontiguousarray(a, dtype=np.float64)
+        self._keep.append(a)
+        return a.ctypes.data
+
+    def ref(self):
+        return C.byref(self.c)
+
+    def n_rows(self, i):
+        return {0: 2, 1: 1, 2: 6}[self.meds[i].geometry]
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+def table_bytes(b: Batch) -> int:
+    lib = load()
+    n = C.c_size_t()
+    _check(lib.rddmc_table_bytes(b.ref(), C.byref(n)))
+    return n.value
+
+
+def tally_bytes(b: Batch) -> int:
+    lib = load()
+    n = C.c_size_t()
+    _check(lib.rddmc_tally_bytes(b.ref(), C.byref(n)))
+    return n.value
+
+
+def work_bytes(b: Batch) -> int:
+    lib = load()
+    n = C.c_size_t()
+    _check(lib.rddmc_work_bytes(b.ref(), C.byref(n)))
+    return n.value
+
+
+def build_leakage(b: Batch, d_tables, stream=None):
+    lib = load()
+    _check(lib.rddmc_build_leakage(b.ref(), C.c_void_p(d_tables.data_ptr()), d_tables.numel(),
+                                   _stream(stream)))
+
+
+def tally_reset(b: Batch, d_tally, stream=None):
+    lib = load()
+    _check(lib.rddmc_tally_reset(b.ref(), C.c_void_p(d_tally.data_ptr()), d_tally.numel() * d_tally.element_size(),
+                                 _stream(stream)))
+
+
+def transport(b: Batch, d_tables, d_tally, d_work, seed=0, first=0, count=0, max_steps=(1 << 62),
+              block=0, grid=0, chunk=0, stream=None):
+    lib = load()
+    run = Run_t(int(seed), int(first), int(count), int(max_steps), int(block), int(grid), int(chunk), 0)
+    _check(lib.rddmc_transport(b.ref(), C.c_void_p(d_tables.data_ptr()), C.byref(run),
+                               C.c_void_p(d_tally.data_ptr()), d_tally.numel() * d_tally.element_size(),
+                               C.c_void_p(d_work.data_ptr()), d_work.numel() * d_work.element_size(),
+                               _stream(stream)))
+
+
+@dataclasses.dataclass
+class CloudTally:
+    spectrum: np.ndarray       # (n_rows, nb+2) int64
+    time_hist: np.ndarray      # (TIME_BINS+2,) int64
+    step_hist: np.ndarray      # (STEP_BINS,) int64
+    launched: int
+    escaped: int
+    capped: int
+    steps_total: int
+    steps_max: int
+    steps_mean: float
+    t_mean: float
+    t_var: float
+
+
+def tally(b: Batch, d_tally, stream=None) -> List[CloudTally]:
+    lib = load()
+    n = len(b.meds)
+    specs = [np.zeros((b.n_rows(i), b.meds[i].n_bins + 2), dtype=np.int64) for i in range(n)]
+    th = [np.zeros(TIME_BINS + 2, dtype=np.int64) for _ in range(n)]
+    sh = [np.zeros(STEP_BINS, dtype=np.int64) for _ in range(n)]
+    sp_ptrs = (C.c_void_p * n)(*[a.ctypes.data for a in specs])
+    th_ptrs = (C.c_void_p * n)(*[a.ctypes.data for a in th])
+    sh_ptrs = (C.c_void_p * n)(*[a.ctypes.data for a in sh])
+    stats = (CloudStats_t * n)()
+    out = TallyOut_t(sp_ptrs, th_ptrs, sh_ptrs, stats)
+    _check(lib.rddmc_tally(b.ref(), C.c_void_p(d_tally.data_ptr()), d_tally.numel() * d_tally.element_size(),
+                           C.byref(out), _stream(stream)))
+    res = []
+    for i in range(n):
+        z = stats[i]
+        res.append(CloudTally(specs[i], th[i], sh[i], z.launched, z.escaped, z.capped, z.steps_total,
+                              z.steps_max, z.steps_mean, z.t_mean, z.t_var))
+    return res
+
+
+HOT_DTYPE = np.dtype([("ln2_over_K", "<f4"), ("d_hi", "<u4"), ("s_hi", "<u4"), ("spare", "<u4")])
+
+
+def read_tables(b: Batch, d_tables, cloud=0, want_rates=True, stream=None):
+    """FP64 k_ij, FP64 rates (if kept), hot records and the u64 thresholds D, S per state."""
+    lib = load()
+    m = b.meds[cloud]
+    ns = m.n_cells_total * m.n_bins
+    nf = 6 if m.geometry == 2 else 2
+    k = np.zeros(ns)
+    rates = np.zeros((ns, nf + 2)) if want_rates else None
+    hot = np.zeros(ns, dtype=HOT_DTYPE)
+    lo = np.zeros((ns, 2), dtype=np.uint32)
+    _check(lib.rddmc_read_tables(b.ref(), C.c_void_p(d_tables.data_ptr()), cloud, k.ctypes.data,
+                                 rates.ctypes.data if want_rates else None, hot.ctypes.data,
+                                 lo.ctypes.data, _stream(stream)))
+    D = (hot["d_hi"].astype(np.uint64) << np.uint64(32)) | lo[:, 0].astype(np.uint64)
+    S = (hot["s_hi"].astype(np.uint64) << np.uint64(32)) | lo[:, 1].astype(np.uint64)
+    return k, rates, hot, D, S
+
+
+def philox_fill(k0, k1, c0, c1, c2, c3, n, d_out, stream=None):
+    lib = load()
+    _check(lib.rddmc_philox_fill(k0, k1, c0, c1, c2, c3, n, C.c_void_p(d_out.data_ptr()), _stream(stream)))
+
+
+class Problem:
+    """Device buffers for one batch: tables, tallies and the work counter (torch tensors)."""
+
+    def __init__(self, meds, keep_rates=False, device="cuda", stream=None):
+        import torch
+        if isinstance(meds, _media.Medium):
+            meds = [meds]
+        self.batch = Batch(meds, keep_rates=keep_rates)
+        self.stream = stream
+        self.tables = torch.empty(table_bytes(self.batch), dtype=torch.uint8, device=device)
+        self.tallies = torch.empty(tally_bytes(self.batch) // 8, dtype=torch.int64, device=device)
+        self.work = torch.zeros(work_bytes(self.batch) // 8, dtype=torch.int64, device=device)
+        build_leakage(self.batch, self.tables, stream)
+        tally_reset(self.batch, self.tallies, stream)
+
+    @property
+    def total_packets(self):
+        return sum(int(m.n_packets) for m in self.batch.meds)
+
+    def reset(self):
+        tally_reset(self.batch, self.tallies, self.stream)
+
+    def run(self, **kw):
+        transport(self.batch, self.tables, self.tallies, self.work, stream=self.stream, **kw)
+
+    def results(self):
+        return tally(self.batch, self.tallies, self.stream)
+
+    def read_tables(self, cloud=0, want_rates=True):
+        return read_tables(self.batch, self.tables, cloud, want_rates, self.stream)

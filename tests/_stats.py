@@ -3,8 +3,13 @@
 Rules: spectra are compared as escape fractions over the lab slots; bins whose
 expected count is below 10 are merged into their neighbours; the per-bin sigma
 against an exact expectation is sqrt(p (1 - p) / N), against another Monte
-Carlo sample sqrt(s1^2 + s2^2).  Pass: at least 99 % of bins with |z| <= 3,
-chi^2 p-value >= 1e-3 and L1 <= the stated bound.
+Carlo sample sqrt(s1^2 + s2^2).  Pass:
+  * "within 3 sigma per bin": the number of bins with |z| > 3 is no larger than a
+    Binomial(n_bins, 0.0027) count exceeds with probability 1e-3 (for many bins this is
+    the ">= 99 % of bins" rule; for ~100 bins it allows the 0-3 chance excursions a
+    correct sampler produces), and no bin has |z| > 5;
+  * chi^2 p-value >= 1e-3;
+  * L1 <= the stated bound.
 """
 import numpy as np
 from scipy import stats
@@ -60,8 +65,17 @@ def compare_two_samples(c1, c2):
             "L1": float(np.abs(c1 / n1 - c2 / n2).sum())}
 
 
+def allowed_3sigma_exceedances(n_bins, p_fail=1e-3):
+    k = 0
+    while stats.binom.sf(k, n_bins, 0.0027) >= p_fail:
+        k += 1
+    return k
+
+
 def assert_spectrum_matches(res, l1_max=None):
-    assert res["frac_within_3sigma"] >= 0.99 or res["max_abs_z"] <= 3.0, res
+    z = np.abs(res["z"])
+    assert int(np.sum(z > 3)) <= allowed_3sigma_exceedances(len(z)), res
+    assert z.max() <= 5.0, res
     assert res["p_value"] >= 1e-3, res
     if l1_max is not None:
         assert res["L1"] <= l1_max, res

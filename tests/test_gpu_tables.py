@@ -1,0 +1,67 @@
+"""GPU FP64 leakage tables against the oracle's FP64 tables (1e-6 relative bar)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import tables as tb
+from paper_1709_10187_amd import media, rddmc
+
+pytestmark = pytest.mark.gpu
+
+LN2 = math.log(2.0)
+
+
+def _cases():
+    nonuni = media.slab(3e4, 1e4, 12, 40, vel=np.linspace(-15, 15, 12))
+    nonuni = nonuni.replace(temp=np.geomspace(2e3, 3e4, 12), k0=np.geomspace(1e4, 1e5, 12))
+    return {
+        "config_slab": media.config_slab(),
+        "config_sphere": media.config_sphere(),
+        "validation_slab": media.validation_slab(),
+        "sweep_cloud_0": media.config_sweep(4)[0],
+        "sweep_cloud_3": media.config_sweep(4)[3],
+        "nonuniform_moving_slab": nonuni,
+        "dirichlet_slab": media.slab(1e3, 1e4, 8, 16, flags=media.FLAG_DIRICHLET),
+        "grey_one_bin": media.slab(50.0, 1e4, 9, 1, x_max=1.0),
+    }
+
+
+CASES = _cases()
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_tables_match_oracle(name):
+    m = CASES[name]
+    print(f"[tables] {name} cells={m.n_cells} bins={m.n_bins}", flush=True)
+    prob = rddmc.Problem(m, keep_rates=True)
+    k, rates, hot, D, S = prob.read_tables(0)
+    t = tb.build(m)
+    nf = t.nf
+    ns = t.nc * t.nb
+    np.testing.assert_allclose(k, t.k.reshape(ns), rtol=1e-6)
+    ref_rates = np.concatenate([t.rate_face.reshape(ns, nf), t.rate_dn.reshape(ns, 1),
+                                t.rate_up.reshape(ns, 1)], axis=1)
+    np.testing.assert_allclose(rates, ref_rates, rtol=1e-6, atol=0)
+    K = t.K.reshape(ns)
+    np.testing.assert_allclose(hot["ln2_over_K"], LN2 / K, rtol=1e-6)
+    two64 = 2.0 ** 64
+    p_dn = D.astype(np.float64) / two64
+    p_sp_exact = (np.uint64(0) - S).astype(np.float64) / two64
+    p_sp = np.where(S == 0, 1.0, p_sp_exact)
+    p_up = (S.astype(np.float64) - D.astype(np.float64)) / two64
+    ps_ref = t.rate_face.reshape(ns, nf).sum(axis=1) / K
+    np.testing.assert_allclose(p_sp, ps_ref, rtol=1e-6, atol=2.0 ** -63)
+    np.testing.assert_allclose(p_dn, t.rate_dn.reshape(ns) / K, rtol=1e-6, atol=2.0 ** -52)
+    np.testing.assert_allclose(p_up, t.rate_up.reshape(ns) / K, rtol=1e-6, atol=2.0 ** -52)
+    assert np.all(D <= S) or np.all((S == 0) == (D == 0))
+
+
+def test_static_table_symmetry_on_gpu():
+    m = media.config_slab()
+    prob = rddmc.Problem(m)
+    k, _, hot, D, S = prob.read_tables(0, want_rates=False)
+    k = k.reshape(64, 128)
+    np.testing.assert_allclose(k, k[:, ::-1], rtol=1e-13)
+    lk = hot["ln2_over_K"].reshape(64, 128)
+    np.testing.assert_array_equal(lk, lk[::-1, :])
