@@ -21,13 +21,15 @@ sys.path.insert(0, ROOT)
 
 METRIC = "packets/s & packet-steps/s at 1 GPU; surrogate vs plain speedup at ≤1% spectrum L1"
 
-# Algorithmic VALU work of one DDMC step, in full-rate lane-op slots (a quarter-rate op
-# -- 32x32->64 multiply, log2 -- costs 4): half a Philox4x32-10 block (10 rounds x (2
-# multiplies x 4 + 2 three-input xors) / 2 = 50), the path length (u32->f32, fma, log2,
-# mul, f32->f64, f64 add = 10) and the event (2 compares, select, add, address = 10).
-SLOTS_PER_STEP = 70.0
-# Full-rate 32-bit VALU lane-op slots of the chip: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
-PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
+# Algorithmic VALU work of one DDMC step (the minimal instruction stream of a step, every
+# VALU instruction issuing at one wave-instruction per 4 cycles per SIMD on gfx950, the
+# 32x32->64 multiply included, as SQ_INSTS_VALU / time confirms): half a Philox4x32-10
+# block (10 rounds x (2 multiplies + 2 three-input xors) / 2 = 20), the path length
+# (u32->f32, scale, log2, multiply, f32->f64, f64 add = 6), the event (3 compares, select,
+# add = 5) and the record address (1): 32 lane-ops.
+OPS_PER_STEP = 32.0
+# VALU lane-op issue rate of the chip: 256 CUs x 4 SIMDs x 64 lanes per 4 cycles x 2.4 GHz.
+PEAK_OPS = 256 * 4 * 16 * 2.4e9
 
 
 def parse():
@@ -96,7 +98,7 @@ def main():
     pk_s = res.launched / sec
     st_s = res.steps_total / sec
     per_launch_s = sec / args.steps
-    achieved = (res.steps_total / args.steps) * SLOTS_PER_STEP / per_launch_s
+    achieved = (res.steps_total / args.steps) * OPS_PER_STEP / per_launch_s
     out = {
         "metric": METRIC,
         "value": pk_s,
@@ -118,8 +120,8 @@ def main():
                    "steps_mean": res.steps_mean, "steps_max": int(res.steps_max),
                    "t_mean_light_crossings": res.t_mean, "wall_s": wall,
                    "precision": "f32 walk, f64 tables and clock, i64 tallies, Philox4x32-10"},
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12,
-                     "unit": "Tslot/s (full-rate VALU lane-ops)", "frac": achieved / PEAK_SLOTS,
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_OPS / 1e12,
+                     "unit": "T VALU lane-ops/s", "frac": achieved / PEAK_OPS,
                      "traffic": None},
     }
     if not args.no_cpu_baseline:

@@ -119,6 +119,10 @@ typedef struct {
  *   max_steps    per-packet step cap (>= 1); capped packets are counted, not dropped.
  *   block, grid  threads per block (multiple of 64, <= 1024) and blocks; 0 = automatic.
  *   chunk        steps between refills of finished lanes (0 = automatic).
+ *   tail_lanes   once every packet of the run has started, a wave with at most this many
+ *                packets left hands them to a cooperative walk in which a whole wave
+ *                advances one packet (0 = automatic (16), < 0 = never).  Results are
+ *                bit-identical either way.
  */
 typedef struct {
     uint64_t seed;
@@ -128,7 +132,7 @@ typedef struct {
     int32_t block;
     int32_t grid;
     int32_t chunk;
-    int32_t reserved0;
+    int32_t tail_lanes;
 } rddmc_run;
 
 /* Per-cloud summary filled by rddmc_tally (FP64 host-side normalisation of the exact
@@ -176,7 +180,8 @@ rddmc_status rddmc_table_bytes(const rddmc_batch *batch, size_t *bytes);
  * rddmc_tally_reset or any fill before the first run; runs accumulate). */
 rddmc_status rddmc_tally_bytes(const rddmc_batch *batch, size_t *bytes);
 
-/* Device bytes for the transport work area (queue counter). */
+/* Device bytes for the transport work area: queue counters and one 32-byte slot per
+ * resident lane for packets handed to the cooperative tail walk. */
 rddmc_status rddmc_work_bytes(const rddmc_batch *batch, size_t *bytes);
 
 /* ---- the path ------------------------------------------------------------------------ */
@@ -219,7 +224,8 @@ rddmc_status rddmc_build_leakage(const rddmc_batch *batch, void *d_tables, size_
  *   d_tables     tables written by rddmc_build_leakage for that batch.
  *   run          run parameters (see rddmc_run).
  *   d_tally      >= rddmc_tally_bytes bytes; accumulated into (not cleared).
- *   d_work       >= rddmc_work_bytes bytes; cleared by the call (with a kernel).
+ *   d_work       >= rddmc_work_bytes bytes (a smaller buffer of >= 256 bytes disables the
+ *                cooperative tail walk); its counters are cleared by the call (a kernel).
  *   stream       hipStream_t; asynchronous.
  * Errors: EINVAL (run parameters), ESIZE, EHIP.
  */

@@ -265,7 +265,10 @@ rddmc_status rddmc_work_bytes(const rddmc_batch *batch, size_t *bytes)
     Layout L;
     rddmc_status st = make_layout(batch, L);
     if (st != RDDMC_OK) return st;
-    *bytes = 256;
+    // queue counters, then one 32-byte slot per lane that may hand its packet to the
+    // cooperative tail walk (at most 2^20 lanes are ever resident)
+    const uint64_t lanes = L.h.total_packets < (1ull << 20) ? L.h.total_packets : (1ull << 20);
+    *bytes = 256 + 32 * lanes;
     return RDDMC_OK;
 }
 
@@ -363,7 +366,8 @@ rddmc_status rddmc_transport(const rddmc_batch *batch, const void *d_tables, con
     if (count == 0) return RDDMC_OK;
     hipError_t e = launch_walk(static_cast<const uint8_t *>(d_tables), L.h, L.clouds.data(), *run, run->first,
                                count, static_cast<unsigned long long *>(d_tally),
-                               static_cast<unsigned long long *>(d_work), reinterpret_cast<hipStream_t>(stream));
+                               static_cast<unsigned long long *>(d_work), work_bytes,
+                               reinterpret_cast<hipStream_t>(stream));
     return e == hipSuccess ? RDDMC_OK : hip_fail(e, "walk kernel");
 }
 

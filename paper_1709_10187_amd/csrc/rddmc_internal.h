@@ -81,7 +81,8 @@ enum BuildError : uint32_t {
 hipError_t launch_build(const DevCloud &c, int cloud_index, uint8_t *d_tables, hipStream_t s);
 hipError_t launch_walk(const uint8_t *d_tables, const DevHeader &h, const DevCloud *host_clouds,
                        const rddmc_run &run, uint64_t first, uint64_t count,
-                       unsigned long long *d_tally, unsigned long long *d_work, hipStream_t s);
+                       unsigned long long *d_tally, unsigned long long *d_work, uint64_t work_bytes,
+                       hipStream_t s);
 hipError_t launch_zero(void *d, size_t words64, hipStream_t s);
 hipError_t launch_philox_fill(uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1, uint32_t c2,
                               uint32_t c3, uint64_t n, uint32_t *d_out, hipStream_t s);

@@ -33,6 +33,20 @@ struct WalkArgs {
     uint32_t key0, key1;
     int32_t chunk;
     int32_t n_clouds;
+    int32_t tail_lanes;    // export a wave's packets once the queue is empty and <= this many remain
+    int32_t pad;
+    uint64_t tail_capacity;
+};
+
+// Work area: u64 words [0] packet queue counter, [1] exported packets, [2] next exported
+// packet to walk cooperatively; exported packet states start at byte kWorkHeaderBytes.
+constexpr uint64_t kWorkHeaderBytes = 256;
+
+struct TailPacket {        // 32 bytes
+    uint32_t cl, pid;
+    int32_t i, j;
+    uint64_t steps;
+    double t;
 };
 
 // Domain tags in the second counter word (high bits of the step index never reach them).
@@ -99,6 +113,15 @@ __device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src)
     return ((uint64_t)hi << 32) | lo;
 }
 
+// Path length of one step in length units: -ln(xi) / K with xi = (tw + 1/2) / 2^32, as
+// -log2(xi) * (ln2 / K).  Written with explicit round-to-nearest operations so that the
+// lane walk and the cooperative walk produce the same bits.
+__device__ __forceinline__ float path_length(uint32_t tw, float ln2_over_K)
+{
+    const float xi = __fmul_rn(__fadd_rn((float)tw, 0.5f), 2.3283064365386963e-10f);
+    return __fmul_rn(-__log2f(xi), ln2_over_K);
+}
+
 // Per-lane packet state of the 1D walk.
 struct Packet1D {
     int cl, nb, nc, geom;
@@ -160,8 +183,7 @@ __device__ __forceinline__ int one_step(Packet1D &p, uint32_t tw, uint32_t ew, u
                                         const uint8_t *__restrict__ tb, const DevCloud *__restrict__ clouds,
                                         const WalkArgs &a, unsigned long long *__restrict__ tally)
 {
-    const float xi = ((float)tw + 0.5f) * 2.3283064365386963e-10f;
-    p.t += (double)(-__log2f(xi) * __uint_as_float(rec.x));
+    p.t += (double)path_length(tw, __uint_as_float(rec.x));
     if (__builtin_expect(ew < rec.z && ew != rec.y, 1)) {
         const int d = (ew < rec.y) ? -1 : 1;
         p.j += d;
@@ -241,6 +263,30 @@ __global__ __launch_bounds__(256) void walk1d(const uint8_t *__restrict__ tb, Wa
         }
         if (!__any(p.active)) break;
 
+        // ---- tail: hand the last few packets of this wave to the cooperative walk ----
+        if (exhausted && a.tail_lanes > 0) {
+            const uint64_t live = __ballot(p.active);
+            if (__popcll(live) <= a.tail_lanes) {
+                const int leader = __ffsll((unsigned long long)live) - 1;
+                uint64_t base = 0;
+                if (lane == leader) base = atomicAdd(&work[1], (unsigned long long)__popcll(live));
+                base = shfl_u64(base, leader);
+                if (p.active) {
+                    const uint64_t slot = base + __popcll(live & ((1ull << lane) - 1ull));
+                    TailPacket *tp = reinterpret_cast<TailPacket *>(reinterpret_cast<uint8_t *>(work) +
+                                                                    kWorkHeaderBytes) + slot;
+                    tp->cl = (uint32_t)p.cl;
+                    tp->pid = p.pid;
+                    tp->i = p.i;
+                    tp->j = p.j;
+                    tp->steps = p.steps;
+                    tp->t = p.t;
+                    p.active = false;
+                }
+                break;
+            }
+        }
+
         // ---- walk up to `chunk` pairs of steps ---------------------------------------
         const uint64_t left = p.active ? (a.max_steps - p.steps) : 0ull;
         const uint64_t pairs = (left + 1) >> 1;
@@ -269,6 +315,142 @@ __global__ __launch_bounds__(256) void walk1d(const uint8_t *__restrict__ tb, Wa
     }
 }
 
+__device__ __forceinline__ uint32_t rl(uint32_t v, int lane)
+{
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, lane);
+}
+
+// Cooperative walk of ONE packet by a whole wave (the packet state is wave-uniform).
+// Per block of up to 64 steps:
+//   * lane l draws the Philox words of step steps+l (all 64 blocks in parallel);
+//   * the records of a 16-bin window of the current cell sit in lanes 0..15;
+//   * lane l packs, for every window bin b, "a move from b would go to the lower bin"
+//     (bit b) and "a step from b needs the slow path" (bit 16+b) into one word;
+//   * the sequential part then costs one readlane and a few scalar bit operations per
+//     step on a one-hot position, stopping at a window exit or a slow-path step, which one
+//     lane executes (tie resolution, spatial leak, escape tally).
+// The clock adds the same f32 path lengths in the same order as the lane walk, so every
+// tally is bit-identical to walking the packet in a single lane.
+template <bool MOVING>
+__device__ void coop_walk(Packet1D &q, const uint8_t *__restrict__ tb, const DevCloud *__restrict__ clouds,
+                          const WalkArgs &a, unsigned long long *__restrict__ tally, int lane)
+{
+    constexpr int WB = 16;
+    int wi = -1, jw = 0;
+    uint32_t v_lk = 0u, v_dhi = 0u, v_shi = 0u;
+    while (q.active) {
+        const uint64_t left = a.max_steps - q.steps;
+        if (left == 0) {
+            if (lane == 0) tally_finish(tally, clouds[q.cl], false, 0, 0, q.t, q.steps);
+            q.active = false;
+            break;
+        }
+        const int m = left < 64 ? (int)left : 64;
+        if (q.i != wi || (q.j - jw < 2 && jw > 0) || (q.j - jw > WB - 3 && jw < q.nb - WB)) {
+            jw = q.j - WB / 2;
+            if (jw > q.nb - WB) jw = q.nb - WB;
+            if (jw < 0) jw = 0;
+            wi = q.i;
+            // sentinel bins beyond a small grid: every event there is "slow" (never reached)
+            v_lk = 0u;
+            v_dhi = 0u;
+            v_shi = 0u;
+            if (lane < WB && jw + lane < q.nb) {
+                const uint4 r = q.hot[q.i * q.nb + jw + lane];
+                v_lk = r.x;
+                v_dhi = r.y;
+                v_shi = r.z;
+            }
+        }
+        const uint64_t sl = q.steps + (uint64_t)lane;
+        const uint64_t pr = sl >> 1;
+        const u32x4 r = philox4x32_10((uint32_t)pr, (uint32_t)(pr >> 32), q.pid, (uint32_t)q.cl, a.key0, a.key1);
+        const uint32_t tw = (sl & 1) ? r.z : r.x;
+        const uint32_t ew = (sl & 1) ? r.w : r.y;
+        uint32_t pk = 0u;
+#pragma unroll
+        for (int b = 0; b < WB; ++b) {
+            const uint32_t dh = rl(v_dhi, b), sh = rl(v_shi, b);
+            pk |= (ew < dh ? 1u : 0u) << b;
+            pk |= ((ew >= sh) || (ew == dh) ? 1u : 0u) << (WB + b);
+        }
+        uint32_t P = 1u << (q.j - jw);     // one-hot window position
+        int jj = q.j, l = 0;
+        uint32_t pst = 0u;                 // lane l: position before step l
+        bool special = false;
+        for (; l < m; ++l) {
+            const uint32_t k = rl(pk, l);
+            if ((k >> WB) & P) {
+                special = true;
+                break;
+            }
+            pst = (lane == l) ? P : pst;
+            const bool dn = (k & P) != 0u;
+            P = dn ? (P >> 1) : (P << 1);
+            jj += dn ? -1 : 1;
+            if ((P & ((1u << WB) - 1u)) == 0u) {   // left the window: this step is done
+                ++l;
+                break;
+            }
+        }
+        const int bl = __ffs((int)pst) - 1;
+        const uint32_t lk_bits = (uint32_t)__shfl((int)v_lk, bl & 63);
+        const float dl = path_length(tw, __uint_as_float(lk_bits));
+        double t = q.t;
+        for (int k = 0; k < l; ++k) t += (double)__uint_as_float(rl(__float_as_uint(dl), k));
+        q.t = t;
+        q.steps += (uint64_t)l;
+        q.j = jj;
+        if (special) {
+            const int b = jj - jw;
+            q.t += (double)path_length(rl(tw, l), __uint_as_float(rl(v_lk, b)));
+            const uint32_t e = rl(ew, l), dh = rl(v_dhi, b), sh = rl(v_shi, b);
+            Packet1D s1 = q;
+            if (lane == 0) slow_step<MOVING>(s1, e, dh, sh, tb, clouds, a, tally);
+            q.i = (int)rl((uint32_t)s1.i, 0);
+            q.j = (int)rl((uint32_t)s1.j, 0);
+            q.steps = ((uint64_t)rl((uint32_t)(s1.steps >> 32), 0) << 32) | rl((uint32_t)s1.steps, 0);
+            q.active = rl(s1.active ? 1u : 0u, 0) != 0u;
+        }
+    }
+}
+
+template <bool MOVING>
+__global__ __launch_bounds__(64) void walk1d_coop(const uint8_t *__restrict__ tb, WalkArgs a,
+                                                  unsigned long long *__restrict__ tally,
+                                                  unsigned long long *__restrict__ work)
+{
+    const DevHeader *H = reinterpret_cast<const DevHeader *>(tb);
+    const DevCloud *clouds = reinterpret_cast<const DevCloud *>(tb + H->off_clouds);
+    const int lane = threadIdx.x & 63;
+    const uint64_t n = work[1];
+    const TailPacket *tp = reinterpret_cast<const TailPacket *>(reinterpret_cast<const uint8_t *>(work) +
+                                                                kWorkHeaderBytes);
+    for (;;) {
+        uint64_t idx = 0;
+        if (lane == 0) idx = atomicAdd(&work[2], 1ull);
+        idx = shfl_u64(idx, 0);
+        if (idx >= n) break;
+        const TailPacket tk = tp[idx];
+        Packet1D q;
+        q.cl = (int)rl(tk.cl, 0);
+        const DevCloud &c = clouds[q.cl];
+        q.pid = rl(tk.pid, 0);
+        q.i = (int)rl((uint32_t)tk.i, 0);
+        q.j = (int)rl((uint32_t)tk.j, 0);
+        q.steps = ((uint64_t)rl((uint32_t)(tk.steps >> 32), 0) << 32) | rl((uint32_t)tk.steps, 0);
+        const uint64_t tb64 = ((uint64_t)rl((uint32_t)(__double_as_longlong(tk.t) >> 32), 0) << 32) |
+                              rl((uint32_t)__double_as_longlong(tk.t), 0);
+        q.t = __longlong_as_double((long long)tb64);
+        q.nb = c.nb;
+        q.nc = c.nc;
+        q.geom = c.geometry;
+        q.hot = reinterpret_cast<const uint4 *>(tb + c.off_hot);
+        q.active = true;
+        coop_walk<MOVING>(q, tb, clouds, a, tally, lane);
+    }
+}
+
 __global__ void philox_fill_kernel(uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1, uint32_t c2,
                                    uint32_t c3, uint64_t n, uint32_t *out)
 {
@@ -283,7 +465,7 @@ __global__ void philox_fill_kernel(uint32_t k0, uint32_t k1, uint32_t c0, uint32
 
 __global__ void reset_work(unsigned long long *work)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) work[0] = 0ull;
+    if (blockIdx.x == 0 && threadIdx.x < 4) work[threadIdx.x] = 0ull;
 }
 
 }  // namespace
@@ -298,7 +480,8 @@ int device_cu_count()
 
 hipError_t launch_walk(const uint8_t *d_tables, const DevHeader &h, const DevCloud *host_clouds,
                        const rddmc_run &run, uint64_t first, uint64_t count,
-                       unsigned long long *d_tally, unsigned long long *d_work, hipStream_t s)
+                       unsigned long long *d_tally, unsigned long long *d_work, uint64_t work_bytes,
+                       hipStream_t s)
 {
     WalkArgs a;
     a.first = first;
@@ -308,22 +491,41 @@ hipError_t launch_walk(const uint8_t *d_tables, const DevHeader &h, const DevClo
     a.key1 = (uint32_t)(run.seed >> 32);
     a.chunk = run.chunk > 0 ? (run.chunk + 1) / 2 : 32;   // in pairs of steps
     a.n_clouds = h.n_clouds;
+    a.tail_lanes = run.tail_lanes == 0 ? 16 : (run.tail_lanes < 0 ? 0 : run.tail_lanes);
+    a.pad = 0;
+    a.tail_capacity = work_bytes > kWorkHeaderBytes ? (work_bytes - kWorkHeaderBytes) / sizeof(TailPacket) : 0;
+    if (a.tail_capacity == 0) a.tail_lanes = 0;
     const int block = run.block > 0 ? run.block : 256;
-    int grid = run.grid;
-    if (grid <= 0) {
-        const uint64_t lanes = count;
-        const uint64_t want = (lanes + block - 1) / block;
+    uint64_t grid = run.grid > 0 ? (uint64_t)run.grid : 0;
+    if (grid == 0) {
+        const uint64_t want = (count + block - 1) / block;
         const uint64_t cap = (uint64_t)device_cu_count() * 8;   // 8 blocks of 256 per CU
-        grid = (int)(want < cap ? want : cap);
+        grid = want < cap ? want : cap;
         if (grid < 1) grid = 1;
+    }
+    const uint64_t lanes = grid * (uint64_t)block;
+    if (a.tail_lanes > 0 && (lanes < count ? lanes : count) > a.tail_capacity) {
+        // every exported packet (at most one per lane, at most `count`) needs a slot
+        grid = a.tail_capacity / block;
+        if (grid < 1) {
+            grid = 1;
+            a.tail_lanes = 0;
+        }
     }
     bool moving = false;
     for (int c = 0; c < h.n_clouds; ++c) moving |= host_clouds[c].moving != 0;
     reset_work<<<1, 64, 0, s>>>(d_work);
     if (moving)
-        walk1d<true><<<grid, block, 0, s>>>(d_tables, a, d_tally, d_work);
+        walk1d<true><<<(unsigned)grid, block, 0, s>>>(d_tables, a, d_tally, d_work);
     else
-        walk1d<false><<<grid, block, 0, s>>>(d_tables, a, d_tally, d_work);
+        walk1d<false><<<(unsigned)grid, block, 0, s>>>(d_tables, a, d_tally, d_work);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || a.tail_lanes == 0) return e;
+    const unsigned cgrid = (unsigned)device_cu_count() * 16;   // one wave per block
+    if (moving)
+        walk1d_coop<true><<<cgrid, 64, 0, s>>>(d_tables, a, d_tally, d_work);
+    else
+        walk1d_coop<false><<<cgrid, 64, 0, s>>>(d_tables, a, d_tally, d_work);
     return hipGetLastError();
 }
 

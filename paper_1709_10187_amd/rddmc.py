@@ -48,7 +48,7 @@ class Batch_t(C.Structure):
 class Run_t(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("first", C.c_uint64), ("count", C.c_uint64),
                 ("max_steps", C.c_uint64), ("block", C.c_int32), ("grid", C.c_int32),
-                ("chunk", C.c_int32), ("reserved0", C.c_int32)]
+                ("chunk", C.c_int32), ("tail_lanes", C.c_int32)]
 
 
 class CloudStats_t(C.Structure):
@@ -187,9 +187,10 @@ def tally_reset(b: Batch, d_tally, stream=None):
 
 
 def transport(b: Batch, d_tables, d_tally, d_work, seed=0, first=0, count=0, max_steps=(1 << 62),
-              block=0, grid=0, chunk=0, stream=None):
+              block=0, grid=0, chunk=0, tail_lanes=0, stream=None):
     lib = load()
-    run = Run_t(int(seed), int(first), int(count), int(max_steps), int(block), int(grid), int(chunk), 0)
+    run = Run_t(int(seed), int(first), int(count), int(max_steps), int(block), int(grid), int(chunk),
+                int(tail_lanes))
     _check(lib.rddmc_transport(b.ref(), C.c_void_p(d_tables.data_ptr()), C.byref(run),
                                C.c_void_p(d_tally.data_ptr()), d_tally.numel() * d_tally.element_size(),
                                C.c_void_p(d_work.data_ptr()), d_work.numel() * d_work.element_size(),

@@ -126,12 +126,13 @@ def test_config_sphere_sampled_packets():
 def test_bit_identical_across_launch_shapes_and_shards():
     m = media.slab(1e4, 1e4, 16, 33).with_packets(20000)
     outs = []
-    for kw in (dict(), dict(block=64, grid=5, chunk=7), dict(block=128, grid=1000, chunk=1)):
+    for kw in (dict(tail_lanes=-1), dict(), dict(block=64, grid=5, chunk=7, tail_lanes=64),
+               dict(block=128, grid=1000, chunk=1, tail_lanes=3), dict(tail_lanes=64, chunk=2)):
         _, r = _run(m, seed=9, **kw)
         outs.append(r)
     p = rddmc.Problem(m)
     for first, count in ((0, 7001), (7001, 12999 - 7001), (12999, 20000 - 12999)):
-        p.run(seed=9, first=first, count=count, block=192, chunk=33)
+        p.run(seed=9, first=first, count=count, block=192, chunk=33, tail_lanes=40)
     outs.append(p.results()[0])
     for o in outs[1:]:
         np.testing.assert_array_equal(o.spectrum, outs[0].spectrum)
@@ -143,6 +144,19 @@ def test_bit_identical_across_launch_shapes_and_shards():
     # a different seed gives a different sample
     _, r2 = _run(m, seed=10)
     assert not np.array_equal(r2.spectrum, outs[0].spectrum)
+
+
+def test_cooperative_tail_is_bit_identical_on_moving_media():
+    """The cooperative tail walk (a wave advances one packet) must reproduce the lane walk bit
+    for bit, including Doppler re-binning, lab-frame escapes and the step cap."""
+    for m, cap in ((SMALL["sphere_outflow"].with_packets(3000), 1 << 62),
+                   (SMALL["sphere_inflow_cold"].with_packets(3000), 5000)):
+        a = _run(m, seed=21, tail_lanes=-1, max_steps=cap)[1]
+        b = _run(m, seed=21, tail_lanes=64, max_steps=cap)[1]
+        np.testing.assert_array_equal(a.spectrum, b.spectrum)
+        np.testing.assert_array_equal(a.time_hist, b.time_hist)
+        np.testing.assert_array_equal(a.step_hist, b.step_hist)
+        assert (a.steps_total, a.capped, a.t_mean, a.t_var) == (b.steps_total, b.capped, b.t_mean, b.t_var)
 
 
 def test_step_cap_matches_exact_survival():
