@@ -36,11 +36,12 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=0,
+                    help="untimed blocks before the timed ones (module load happens at the table build)")
     ap.add_argument("--block-packets", type=int, default=1 << 16,
                     help="packets of the 2^22-packet job per benchmark step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-packets", type=int, default=24)
+    ap.add_argument("--cpu-packets", type=int, default=12)
     ap.add_argument("--cpu-threads", type=int, default=0)
     return ap.parse_args()
 

@@ -81,6 +81,10 @@ enum { RDDMC_SLAB = 0, RDDMC_SPHERE = 1, RDDMC_CART3D = 2 };
  *                x,y,z) and comoving frequencies.  A source exactly on an interior face
  *                or bin edge is split with probability 1/2 between its two neighbours;
  *                packets are shared equally between sources.
+ *   stream       this cloud's random-stream key: packet p of the cloud draws from Philox
+ *                counters (step, p, stream); results of a cloud depend on (seed, stream)
+ *                only, not on its position in a batch.  Give clouds of one batch distinct
+ *                keys (the Python binding uses the batch index).
  *   n_packets    packets emitted by this cloud (initial flash, equal weights, t = 0).
  */
 typedef struct {
@@ -97,7 +101,7 @@ typedef struct {
     double f_mu;
     double lambda;
     int32_t n_src;
-    int32_t reserved0;
+    uint32_t stream;
     const double *src_pos;
     const double *src_x;
     uint64_t n_packets;
@@ -113,7 +117,7 @@ typedef struct {
 /*
  * Transport run parameters.
  *   seed         Philox4x32-10 key (Salmon et al. 2011); every packet's stream is keyed
- *                by (seed, cloud, packet id) and indexed by its step count.
+ *                by (seed, cloud stream key, packet id) and indexed by its step count.
  *   first, count packets first .. first+count-1 of the batch's flattened packet space
  *                (cloud 0's packets, then cloud 1's, ...); count = 0 means "to the end".
  *   max_steps    per-packet step cap (>= 1); capped packets are counted, not dropped.

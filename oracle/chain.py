@@ -75,6 +75,31 @@ def _overlap_matrix(edges, lo, hi):
     return np.asarray(idx), wt / wt.sum()
 
 
+def _overlaps(edges, A, B):
+    """All bins' images [A_j, B_j] re-binned on ``edges``: returns (j, j', weight) triples
+    with weight = fraction of [A_j, B_j] inside bin j' (parts below / above the grid are
+    given to the first / last bin).  Same rule as _overlap_matrix, vectorised over j."""
+    nb = len(edges) - 1
+    w = B - A
+    first = np.clip(np.searchsorted(edges, A, side="right") - 1, 0, nb - 1)
+    last = np.clip(np.searchsorted(edges, B, side="left") - 1, 0, nb - 1)
+    span = int((last - first).max()) + 1
+    js, jd, wt = [], [], []
+    for d in range(span):
+        jp = first + d
+        ok = jp <= last
+        lo = np.where(jp > 0, np.maximum(A, edges[np.minimum(jp, nb)]), A)
+        hi = np.where(jp < nb - 1, np.minimum(B, edges[np.minimum(jp + 1, nb)]), B)
+        frac = np.clip(hi - lo, 0.0, None) / w
+        ok &= frac > 0
+        js.append(np.nonzero(ok)[0])
+        jd.append(jp[ok])
+        wt.append(frac[ok])
+    js, jd, wt = np.concatenate(js), np.concatenate(jd), np.concatenate(wt)
+    tot = np.bincount(js, weights=wt, minlength=len(A))
+    return js, jd, wt / tot[js]
+
+
 def _ramp_area(t):
     t = np.maximum(t, 0.0)
     return 0.5 * t * t
@@ -161,18 +186,11 @@ def solve(m, tabs=None) -> ChainResult:
                     er.append(r[j] * pb[nzb])
                 continue
             rho, sh = t.rho[c, f], t.shift[c, f]
-            for j in range(nb):
-                if r[j] <= 0:
-                    continue
-                if rho == 1.0 and sh == 0.0:
-                    rows.append(np.array([c * nb + j]))
-                    cols.append(np.array([n * nb + j]))
-                    vals.append(np.array([r[j]]))
-                else:
-                    idx, wt = _overlap_matrix(edges, rho * lo_e[j] + sh, rho * hi_e[j] + sh)
-                    rows.append(np.full(len(idx), c * nb + j))
-                    cols.append(n * nb + idx)
-                    vals.append(r[j] * wt)
+            src_j, dst_j, wts = _overlaps(edges, rho * lo_e + sh, rho * hi_e + sh)
+            keep = r[src_j] > 0
+            rows.append(c * nb + src_j[keep])
+            cols.append(n * nb + dst_j[keep])
+            vals.append(r[src_j[keep]] * wts[keep])
     rows = np.concatenate(rows)
     cols = np.concatenate(cols)
     vals = np.concatenate(vals) / K[rows]

@@ -115,6 +115,11 @@ __global__ void build_maps(DevCloud c, uint8_t *tb)
     map[0] = rho;
     map[1] = shift;
     map[2] = vn_c / vth_dev(T[cell]);
+    if (c.nf == 2) {   // compact per-cell copy read together with the hot record
+        float *cm = reinterpret_cast<float *>(tb + c.off_cmap) + 4 * cell + 2 * f;
+        cm[0] = (float)rho;
+        cm[1] = (float)shift;
+    }
 }
 
 __global__ void build_k(DevCloud c, uint8_t *tb, uint32_t *err)
@@ -205,7 +210,8 @@ __global__ void build_rates(DevCloud c, uint8_t *tb, uint32_t *err)
     const double K = rs + rd + ru;
     if (!(K > 0.0) || !isfinite(K)) atomicOr(err, (uint32_t)BE_NONFINITE);
 
-    // categorical thresholds in units of 2^-64: D = P(lower), S = 1 - P(spatial)
+    // categorical thresholds in units of 2^-64: D = P(lower), S = 1 - P(spatial),
+    // F = S + P(face 0) (the face-0 / face-1 boundary of 1D cells)
     const uint64_t D = prob_to_u64(rd / K);
     uint64_t Tsp = prob_to_u64(rs / K);
     uint64_t S;
@@ -216,15 +222,20 @@ __global__ void build_rates(DevCloud c, uint8_t *tb, uint32_t *err)
         S = 0ull - Tsp;                             // 2^64 - Tsp
         if (S < D) S = D;
     }
+    // face 1 gets [F, 2^64); saturate if rounding leaves it less than nothing
+    uint64_t F = S + prob_to_u64(rf[0] / K);
+    if (F < S || rf[1] <= 0.0) F = ~0ull;
     HotRecord h;
     h.ln2_over_K = (float)(0.69314718055994530942 / K);
     h.d_hi = (uint32_t)(D >> 32);
     h.s_hi = (uint32_t)(S >> 32);
-    h.spare = 0u;
+    h.f_hi = (uint32_t)(F >> 32);
     reinterpret_cast<HotRecord *>(tb + c.off_hot)[s] = h;
-    uint32_t *lw = reinterpret_cast<uint32_t *>(tb + c.off_lo_words) + 2 * s;
+    uint32_t *lw = reinterpret_cast<uint32_t *>(tb + c.off_lo_words) + 4 * s;
     lw[0] = (uint32_t)D;
     lw[1] = (uint32_t)S;
+    lw[2] = (uint32_t)F;
+    lw[3] = 0u;
 
     // cumulative face split: thresholds for faces 0 .. nf-2
     uint32_t *fsplit = reinterpret_cast<uint32_t *>(tb + c.off_face_split) + s * (nf - 1);

@@ -170,10 +170,21 @@ rddmc_status make_layout(const rddmc_batch *b, Layout &L)
         }
         L.any_moving |= c.moving != 0;
         c.n_packets = m.n_packets;
+        c.stream = m.stream;
         c.packet_base = L.prefix[ci];
         L.prefix[ci + 1] = L.prefix[ci] + m.n_packets;
         c.n_states = (uint64_t)c.nc * c.nb;
         c.tau_th = m.tau_threshold;
+        {
+            const double e0 = m.bin_edges[0], dxu = (m.bin_edges[m.n_bins] - e0) / m.n_bins;
+            bool uni = true;
+            for (int j = 0; j <= m.n_bins && uni; ++j)
+                uni = std::fabs(m.bin_edges[j] - (e0 + j * dxu)) <= 1e-9 * std::fabs(dxu);
+            c.uniform_bins = uni ? 1 : 0;
+            c.x0 = (float)e0;
+            c.dx = (float)dxu;
+            c.inv_dx = (float)(1.0 / dxu);
+        }
         c.f_mu = m.f_mu;
         c.lambda = m.lambda;
         // sources -> (state, probability)
@@ -212,10 +223,11 @@ rddmc_status make_layout(const rddmc_batch *b, Layout &L)
         c.off_src_cdf = take(8ull * c.n_src);
         c.off_k = take(8ull * c.n_states);
         c.off_hot = take(sizeof(HotRecord) * c.n_states);
-        c.off_lo_words = take(8ull * c.n_states);
+        c.off_lo_words = take(16ull * c.n_states);
         c.off_face_split = take(4ull * c.n_states * (c.nf - 1));
         c.off_rates = c.keep_rates ? take(8ull * c.n_states * (c.nf + 2)) : 0;
         c.off_map = take(8ull * 3 * c.nc * c.nf);
+        c.off_cmap = take(16ull * c.nc);
         c.tally_off = tally;
         c.tally_words = kTallyHeader + (uint64_t)c.n_rows * (c.nb + 2) + (RDDMC_TIME_BINS + 2) + RDDMC_STEP_BINS;
         tally += c.tally_words;
@@ -438,7 +450,7 @@ rddmc_status rddmc_read_tables(const rddmc_batch *batch, const void *d_tables, i
     if (hot && (e = hipMemcpyAsync(hot, base + c.off_hot, sizeof(HotRecord) * c.n_states, hipMemcpyDeviceToHost,
                                    s)) != hipSuccess)
         return hip_fail(e, "read hot");
-    if (lo_words && (e = hipMemcpyAsync(lo_words, base + c.off_lo_words, 8 * c.n_states, hipMemcpyDeviceToHost,
+    if (lo_words && (e = hipMemcpyAsync(lo_words, base + c.off_lo_words, 16 * c.n_states, hipMemcpyDeviceToHost,
                                         s)) != hipSuccess)
         return hip_fail(e, "read lo words");
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");

@@ -24,16 +24,18 @@ enum TallyWord {
     TW_LAUNCHED = 7,
 };
 
-// The per-state record every DDMC step reads: one 16-byte load.  With
-// D = P(lower bin) * 2^64 and S = (P(lower bin) + P(upper bin)) * 2^64 (u64), a uniform
-// u64 U selects: U < D -> lower bin, D <= U < S -> upper bin, U >= S -> spatial leak.
-// Only the high words of D and S live here; the low words (needed only when the high
-// word of U ties with one of them, probability ~2^-31) live in the cold `lo_words` array.
+// The per-state record every DDMC step reads: one 16-byte load.  A uniform u64 U picks the
+// event against three u64 thresholds D <= S <= F:
+//   U < D -> lower bin,  D <= U < S -> upper bin,  S <= U < F -> face 0,  U >= F -> face 1
+// (1D geometries; 3D uses the first two and a separate face CDF), with
+// D = P(lower bin) 2^64, S = (1 - P(spatial)) 2^64, F = S + P(face 0) 2^64.
+// Only the high words live here; the low words (needed only when U's high word ties with a
+// threshold's, probability ~3 * 2^-32) live in the cold `lo_words` array.
 struct alignas(16) HotRecord {
     float ln2_over_K;      // ln(2) / K, K = total leakage rate of the state [1/length]
     uint32_t d_hi;         // high word of D
     uint32_t s_hi;         // high word of S
-    uint32_t spare;
+    uint32_t f_hi;         // high word of F
 };
 static_assert(sizeof(HotRecord) == 16, "hot record must be 16 bytes");
 
@@ -43,6 +45,7 @@ struct alignas(16) DevCloud {
     int32_t n[3];
     int32_t moving;
     int32_t n_src, keep_rates, n_rows, dirichlet;
+    uint32_t stream, pad0;
     uint64_t n_packets;
     uint64_t packet_base;        // flattened index of this cloud's first packet
     uint64_t n_states;
@@ -53,13 +56,16 @@ struct alignas(16) DevCloud {
     uint64_t off_src_cdf;        // f64 [n_src]
     uint64_t off_k;              // f64 [n_states]   eq. 14
     uint64_t off_hot;            // HotRecord [n_states]
-    uint64_t off_lo_words;       // u32x2 [n_states]: low words of D and S
+    uint64_t off_lo_words;       // u32x4 [n_states]: low words of D, S, F and 0
     uint64_t off_face_split;     // u32 [n_states * (nf-1)]  P(face f | spatial) CDF * 2^31
     uint64_t off_rates;          // f64 [n_states * (nf+2)]  (only with keep_rates)
     uint64_t off_map;            // f64 [nc * nf * 3]: rho, shift, u_n per (cell, face)
+    uint64_t off_cmap;           // f32x4 [nc] (1D): rho and shift of face 0, then of face 1
     uint64_t tally_off;          // int64 word offset of this cloud's tally block
     uint64_t tally_words;
     double tau_th, f_mu, lambda;
+    float x0, dx, inv_dx;        // uniform bin grid: first edge, width, 1/width
+    int32_t uniform_bins;        // 1 when every bin has the same width
 };
 
 struct alignas(16) DevHeader {

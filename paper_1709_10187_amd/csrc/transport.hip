@@ -125,78 +125,150 @@ __device__ __forceinline__ float path_length(uint32_t tw, float ln2_over_K)
 // Per-lane packet state of the 1D walk.
 struct Packet1D {
     int cl, nb, nc, geom;
-    uint32_t pid;
+    uint32_t pid, key;         // packet id within its cloud; the cloud's stream key
     int i, j;
     double t;
     uint64_t steps;
     const uint4 *hot;          // HotRecord viewed as 4 words
+    const float4 *cmap;        // per-cell Doppler maps {rho0, shift0, rho1, shift1}
+    float x0, dx, inv_dx;      // uniform bin grid
+    bool uniform;
+    bool moving;               // the cloud has bulk velocity (one Philox block per step)
     bool active;
 };
 
-// Rare path of a step: the high word tied with a threshold (resolved with an auxiliary
-// low word) or the step is a spatial leak.  Returns false when the packet escaped.
+// Random words of one step.  Static clouds: one Philox block serves two steps (time and
+// event words); moving clouds: one block per step (time, event, re-binning, escape mu).
+// The layout is a property of the cloud, so a cloud's packets draw the same numbers in
+// whichever kernel variant walks them.
+struct StepWords {
+    uint32_t t, e, z, w;
+};
+
+// Comoving re-binning across face `face` (Sec. 2.5, eq. 20): x uniform in bin j, mapped to
+// the neighbour's frame x' = rho x + shift, re-binned and clamped to the grid.
+__device__ __forceinline__ void rebin(Packet1D &p, int face, float4 cm, uint32_t zw,
+                                      const DevCloud &c, const uint8_t *__restrict__ tb)
+{
+    const float rho = face ? cm.z : cm.x;
+    const float sh = face ? cm.w : cm.y;
+    if (rho == 1.0f && sh == 0.0f) return;
+    int jn;
+    if (p.uniform) {
+        const float u = ((float)(zw >> 8) + 0.5f) * 5.9604644775390625e-8f;   // 24-bit uniform
+        const float x = p.x0 + ((float)p.j + u) * p.dx;
+        jn = (int)floorf((fmaf(rho, x, sh) - p.x0) * p.inv_dx);
+    } else {
+        const double *e = reinterpret_cast<const double *>(tb + c.off_edges);
+        const double x = e[p.j] + (e[p.j + 1] - e[p.j]) * u01_open_low(zw);
+        jn = locate_bin(e, p.nb, (double)rho * x + (double)sh);
+    }
+    p.j = jn < 0 ? 0 : (jn > p.nb - 1 ? p.nb - 1 : jn);
+}
+
+// Rare path of a step: the event word tied with a threshold's high word (resolved with an
+// auxiliary low word) or an escape.  Returns false when the packet escaped.
 template <bool MOVING>
-__device__ __forceinline__ bool slow_step(Packet1D &p, uint32_t ew, uint32_t d_hi, uint32_t s_hi,
-                                       const uint8_t *__restrict__ tb, const DevCloud *__restrict__ clouds,
-                                       const WalkArgs &a, unsigned long long *__restrict__ tally)
+__device__ __forceinline__ bool slow_step(Packet1D &p, StepWords w, uint4 rec, float4 cm,
+                                          const uint8_t *__restrict__ tb, const DevCloud *__restrict__ clouds,
+                                          const WalkArgs &a, unsigned long long *__restrict__ tally)
 {
     const DevCloud &c = clouds[p.cl];
     const int s = p.i * p.nb + p.j;
-    const u32x4 aux = philox4x32_10((uint32_t)p.steps, kDomAux | (uint32_t)(p.steps >> 32), p.pid,
-                                    (uint32_t)p.cl, a.key0, a.key1);
-    const uint2 lw = reinterpret_cast<const uint2 *>(tb + c.off_lo_words)[s];
-    const uint64_t U = ((uint64_t)ew << 32) | aux.x;
-    const uint64_t D = ((uint64_t)d_hi << 32) | lw.x;
-    const uint64_t S = ((uint64_t)s_hi << 32) | lw.y;
+    const u32x4 aux = philox4x32_10((uint32_t)p.steps, kDomAux | (uint32_t)(p.steps >> 32), p.pid, p.key,
+                                    a.key0, a.key1);
+    const uint4 lw = reinterpret_cast<const uint4 *>(tb + c.off_lo_words)[s];
+    const uint64_t U = ((uint64_t)w.e << 32) | aux.x;
+    const uint64_t D = ((uint64_t)rec.y << 32) | lw.x;
+    const uint64_t S = ((uint64_t)rec.z << 32) | lw.y;
+    const uint64_t F = ((uint64_t)rec.w << 32) | lw.z;
     if (U < D) { --p.j; ++p.steps; return true; }
     if (U < S) { ++p.j; ++p.steps; return true; }
     // spatial leak: face 0 (lower / inner) or face 1 (upper / outer)
-    const uint32_t fs = reinterpret_cast<const uint32_t *>(tb + c.off_face_split)[s];
-    const int face = ((aux.y & 0x7fffffffu) < fs) ? 0 : 1;
+    const int face = (U < F) ? 0 : 1;
     const int ni = face ? p.i + 1 : p.i - 1;
-    const double *e = reinterpret_cast<const double *>(tb + c.off_edges);
-    const double *map = reinterpret_cast<const double *>(tb + c.off_map) + 3 * (p.i * 2 + face);
     ++p.steps;
     if (ni < 0 || ni >= p.nc) {
         int slot = p.j + 1;
-        if (MOVING && map[2] != 0.0) {   // lab frame: x uniform in the bin, outward mu uniform
-            const double x = e[p.j] + (e[p.j + 1] - e[p.j]) * u01_open_low(aux.z);
-            slot = locate_bin(e, p.nb, x + u01_open_low(aux.w) * map[2]) + 1;
+        if (MOVING && p.moving) {   // lab frame: x uniform in the bin, outward mu uniform in (0, 1]
+            const double *e = reinterpret_cast<const double *>(tb + c.off_edges);
+            const double un = reinterpret_cast<const double *>(tb + c.off_map)[3 * (p.i * 2 + face) + 2];
+            if (un != 0.0) {
+                const double x = e[p.j] + (e[p.j + 1] - e[p.j]) * u01_open_low(w.z);
+                slot = locate_bin(e, p.nb, x + u01_open_low(w.w) * un) + 1;
+            }
         }
         tally_finish(tally, c, true, (p.geom == RDDMC_SLAB) ? face : 0, slot, p.t, p.steps);
         p.active = false;
         return false;
     }
-    if (MOVING && (map[0] != 1.0 || map[1] != 0.0)) {   // comoving re-binning (eq. 20)
-        const double x = e[p.j] + (e[p.j + 1] - e[p.j]) * u01_open_low(aux.z);
-        const int jn = locate_bin(e, p.nb, map[0] * x + map[1]);
-        p.j = jn < 0 ? 0 : (jn > p.nb - 1 ? p.nb - 1 : jn);
-    }
+    if (MOVING && p.moving) rebin(p, face, cm, w.z, c, tb);
     p.i = ni;
     return true;
 }
 
-// One step with the words (tw: path length, ew: event high word) and the state's record.
-// Returns -1 / +1 for a frequency move decided on the fast path, 0 otherwise.
+// One step with its random words, the state's hot record and (moving media) the cell's
+// Doppler map.  Returns -1 / +1 for a frequency move and 2 for a spatial move decided on
+// the fast path, 0 for a step that took the slow path.
 template <bool MOVING>
-__device__ __forceinline__ int one_step(Packet1D &p, uint32_t tw, uint32_t ew, uint4 rec,
+__device__ __forceinline__ int one_step(Packet1D &p, StepWords w, uint4 rec, float4 cm,
                                         const uint8_t *__restrict__ tb, const DevCloud *__restrict__ clouds,
                                         const WalkArgs &a, unsigned long long *__restrict__ tally)
 {
-    p.t += (double)path_length(tw, __uint_as_float(rec.x));
-    if (__builtin_expect(ew < rec.z && ew != rec.y, 1)) {
-        const int d = (ew < rec.y) ? -1 : 1;
-        p.j += d;
-        ++p.steps;
-        return d;
+    p.t += (double)path_length(w.t, __uint_as_float(rec.x));
+    const uint32_t ew = w.e;
+    const bool tie = (ew == rec.y) | (ew == rec.z) | (ew == rec.w);
+    if (__builtin_expect(!tie, 1)) {
+        if (ew < rec.z) {
+            const int d = (ew < rec.y) ? -1 : 1;
+            p.j += d;
+            ++p.steps;
+            return d;
+        }
+        const int face = (ew < rec.w) ? 0 : 1;
+        const int ni = face ? p.i + 1 : p.i - 1;
+        if ((unsigned)ni < (unsigned)p.nc) {
+            if (MOVING && p.moving) rebin(p, face, cm, w.z, clouds[p.cl], tb);
+            p.i = ni;
+            ++p.steps;
+            return 2;
+        }
     }
-    slow_step<MOVING>(p, ew, rec.y, rec.z, tb, clouds, a, tally);
+    slow_step<MOVING>(p, w, rec, cm, tb, clouds, a, tally);
     return 0;
 }
 
+template <bool MOVING>
+__device__ __forceinline__ StepWords words_of_step(const Packet1D &p, uint64_t step, const WalkArgs &a)
+{
+    if (MOVING && p.moving) {
+        const u32x4 r = philox4x32_10((uint32_t)step, (uint32_t)(step >> 32), p.pid, p.key, a.key0, a.key1);
+        return {r.x, r.y, r.z, r.w};
+    }
+    const uint64_t pr = step >> 1;
+    const u32x4 r = philox4x32_10((uint32_t)pr, (uint32_t)(pr >> 32), p.pid, p.key, a.key0, a.key1);
+    return (step & 1) ? StepWords{r.z, r.w, 0u, 0u} : StepWords{r.x, r.y, 0u, 0u};
+}
+
+// A few single steps of one packet (lane-walk arithmetic), used by the cooperative walk
+// where spatial leaks dominate.
+template <bool MOVING>
+__device__ void single_steps(Packet1D &p, int n, const uint8_t *__restrict__ tb,
+                             const DevCloud *__restrict__ clouds, const WalkArgs &a,
+                             unsigned long long *__restrict__ tally)
+{
+    for (int k = 0; k < n && p.active && p.steps < a.max_steps; ++k) {
+        const StepWords w = words_of_step<MOVING>(p, p.steps, a);
+        const uint4 rec = p.hot[p.i * p.nb + p.j];
+        const float4 cm = (MOVING && p.moving) ? p.cmap[p.i] : make_float4(1.f, 0.f, 1.f, 0.f);
+        one_step<MOVING>(p, w, rec, cm, tb, clouds, a, tally);
+    }
+}
+
 // 1D walk (slab or sphere), pure DDMC; MOVING enables Doppler re-binning and lab-frame
-// escape frequencies.  One Philox block per pair of steps: (x, y) for the even step and
-// (z, w) for the odd one; all active lanes of a wave are at even step counts between pairs.
+// escape frequencies.  Static media take one Philox block per pair of steps ((x, y) for the
+// even step and (z, w) for the odd one; all active lanes of a wave are at even step counts
+// between pairs); moving media take one block per step.
 template <bool MOVING>
 __global__ __launch_bounds__(256) void walk1d(const uint8_t *__restrict__ tb, WalkArgs a,
                                               unsigned long long *__restrict__ tally,
@@ -209,8 +281,10 @@ __global__ __launch_bounds__(256) void walk1d(const uint8_t *__restrict__ tb, Wa
 
     Packet1D p;
     p.active = false;
-    p.cl = 0; p.nb = 1; p.nc = 1; p.geom = 0; p.pid = 0; p.i = 0; p.j = 0; p.t = 0.0; p.steps = 0;
+    p.cl = 0; p.nb = 1; p.nc = 1; p.geom = 0; p.pid = 0; p.key = 0; p.i = 0; p.j = 0; p.t = 0.0; p.steps = 0;
     p.hot = nullptr;
+    p.cmap = nullptr;
+    p.x0 = 0.f; p.dx = 1.f; p.inv_dx = 1.f; p.uniform = false; p.moving = false;
     int last_state = 0;
     bool exhausted = false;       // wave-uniform: the queue is empty
 
@@ -238,13 +312,20 @@ __global__ __launch_bounds__(256) void walk1d(const uint8_t *__restrict__ tb, Wa
                         p.cl = lo;
                         const DevCloud &c = clouds[lo];
                         p.pid = (uint32_t)(g - prefix[lo]);
+                        p.key = c.stream;
                         p.nb = c.nb;
                         p.nc = c.nc;
                         p.geom = c.geometry;
                         p.hot = reinterpret_cast<const uint4 *>(tb + c.off_hot);
+                        p.cmap = reinterpret_cast<const float4 *>(tb + c.off_cmap);
+                        p.x0 = c.x0;
+                        p.dx = c.dx;
+                        p.inv_dx = c.inv_dx;
+                        p.uniform = c.uniform_bins != 0;
+                        p.moving = c.moving != 0;
                         last_state = (int)c.n_states - 1;
                         // emission (Sec. 2.3): a source state drawn by its probability
-                        const u32x4 r = philox4x32_10(0u, kDomEmit, p.pid, (uint32_t)lo, a.key0, a.key1);
+                        const u32x4 r = philox4x32_10(0u, kDomEmit, p.pid, p.key, a.key0, a.key1);
                         const double u = u01_open_low(r.x);
                         const int32_t *ss = reinterpret_cast<const int32_t *>(tb + c.off_src_state);
                         const double *cdf = reinterpret_cast<const double *>(tb + c.off_src_cdf);
@@ -289,24 +370,39 @@ __global__ __launch_bounds__(256) void walk1d(const uint8_t *__restrict__ tb, Wa
 
         // ---- walk up to `chunk` pairs of steps ---------------------------------------
         const uint64_t left = p.active ? (a.max_steps - p.steps) : 0ull;
-        const uint64_t pairs = (left + 1) >> 1;
-        const int budget = pairs < (uint64_t)a.chunk ? (int)pairs : a.chunk;
-        for (int k = 0; k < budget; ++k) {
-            const int s = p.i * p.nb + p.j;
-            const uint4 rm = p.hot[s > 0 ? s - 1 : 0];
-            const uint4 r0 = p.hot[s];
-            const uint4 rp = p.hot[s < last_state ? s + 1 : last_state];
-            const uint64_t pair = p.steps >> 1;
-            const u32x4 r = philox4x32_10((uint32_t)pair, (uint32_t)(pair >> 32), p.pid, (uint32_t)p.cl,
-                                          a.key0, a.key1);
-            const int d = one_step<MOVING>(p, r.x, r.y, r0, tb, clouds, a, tally);
-            if (!p.active || p.steps >= a.max_steps) break;
-            uint4 rb;
-            if (d < 0) rb = rm;
-            else if (d > 0) rb = rp;
-            else rb = p.hot[p.i * p.nb + p.j];
-            one_step<MOVING>(p, r.z, r.w, rb, tb, clouds, a, tally);
-            if (!p.active) break;
+        if (!(MOVING && p.moving)) {
+            const uint64_t pairs = (left + 1) >> 1;
+            const int budget = pairs < (uint64_t)a.chunk ? (int)pairs : a.chunk;
+            for (int k = 0; k < budget; ++k) {
+                const int s = p.i * p.nb + p.j;
+                const uint4 rm = p.hot[s > 0 ? s - 1 : 0];
+                const uint4 r0 = p.hot[s];
+                const uint4 rp = p.hot[s < last_state ? s + 1 : last_state];
+                const uint64_t pair = p.steps >> 1;
+                const u32x4 r = philox4x32_10((uint32_t)pair, (uint32_t)(pair >> 32), p.pid, p.key,
+                                              a.key0, a.key1);
+                const float4 nomap = make_float4(1.f, 0.f, 1.f, 0.f);
+                const int d = one_step<MOVING>(p, StepWords{r.x, r.y, 0u, 0u}, r0, nomap, tb, clouds, a, tally);
+                if (!p.active || p.steps >= a.max_steps) break;
+                uint4 rb;
+                if (d == -1) rb = rm;
+                else if (d == 1) rb = rp;
+                else rb = p.hot[p.i * p.nb + p.j];   // spatial move or slow step: new record
+                one_step<MOVING>(p, StepWords{r.z, r.w, 0u, 0u}, rb, nomap, tb, clouds, a, tally);
+                if (!p.active) break;
+            }
+        }
+        if (MOVING && p.moving) {
+            const uint64_t lim = 2ull * (uint64_t)a.chunk;
+            const int budget = left < lim ? (int)left : (int)lim;
+            for (int k = 0; k < budget; ++k) {
+                const uint4 rec = p.hot[p.i * p.nb + p.j];
+                const float4 cm = p.cmap[p.i];
+                const u32x4 r = philox4x32_10((uint32_t)p.steps, (uint32_t)(p.steps >> 32), p.pid, p.key,
+                                              a.key0, a.key1);
+                one_step<true>(p, StepWords{r.x, r.y, r.z, r.w}, rec, cm, tb, clouds, a, tally);
+                if (!p.active) break;
+            }
         }
         if (p.active && p.steps >= a.max_steps) {
             tally_finish(tally, clouds[p.cl], false, 0, 0, p.t, p.steps);
@@ -337,7 +433,7 @@ __device__ void coop_walk(Packet1D &q, const uint8_t *__restrict__ tb, const Dev
 {
     constexpr int WB = 16;
     int wi = -1, jw = 0;
-    uint32_t v_lk = 0u, v_dhi = 0u, v_shi = 0u;
+    uint32_t v_lk = 0u, v_dhi = 0u, v_shi = 0u, v_fhi = 0u;
     while (q.active) {
         const uint64_t left = a.max_steps - q.steps;
         if (left == 0) {
@@ -355,18 +451,18 @@ __device__ void coop_walk(Packet1D &q, const uint8_t *__restrict__ tb, const Dev
             v_lk = 0u;
             v_dhi = 0u;
             v_shi = 0u;
+            v_fhi = 0u;
             if (lane < WB && jw + lane < q.nb) {
                 const uint4 r = q.hot[q.i * q.nb + jw + lane];
                 v_lk = r.x;
                 v_dhi = r.y;
                 v_shi = r.z;
+                v_fhi = r.w;
             }
         }
-        const uint64_t sl = q.steps + (uint64_t)lane;
-        const uint64_t pr = sl >> 1;
-        const u32x4 r = philox4x32_10((uint32_t)pr, (uint32_t)(pr >> 32), q.pid, (uint32_t)q.cl, a.key0, a.key1);
-        const uint32_t tw = (sl & 1) ? r.z : r.x;
-        const uint32_t ew = (sl & 1) ? r.w : r.y;
+        const StepWords wl = words_of_step<MOVING>(q, q.steps + (uint64_t)lane, a);
+        const uint32_t tw = wl.t;
+        const uint32_t ew = wl.e;
         uint32_t pk = 0u;
 #pragma unroll
         for (int b = 0; b < WB; ++b) {
@@ -402,14 +498,23 @@ __device__ void coop_walk(Packet1D &q, const uint8_t *__restrict__ tb, const Dev
         q.steps += (uint64_t)l;
         q.j = jj;
         if (special) {
+            // the step at l in lane 0 with the lane walk's arithmetic; then, if this block
+            // stopped early (spatial leaks dominate here), a run of single steps in lane 0
             const int b = jj - jw;
-            q.t += (double)path_length(rl(tw, l), __uint_as_float(rl(v_lk, b)));
-            const uint32_t e = rl(ew, l), dh = rl(v_dhi, b), sh = rl(v_shi, b);
+            const StepWords ws = {rl(tw, l), rl(ew, l), rl(wl.z, l), rl(wl.w, l)};
+            const uint4 rec = make_uint4(rl(v_lk, b), rl(v_dhi, b), rl(v_shi, b), rl(v_fhi, b));
             Packet1D s1 = q;
-            if (lane == 0) slow_step<MOVING>(s1, e, dh, sh, tb, clouds, a, tally);
+            if (lane == 0) {
+                const float4 cm = (MOVING && s1.moving) ? s1.cmap[s1.i] : make_float4(1.f, 0.f, 1.f, 0.f);
+                one_step<MOVING>(s1, ws, rec, cm, tb, clouds, a, tally);
+                if (l < 16) single_steps<MOVING>(s1, 256, tb, clouds, a, tally);
+            }
             q.i = (int)rl((uint32_t)s1.i, 0);
             q.j = (int)rl((uint32_t)s1.j, 0);
             q.steps = ((uint64_t)rl((uint32_t)(s1.steps >> 32), 0) << 32) | rl((uint32_t)s1.steps, 0);
+            const uint64_t tbits = (uint64_t)__double_as_longlong(s1.t);
+            q.t = __longlong_as_double((long long)(((uint64_t)rl((uint32_t)(tbits >> 32), 0) << 32) |
+                                                   rl((uint32_t)tbits, 0)));
             q.active = rl(s1.active ? 1u : 0u, 0) != 0u;
         }
     }
@@ -436,6 +541,7 @@ __global__ __launch_bounds__(64) void walk1d_coop(const uint8_t *__restrict__ tb
         q.cl = (int)rl(tk.cl, 0);
         const DevCloud &c = clouds[q.cl];
         q.pid = rl(tk.pid, 0);
+        q.key = c.stream;
         q.i = (int)rl((uint32_t)tk.i, 0);
         q.j = (int)rl((uint32_t)tk.j, 0);
         q.steps = ((uint64_t)rl((uint32_t)(tk.steps >> 32), 0) << 32) | rl((uint32_t)tk.steps, 0);
@@ -446,6 +552,12 @@ __global__ __launch_bounds__(64) void walk1d_coop(const uint8_t *__restrict__ tb
         q.nc = c.nc;
         q.geom = c.geometry;
         q.hot = reinterpret_cast<const uint4 *>(tb + c.off_hot);
+        q.cmap = reinterpret_cast<const float4 *>(tb + c.off_cmap);
+        q.x0 = c.x0;
+        q.dx = c.dx;
+        q.inv_dx = c.inv_dx;
+        q.uniform = c.uniform_bins != 0;
+        q.moving = c.moving != 0;
         q.active = true;
         coop_walk<MOVING>(q, tb, clouds, a, tally, lane);
     }

@@ -37,7 +37,7 @@ class Medium_t(C.Structure):
                 ("flags", C.c_uint32), ("faces", C.c_void_p * 3), ("bin_edges", C.c_void_p),
                 ("k0", C.c_void_p), ("temp", C.c_void_p), ("vel", C.c_void_p),
                 ("tau_threshold", C.c_double), ("f_mu", C.c_double), ("lambda_", C.c_double),
-                ("n_src", C.c_int32), ("reserved0", C.c_int32), ("src_pos", C.c_void_p),
+                ("n_src", C.c_int32), ("stream", C.c_uint32), ("src_pos", C.c_void_p),
                 ("src_x", C.c_void_p), ("n_packets", C.c_uint64)]
 
 
@@ -105,8 +105,10 @@ def _check(rc):
 class Batch:
     """ctypes view of a list of ``media.Medium`` (keeps the numpy inputs alive)."""
 
-    def __init__(self, meds: Sequence[_media.Medium], keep_rates: bool = False):
+    def __init__(self, meds: Sequence[_media.Medium], keep_rates: bool = False,
+                 streams: Optional[Sequence[int]] = None):
         self.meds = list(meds)
+        self.streams = list(range(len(self.meds))) if streams is None else [int(v) for v in streams]
         self._keep = []
         arr = (Medium_t * len(self.meds))()
         for i, m in enumerate(self.meds):
@@ -126,6 +128,7 @@ class Batch:
             s.f_mu = m.f_mu
             s.lambda_ = m.lam
             s.n_src = len(m.src_x)
+            s.stream = self.streams[i]
             s.src_pos = self._ptr(np.asarray(m.src_pos, dtype=np.float64).reshape(-1, 3))
             s.src_x = self._ptr(m.src_x)
             s.n_packets = int(m.n_packets)
@@ -233,11 +236,11 @@ def tally(b: Batch, d_tally, stream=None) -> List[CloudTally]:
     return res
 
 
-HOT_DTYPE = np.dtype([("ln2_over_K", "<f4"), ("d_hi", "<u4"), ("s_hi", "<u4"), ("spare", "<u4")])
+HOT_DTYPE = np.dtype([("ln2_over_K", "<f4"), ("d_hi", "<u4"), ("s_hi", "<u4"), ("f_hi", "<u4")])
 
 
 def read_tables(b: Batch, d_tables, cloud=0, want_rates=True, stream=None):
-    """FP64 k_ij, FP64 rates (if kept), hot records and the u64 thresholds D, S per state."""
+    """FP64 k_ij, FP64 rates (if kept), hot records and the u64 thresholds D, S, F per state."""
     lib = load()
     m = b.meds[cloud]
     ns = m.n_cells_total * m.n_bins
@@ -245,13 +248,14 @@ def read_tables(b: Batch, d_tables, cloud=0, want_rates=True, stream=None):
     k = np.zeros(ns)
     rates = np.zeros((ns, nf + 2)) if want_rates else None
     hot = np.zeros(ns, dtype=HOT_DTYPE)
-    lo = np.zeros((ns, 2), dtype=np.uint32)
+    lo = np.zeros((ns, 4), dtype=np.uint32)
     _check(lib.rddmc_read_tables(b.ref(), C.c_void_p(d_tables.data_ptr()), cloud, k.ctypes.data,
                                  rates.ctypes.data if want_rates else None, hot.ctypes.data,
                                  lo.ctypes.data, _stream(stream)))
     D = (hot["d_hi"].astype(np.uint64) << np.uint64(32)) | lo[:, 0].astype(np.uint64)
     S = (hot["s_hi"].astype(np.uint64) << np.uint64(32)) | lo[:, 1].astype(np.uint64)
-    return k, rates, hot, D, S
+    F = (hot["f_hi"].astype(np.uint64) << np.uint64(32)) | lo[:, 2].astype(np.uint64)
+    return k, rates, hot, D, S, F
 
 
 def philox_fill(k0, k1, c0, c1, c2, c3, n, d_out, stream=None):
@@ -262,11 +266,11 @@ def philox_fill(k0, k1, c0, c1, c2, c3, n, d_out, stream=None):
 class Problem:
     """Device buffers for one batch: tables, tallies and the work counter (torch tensors)."""
 
-    def __init__(self, meds, keep_rates=False, device="cuda", stream=None):
+    def __init__(self, meds, keep_rates=False, device="cuda", stream=None, streams=None):
         import torch
         if isinstance(meds, _media.Medium):
             meds = [meds]
-        self.batch = Batch(meds, keep_rates=keep_rates)
+        self.batch = Batch(meds, keep_rates=keep_rates, streams=streams)
         self.stream = stream
         self.tables = torch.empty(table_bytes(self.batch), dtype=torch.uint8, device=device)
         self.tallies = torch.empty(tally_bytes(self.batch) // 8, dtype=torch.int64, device=device)
@@ -283,6 +287,16 @@ class Problem:
 
     def run(self, **kw):
         transport(self.batch, self.tables, self.tallies, self.work, stream=self.stream, **kw)
+
+    def capture(self, **kw):
+        """Capture one rddmc_transport call (work-counter reset, lane walk, cooperative tail
+        walk) into a HIP graph; ``graph.replay()`` re-runs it on the current stream, adding to
+        the tallies.  The run parameters are fixed at capture time."""
+        import torch
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            transport(self.batch, self.tables, self.tallies, self.work, stream=None, **kw)
+        return g
 
     def results(self):
         return tally(self.batch, self.tallies, self.stream)

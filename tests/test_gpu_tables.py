@@ -35,7 +35,7 @@ def test_tables_match_oracle(name):
     m = CASES[name]
     print(f"[tables] {name} cells={m.n_cells} bins={m.n_bins}", flush=True)
     prob = rddmc.Problem(m, keep_rates=True)
-    k, rates, hot, D, S = prob.read_tables(0)
+    k, rates, hot, D, S, F = prob.read_tables(0)
     t = tb.build(m)
     nf = t.nf
     ns = t.nc * t.nb
@@ -55,12 +55,15 @@ def test_tables_match_oracle(name):
     np.testing.assert_allclose(p_dn, t.rate_dn.reshape(ns) / K, rtol=1e-6, atol=2.0 ** -52)
     np.testing.assert_allclose(p_up, t.rate_up.reshape(ns) / K, rtol=1e-6, atol=2.0 ** -52)
     assert np.all(D <= S) or np.all((S == 0) == (D == 0))
+    # face 0 gets [S, F): P(face 0) = (F - S) / 2^64 (exact integer difference)
+    p_f0 = (F - S).astype(np.float64) / two64
+    np.testing.assert_allclose(p_f0, t.rate_face.reshape(ns, nf)[:, 0] / K, rtol=1e-6, atol=2.0 ** -52)
 
 
 def test_static_table_symmetry_on_gpu():
     m = media.config_slab()
     prob = rddmc.Problem(m)
-    k, _, hot, D, S = prob.read_tables(0, want_rates=False)
+    k, _, hot, D, S, F = prob.read_tables(0, want_rates=False)
     k = k.reshape(64, 128)
     np.testing.assert_allclose(k, k[:, ::-1], rtol=1e-13)
     lk = hot["ln2_over_K"].reshape(64, 128)

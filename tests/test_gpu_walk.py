@@ -23,6 +23,9 @@ SMALL = {
     "sphere_outflow": media.sphere(1e3, 1e4, 8, 24, x_max=8.0, v_max=20.0),
     "slab_cold_odd_bins": media.slab(1e3, 1e2, 6, 15),
     "sphere_inflow_cold": media.sphere(3e3, 3e2, 10, 41, x_max=12.0, v_max=-6.0),
+    # wide bins: spatial leaks dominate (the fast spatial path and its fallbacks)
+    "slab_wide_bins": media.slab(2e3, 1e4, 24, 5, x_max=6.0),
+    "sphere_wide_bins_outflow": media.sphere(3e3, 1e3, 20, 7, x_max=8.0, v_max=10.0),
 }
 
 
@@ -150,7 +153,9 @@ def test_cooperative_tail_is_bit_identical_on_moving_media():
     """The cooperative tail walk (a wave advances one packet) must reproduce the lane walk bit
     for bit, including Doppler re-binning, lab-frame escapes and the step cap."""
     for m, cap in ((SMALL["sphere_outflow"].with_packets(3000), 1 << 62),
-                   (SMALL["sphere_inflow_cold"].with_packets(3000), 5000)):
+                   (SMALL["sphere_inflow_cold"].with_packets(3000), 5000),
+                   (SMALL["slab_wide_bins"].with_packets(3000), 1 << 62),
+                   (SMALL["sphere_wide_bins_outflow"].with_packets(3000), 1 << 62)):
         a = _run(m, seed=21, tail_lanes=-1, max_steps=cap)[1]
         b = _run(m, seed=21, tail_lanes=64, max_steps=cap)[1]
         np.testing.assert_array_equal(a.spectrum, b.spectrum)
