@@ -15,8 +15,9 @@ moments of the escape time are solutions of sparse linear systems:
 With bulk velocity a spatial move draws x uniformly in the bin, maps it to the
 neighbour's frame (Sec. 2.5) and re-bins it; the exact transition weights are
 the overlaps of the shifted bin with the neighbour's bins (parts outside the
-grid go to the edge bins).  An escaping packet's lab-frame frequency is
-x + mu u_n with x uniform in its bin and mu uniform in (0, 1].
+grid go to the edge bins).  An escaping packet's lab-frame frequency is x + n.u with x
+uniform in its bin and n an isotropic outward direction (mu uniform in (0, 1]); in 1D
+geometries the velocity is normal to the faces and this is x + mu u_n.
 """
 from __future__ import annotations
 
@@ -126,6 +127,30 @@ def lab_bin_probs(edges, lo, hi, u):
     return out
 
 
+def lab_bin_probs_3d(edges, lo, hi, u_n, u_t, n_mu=64, n_phi=64):
+    """P(x + n.u in lab bin b) for x ~ U[lo, hi] and an isotropic outward direction n
+    (mu = n.n_face uniform in (0, 1], azimuth uniform): the shift is
+    mu u_n + sqrt(1 - mu^2) u_t cos(phi).  Gauss-Legendre in mu, trapezoid (periodic,
+    spectrally accurate) in phi."""
+    if u_t == 0.0:
+        return lab_bin_probs(edges, lo, hi, u_n)
+    nb = len(edges) - 1
+    gx, gw = np.polynomial.legendre.leggauss(n_mu)
+    mu = 0.5 * (gx + 1.0)
+    wmu = 0.5 * gw
+    phi = 2.0 * np.pi * (np.arange(n_phi) + 0.5) / n_phi
+    shift = (mu[:, None] * u_n + np.sqrt(1.0 - mu[:, None] ** 2) * u_t * np.cos(phi[None, :])).ravel()
+    wts = (wmu[:, None] * np.full(n_phi, 1.0 / n_phi)[None, :]).ravel()
+    a = lo + shift
+    b = hi + shift
+    y = np.asarray(edges)
+    cdf = np.clip((y[None, :] - a[:, None]) / (b - a)[:, None], 0.0, 1.0)   # (nodes, nb+1)
+    # per-node slot masses (each >= 0, exactly 0 outside the node's support), then the
+    # weighted mean: no cancellation between cumulative sums
+    slots = np.concatenate([cdf[:, :1], np.diff(cdf, axis=1), 1.0 - cdf[:, -1:]], axis=1)
+    return (wts @ slots) / wts.sum()
+
+
 def solve(m, tabs=None) -> ChainResult:
     """Exact expected results of pure DDMC on medium ``m``."""
     t = tabs if tabs is not None else tb.build(m)
@@ -160,7 +185,8 @@ def solve(m, tabs=None) -> ChainResult:
             rows.append(src_s)
             cols.append(dst_s)
             vals.append(r[mask])
-        vac_static = (t.nbr[:, f] == tb.NBR_VACUUM) & ((t.u_n[:, f] == 0.0) | (not t.moving))
+        vac_static = (t.nbr[:, f] == tb.NBR_VACUUM) & (((t.u_n[:, f] == 0.0) & (t.u_t[:, f] == 0.0))
+                                                       | (not t.moving))
         if np.any(vac_static):
             cs = np.nonzero(vac_static)[0]
             jj = np.arange(nb)
@@ -175,10 +201,11 @@ def solve(m, tabs=None) -> ChainResult:
                 continue
             if n == tb.NBR_VACUUM:
                 u = t.u_n[c, f] if t.moving else 0.0
+                ut = t.u_t[c, f] if t.moving else 0.0
                 for j in range(nb):
                     if r[j] <= 0:
                         continue
-                    pb = lab_bin_probs(edges, lo_e[j], hi_e[j], u)
+                    pb = lab_bin_probs_3d(edges, lo_e[j], hi_e[j], u, ut)
                     nzb = np.nonzero(pb)[0]
                     es.append(np.full(len(nzb), c * nb + j))
                     ef.append(np.full(len(nzb), face_row[f]))

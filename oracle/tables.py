@@ -57,6 +57,7 @@ class Tables:
     rho: np.ndarray          # (nc, nf)
     shift: np.ndarray        # (nc, nf)
     u_n: np.ndarray          # (nc, nf) outward normal velocity / v_th(T_c) (all faces)
+    u_t: np.ndarray          # (nc, nf) tangential speed / v_th(T_c) (3D; zero in 1D)
     width: np.ndarray        # (nc, nf) width of the cell across each face
     moving: bool
 
@@ -161,6 +162,12 @@ def build(m, f_mu: Optional[float] = None) -> Tables:
         dvn = np.where(has, vn[idx, f] - vn[:, f], 0.0)
         shift[:, f] = np.where(has, -fmu * dvn / vth[idx], 0.0)
     u_n = vn / vth[:, None]
+    u_t = np.zeros((nc, nf))
+    if moving and m.geometry == CART3D:
+        v = np.asarray(m.vel, dtype=np.float64).reshape(nc, 3)
+        sp2 = (v * v).sum(axis=1)
+        for f in range(nf):
+            u_t[:, f] = np.sqrt(np.maximum(sp2 - v[:, f >> 1] ** 2, 0.0)) / vth
 
     rate_face = np.zeros((nc, nb, nf))
     face_is_mc = np.zeros((nc, nb, nf), dtype=bool)
@@ -216,7 +223,7 @@ def build(m, f_mu: Optional[float] = None) -> Tables:
 
     return Tables(geometry=m.geometry, nc=nc, nb=nb, nf=nf, bin_edges=edges, k=k, tau=tau,
                   thick=thick, rate_face=rate_face, face_is_mc=face_is_mc, rate_dn=rate_dn,
-                  rate_up=rate_up, nbr=nbr, rho=rho, shift=shift, u_n=u_n, width=width,
+                  rate_up=rate_up, nbr=nbr, rho=rho, shift=shift, u_n=u_n, u_t=u_t, width=width,
                   moving=bool(moving))
 
 

@@ -1,0 +1,119 @@
+"""Pins of the 3D hybrid oracle walker (O1-3D): its own Dawson/Voigt, the atom-velocity
+sampler, the interface conversion probability, continuous-MC geometry and opacity against
+independent quadratures, and pure-DDMC runs against the exact chain."""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate, special
+
+from oracle import chain, linemath, walk3d
+from paper_1709_10187_amd import media
+from tests._stats import assert_spectrum_matches, compare_exact
+
+
+def test_own_dawson_and_voigt():
+    xs = np.concatenate([np.linspace(-30, 30, 301), [1e-4, 0.2, 5.999, 6.0, 6.001, 80.0, 1e4]])
+    for x in xs:
+        if x == 0:
+            continue
+        assert walk3d.dawson(x) == pytest.approx(special.dawsn(x), rel=1e-13)
+        assert walk3d.voigt(4.702e-4, x) == pytest.approx(float(linemath.voigt_H(4.702e-4, x)), rel=1e-11,
+                                                          abs=1e-300)
+
+
+@pytest.mark.parametrize("a,x", [(4.702e-4, 0.0), (4.702e-4, 1.7), (4.702e-4, 3.0), (4.702e-4, -6.0),
+                                 (1.4869e-2, 2.2), (4.702e-4, 25.0)])
+def test_atom_velocity_sampler_matches_density(a, x):
+    """u_par ~ exp(-u^2) / (a^2 + (x - u)^2) (the parallel atom velocity of a scattering at
+    frequency x; the paper's density without its missing minus sign)."""
+    n = 200000
+    smp = walk3d.upar_samples(a, x, n, seed=11)
+    f = lambda u: math.exp(-u * u) / (a * a + (x - u) ** 2)
+    lo, hi = np.percentile(smp, [0.5, 99.5])
+    edges = np.linspace(lo, hi, 31)
+    cnt, _ = np.histogram(smp, edges)
+    Z = integrate.quad(f, -20, 20 + abs(x), points=[x], limit=800)[0]
+    p = np.array([integrate.quad(f, edges[i], edges[i + 1], limit=200,
+                                 points=[x] if edges[i] < x < edges[i + 1] else None)[0] for i in range(30)]) / Z
+    z = (cnt / n - p) / np.sqrt(p * (1 - p) / n)
+    assert np.sum(np.abs(z) > 3) <= 2 and np.abs(z).max() < 5
+
+
+def test_interface_conversion_probability_needs_tau_at_least_two():
+    """P = 2/(tau + 2 lambda) (2/3 + mu) <= 1 for every mu in (0, 1] iff tau >= 10/3 - 2 lambda
+    (~1.91), the hybrid section's 'tau_DDMC >~ 2' condition."""
+    lam = 0.7104
+    P = lambda tau, mu: 2.0 / (tau + 2 * lam) * (2.0 / 3.0 + mu)
+    assert P(2.0, 1.0) <= 1.0 and P(1.85, 1.0) > 1.0
+    assert abs((10.0 / 3.0 - 2 * lam) - 1.9125) < 1e-3
+
+
+def _uniform_cube(n, tau_cell, nb=8, dv=25.0, tau_th=1e30, packets=20000):
+    m = media.cube(n=n, seed=1, mean_tau_cell=tau_cell, sigma_ln=1e-9, sigma_v=0.0, n_bins=nb + 1, dv_bin=dv,
+                   tau_threshold=tau_th, n_sources=1, packets_per_source=packets)
+    c = n // 2
+    return m.replace(k0=np.full(n ** 3, float(tau_cell)), vel=None, src_pos=np.array([[c + 0.5] * 3]))
+
+
+def test_free_streaming_escape_time():
+    """Optically thin cube, all-MC (tau_th huge): packets fly straight from the centre; the mean
+    escape time is (L/2) E[1 / max_i |n_i|] over isotropic n (independent quadrature)."""
+    n = 5
+    m = _uniform_cube(n, 1e-7, packets=40000)
+    r = walk3d.run(m, seed=3)
+    assert r.escaped == 40000 and r.reflected == 0
+    f = lambda th, ph: 1.0 / max(abs(math.sin(th) * math.cos(ph)), abs(math.sin(th) * math.sin(ph)),
+                                 abs(math.cos(th))) * math.sin(th) / (4 * math.pi)
+    E, _ = integrate.dblquad(lambda th, ph: f(th, ph), 0, 2 * math.pi, 0, math.pi, epsabs=1e-7)
+    ref = 0.5 * n * E
+    assert r.t_mean == pytest.approx(ref, rel=4 * (0.3 / math.sqrt(40000)) + 1e-3)
+    # no scattering: the escape spectrum is the source line, all in the central bin
+    assert r.spectrum.sum(axis=0)[1 + 4] == 40000
+
+
+def test_unscattered_escape_fraction():
+    """P(no scattering before escape) = E[exp(-k0 H(a,0) d(n))] from the centre of a uniform
+    cube: checks the MC opacity k0 H(a,x) and the exponential path sampling."""
+    n = 1                      # one cell: the first event is a scattering or the escape
+    tau = 0.4
+    m = _uniform_cube(n, tau, packets=100000)
+    r = walk3d.run(m, seed=5, max_steps=1)
+    k = tau * float(linemath.voigt_H(float(linemath.damping(1e4)), 0.0))
+
+    def d(th, ph):
+        nn = (abs(math.sin(th) * math.cos(ph)), abs(math.sin(th) * math.sin(ph)), abs(math.cos(th)))
+        return 0.5 * n / max(nn)
+
+    P, _ = integrate.dblquad(lambda th, ph: math.exp(-k * d(th, ph)) * math.sin(th) / (4 * math.pi),
+                             0, 2 * math.pi, 0, math.pi, epsabs=1e-8)
+    frac = r.escaped / 100000
+    assert abs(frac - P) < 4 * math.sqrt(P * (1 - P) / 100000)
+
+
+def test_pure_ddmc_cube_matches_exact_chain():
+    m = media.cube(n=5, seed=7, mean_tau_cell=300.0, n_bins=16, dv_bin=25.0, tau_threshold=0.0, n_sources=2,
+                   packets_per_source=30000)
+    r = walk3d.run(m, seed=1)
+    c = chain.solve(m)
+    res = compare_exact(r.spectrum, c.spectrum, r.n_packets)
+    assert_spectrum_matches(res)
+    assert abs(r.steps_mean - c.steps) < 4 * math.sqrt(c.steps_var / r.n_packets)
+    assert abs(r.t_mean - c.t_mean) < 4 * math.sqrt(c.t_var / r.n_packets)
+    assert r.to_mc == 0 and r.pixels.sum() == r.n_packets
+
+
+def test_lab_escape_law_quadrature_against_sampling():
+    rng = np.random.default_rng(1)
+    n = 1_000_000
+    e = np.linspace(-5, 5, 21)
+    lo, hi, un, ut = 0.0, 0.5, 0.7, 1.3
+    x = rng.uniform(lo, hi, n)
+    mu = rng.uniform(0, 1, n)
+    ph = rng.uniform(0, 2 * np.pi, n)
+    xl = x + mu * un + np.sqrt(1 - mu * mu) * ut * np.cos(ph)
+    cnt = np.bincount(np.clip(np.searchsorted(e, xl, side="right"), 0, 21), minlength=22) / n
+    p = chain.lab_bin_probs_3d(e, lo, hi, un, ut)
+    assert p.sum() == pytest.approx(1.0, abs=1e-12)
+    assert np.all(p >= 0.0)
+    assert np.all(np.abs(cnt - p) < 5 * np.sqrt(p * (1 - p) / n) + 1e-6)
