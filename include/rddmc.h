@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define RDDMC_ABI_VERSION 1
+#define RDDMC_ABI_VERSION 2
 
 typedef enum {
     RDDMC_OK = 0,
@@ -152,6 +152,12 @@ typedef struct {
     double   t_var;          /* variance of the escape time                              */
     int32_t  n_rows;         /* spectrum rows (escape faces): slab 2, sphere 1, 3D 6     */
     int32_t  n_slots;        /* n_bins + 2 (slot 0 below the grid, slot n_bins+1 above) */
+    uint64_t to_mc;          /* hybrid (3D): DDMC -> continuous-MC conversions            */
+    uint64_t to_ddmc;        /* hybrid (3D): continuous-MC -> DDMC conversions            */
+    uint64_t reflected;      /* hybrid (3D): MC packets reflected at a thick interface    */
+    uint64_t mc_steps;       /* hybrid (3D): MC events (scatterings and face crossings),  */
+                             /* included in steps_total                                  */
+    uint64_t n_pix;          /* 3D: escape pixels 2 (ny nz + nx nz + nx ny); else 0       */
 } rddmc_cloud_stats;
 
 /*
@@ -159,7 +165,11 @@ typedef struct {
  *   spectrum[c]   int64 [n_rows * (n_bins + 2)] escape counts per face row and lab slot,
  *   time_hist[c]  int64 [RDDMC_TIME_BINS + 2],
  *   step_hist[c]  int64 [RDDMC_STEP_BINS],
- *   stats[c].
+ *   stats[c],
+ *   pixels[c]     (3D) int64 [n_pix] escape counts per boundary cell: for face f (0 = -x,
+ *                 1 = +x, 2 = -y, 3 = +y, 4 = -z, 5 = +z) a block of the face's cells, blocks
+ *                 in face order; x faces index iz*ny + iy, y faces iz*nx + ix, z faces
+ *                 iy*nx + ix.
  * Any pointer array may be NULL to skip that output.
  */
 typedef struct {
@@ -167,6 +177,7 @@ typedef struct {
     int64_t **time_hist;
     int64_t **step_hist;
     rddmc_cloud_stats *stats;
+    int64_t **pixels;
 } rddmc_tally_out;
 
 /* ---- queries ------------------------------------------------------------------------- */

@@ -71,6 +71,7 @@ typedef struct {
     int64_t *step_hist;    /* [O3_STEP_BINS] */
     double t_sum, t2_sum, steps_sum, mc_steps_sum;
     int64_t escaped, capped, to_mc, to_ddmc, reflected;
+    double steps2_sum, mc_steps2_sum;
 } o3_result;
 
 /* ---- RNG ------------------------------------------------------------------------- */
@@ -417,6 +418,8 @@ static void walk_packet(const o3_problem *p, uint64_t id, uint64_t seed, uint64_
     }
     R->steps_sum += (double)steps;
     R->mc_steps_sum += (double)mcsteps;
+    R->steps2_sum += (double)steps * (double)steps;
+    R->mc_steps2_sum += (double)mcsteps * (double)mcsteps;
     R->step_hist[step_bin(steps ? steps : 1)]++;
 }
 
@@ -447,6 +450,7 @@ static void *worker(void *arg)
     R->t_sum += L.t_sum; R->t2_sum += L.t2_sum; R->steps_sum += L.steps_sum; R->mc_steps_sum += L.mc_steps_sum;
     R->escaped += L.escaped; R->capped += L.capped; R->to_mc += L.to_mc; R->to_ddmc += L.to_ddmc;
     R->reflected += L.reflected;
+    R->steps2_sum += L.steps2_sum; R->mc_steps2_sum += L.mc_steps2_sum;
     pthread_mutex_unlock(jb->lock);
     free(L.spectrum); free(L.pixels); free(L.time_hist); free(L.step_hist);
     return NULL;

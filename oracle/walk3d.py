@@ -40,7 +40,7 @@ class _Result(C.Structure):
                 ("step_hist", C.c_void_p), ("t_sum", C.c_double), ("t2_sum", C.c_double),
                 ("steps_sum", C.c_double), ("mc_steps_sum", C.c_double), ("escaped", C.c_int64),
                 ("capped", C.c_int64), ("to_mc", C.c_int64), ("to_ddmc", C.c_int64),
-                ("reflected", C.c_int64)]
+                ("reflected", C.c_int64), ("steps2_sum", C.c_double), ("mc_steps2_sum", C.c_double)]
 
 
 _lib = None
@@ -94,6 +94,8 @@ class Walk3DResult:
     to_ddmc: int
     reflected: int
     n_packets: int
+    steps2_sum: float = 0.0
+    mc_steps2_sum: float = 0.0
 
     @property
     def t_mean(self):
@@ -102,6 +104,22 @@ class Walk3DResult:
     @property
     def steps_mean(self):
         return self.steps_sum / max(self.n_packets, 1)
+
+    @property
+    def steps_var(self):
+        return self.steps2_sum / max(self.n_packets, 1) - self.steps_mean ** 2
+
+    @property
+    def mc_steps_mean(self):
+        return self.mc_steps_sum / max(self.n_packets, 1)
+
+    @property
+    def mc_steps_var(self):
+        return self.mc_steps2_sum / max(self.n_packets, 1) - self.mc_steps_mean ** 2
+
+    @property
+    def t_var(self):
+        return self.t2_sum / max(self.escaped, 1) - self.t_mean ** 2
 
 
 def run(m, n_packets=None, seed=0, first_id=0, max_steps=(1 << 62), n_threads=None, tabs=None):
@@ -146,9 +164,9 @@ def run(m, n_packets=None, seed=0, first_id=0, max_steps=(1 << 62), n_threads=No
     th = np.zeros(TIME_BINS + 2, dtype=np.int64)
     sh = np.zeros(STEP_BINS, dtype=np.int64)
     R = _Result(spec.ctypes.data, pix.ctypes.data, th.ctypes.data, sh.ctypes.data, 0.0, 0.0, 0.0, 0.0,
-                0, 0, 0, 0, 0)
+                0, 0, 0, 0, 0, 0.0, 0.0)
     rc = lib.o3_run(C.byref(P), first_id, n, seed, max_steps, n_threads or os.cpu_count() or 1, C.byref(R))
     if rc != 0:
         raise RuntimeError("o3_run failed")
     return Walk3DResult(spec, pix, th, sh, R.t_sum, R.t2_sum, R.steps_sum, R.mc_steps_sum, R.escaped,
-                        R.capped, R.to_mc, R.to_ddmc, R.reflected, n)
+                        R.capped, R.to_mc, R.to_ddmc, R.reflected, n, R.steps2_sum, R.mc_steps2_sum)

@@ -6,7 +6,9 @@
 //                outward normal velocity u_n (in thermal units) for escapes;
 //   build_k    : per state the tophat bin-averaged opacity k_ij (eq. 14);
 //   build_rates: per state the face and frequency leakage rates, packed into the
-//                16-byte hot record and the face-split thresholds.
+//                16-byte hot record and the face-split thresholds;
+//   build_mcell: (3D) per cell the FP32 record of the continuous-MC step;
+// and, once per buffer of a 3D batch, the FP32 Voigt and sampler tables of the MC step.
 #include <hip/hip_runtime.h>
 
 #include "linemath_dev.h"
@@ -166,10 +168,28 @@ __global__ void build_rates(DevCloud c, uint8_t *tb, uint32_t *err)
     const double lo = e[j], hi = e[j + 1], dx = hi - lo;
     const double ks = kk[s];
     const bool hybrid = c.tau_th > 0.0;
-    if (hybrid && ks * min_width(c, tb, cell) < c.tau_th) atomicOr(err, (uint32_t)BE_THIN);
+    const bool cart = c.geometry == RDDMC_CART3D;
+    const bool thick = !hybrid || ks * min_width(c, tb, cell) >= c.tau_th;
+    if (!thick) {
+        if (!cart) {   // the 1D walk is pure DDMC
+            atomicOr(err, (uint32_t)BE_THIN);
+            return;
+        }
+        // a continuous-MC state: no DDMC rates, flags = 0 (not thick)
+        reinterpret_cast<HotRecord *>(tb + c.off_hot)[s] = HotRecord{0.0f, 0u, 0u, 0u};
+        reinterpret_cast<uint4 *>(tb + c.off_lo_words)[s] = make_uint4(0u, 0u, 0u, 0u);
+        uint32_t *fs = reinterpret_cast<uint32_t *>(tb + c.off_face_split) + s * (nf - 1);
+        for (int f = 0; f < nf - 1; ++f) fs[f] = 0u;
+        if (c.keep_rates) {
+            double *rr = reinterpret_cast<double *>(tb + c.off_rates) + s * (nf + 2);
+            for (int f = 0; f < nf + 2; ++f) rr[f] = 0.0;
+        }
+        return;
+    }
 
     double rf[kMaxFaces];
     double rs = 0.0;
+    uint32_t iface = 0u;     // faces whose leak enters a thin state or vacuum
     for (int f = 0; f < nf; ++f) {
         const FaceGeom g = face_geom(c, tb, cell, f);
         const double kw = ks * g.width;
@@ -179,6 +199,7 @@ __global__ void build_rates(DevCloud c, uint8_t *tb, uint32_t *err)
         } else if (g.nbr == -1) {
             r = c.dirichlet ? g.area_over_vol * 2.0 / (3.0 * kw)
                             : g.area_over_vol * 2.0 / (3.0 * (kw + 2.0 * c.lambda));
+            iface |= 1u << f;
         } else {
             const double rho = map[3 * (cell * nf + f)];
             const double sh = map[3 * (cell * nf + f) + 1];
@@ -194,6 +215,7 @@ __global__ void build_rates(DevCloud c, uint8_t *tb, uint32_t *err)
             const bool nb_thick = !hybrid || kn * min_width(c, tb, g.nbr) >= c.tau_th;
             r = nb_thick ? g.area_over_vol * 2.0 / (3.0 * (kw + kn * gn.width))      // eq. 10
                          : g.area_over_vol * 2.0 / (3.0 * (kw + 2.0 * c.lambda));
+            if (!nb_thick) iface |= 1u << f;
         }
         rf[f] = r;
         rs += r;
@@ -220,7 +242,7 @@ __global__ void build_rates(DevCloud c, uint8_t *tb, uint32_t *err)
     } else {
         if (Tsp == 0ull) Tsp = 1ull;                // keep the spatial leak reachable
         S = 0ull - Tsp;                             // 2^64 - Tsp
-        if (S < D) S = D;
+        if (S < D || ru <= 0.0) S = D;              // no upper move from the last bin, even by rounding
     }
     // face 1 gets [F, 2^64); saturate if rounding leaves it less than nothing
     uint64_t F = S + prob_to_u64(rf[0] / K);
@@ -229,12 +251,18 @@ __global__ void build_rates(DevCloud c, uint8_t *tb, uint32_t *err)
     h.ln2_over_K = (float)(0.69314718055994530942 / K);
     h.d_hi = (uint32_t)(D >> 32);
     h.s_hi = (uint32_t)(S >> 32);
-    h.f_hi = (uint32_t)(F >> 32);
+    uint32_t flags = kFlagThick | (iface << kFlagFaceShift);
+    if (cart && hybrid) {
+        const double wmin = min_width(c, tb, cell);
+        if (j > 0 && kk[s - 1] * wmin < c.tau_th) flags |= kFlagDnThin;
+        if (j < nb - 1 && kk[s + 1] * wmin < c.tau_th) flags |= kFlagUpThin;
+    }
+    h.f_hi = cart ? flags : (uint32_t)(F >> 32);
     reinterpret_cast<HotRecord *>(tb + c.off_hot)[s] = h;
     uint32_t *lw = reinterpret_cast<uint32_t *>(tb + c.off_lo_words) + 4 * s;
     lw[0] = (uint32_t)D;
     lw[1] = (uint32_t)S;
-    lw[2] = (uint32_t)F;
+    lw[2] = cart ? 0u : (uint32_t)F;
     lw[3] = 0u;
 
     // cumulative face split: thresholds for faces 0 .. nf-2
@@ -250,6 +278,64 @@ __global__ void build_rates(DevCloud c, uint8_t *tb, uint32_t *err)
         rr[nf] = rd;
         rr[nf + 1] = ru;
     }
+}
+
+// Per-cell FP32 record of the continuous-MC step (3D): {k0, a, sqrt(T), w_min} and the bulk
+// velocity in units of the cell's own thermal speed.
+__global__ void build_mcell(DevCloud c, uint8_t *tb)
+{
+    const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= (int64_t)c.nc) return;
+    const double T = f64p(tb, c.off_T)[cell];
+    const double vth = vth_dev(T);
+    float4 *mc = reinterpret_cast<float4 *>(tb + c.off_mcell) + 2 * cell;
+    mc[0] = make_float4((float)f64p(tb, c.off_k0)[cell], (float)damping_dev(T), (float)sqrt(T),
+                        (float)min_width(c, tb, cell));
+    float4 u = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (c.moving) {
+        const double *v = f64p(tb, c.off_vel) + 3 * cell;
+        u = make_float4((float)(v[0] / vth), (float)(v[1] / vth), (float)(v[2] / vth), 0.f);
+    }
+    mc[1] = u;
+}
+
+// H1(x) = (2/sqrt(pi)) (2 x F(x) - 1), the first-order term of eq. 12 in a, on x = i/256.
+__global__ void build_voigt_table(float *out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kVoigtN) return;
+    const double x = (double)i / (double)kVoigtScale;
+    out[i] = (float)(1.12837916709551257390 * (2.0 * x * dawson_dev(x) - 1.0));
+}
+
+// Proposal mass of the atom-velocity sampler split at u0 (times pi/a): the Lorentzian
+// centred on |x| below u0 plus exp(-u0^2) times the Lorentzian above u0.
+__device__ double split_mass(double a, double ax, double u0)
+{
+    const double th = atan((u0 - ax) / a);
+    return (1.57079632679489661923 + th) + exp(-u0 * u0) * (1.57079632679489661923 - th);
+}
+
+// Split point minimising the proposal mass over [0, |x|] (golden-section search).
+__global__ void build_u0_table(float *out)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= kU0NA * kU0NX) return;
+    const int ia = t / kU0NX, ix = t % kU0NX;
+    const double a = pow(10.0, -6.0 + ia / (double)kU0Scale);
+    const double ax = ix / (double)kU0Scale;
+    const double g = 0.61803398874989484820;
+    double lo = 0.0, hi = ax;
+    double c1 = hi - g * (hi - lo), c2 = lo + g * (hi - lo);
+    double f1 = split_mass(a, ax, c1), f2 = split_mass(a, ax, c2);
+    for (int it = 0; it < 60; ++it) {
+        if (f1 < f2) {
+            hi = c2; c2 = c1; f2 = f1; c1 = hi - g * (hi - lo); f1 = split_mass(a, ax, c1);
+        } else {
+            lo = c1; c1 = c2; f1 = f2; c2 = lo + g * (hi - lo); f2 = split_mass(a, ax, c2);
+        }
+    }
+    out[t] = (float)(0.5 * (lo + hi));
 }
 
 __global__ void zero_words(unsigned long long *d, size_t n)
@@ -272,6 +358,16 @@ hipError_t launch_build(const DevCloud &c, int cloud_index, uint8_t *d_tables, h
     const unsigned g = (unsigned)((ns + bs - 1) / bs);
     build_k<<<g, bs, 0, s>>>(c, d_tables, err);
     build_rates<<<g, bs, 0, s>>>(c, d_tables, err);
+    if (c.geometry == RDDMC_CART3D)
+        build_mcell<<<(unsigned)((c.nc + bs - 1) / bs), bs, 0, s>>>(c, d_tables);
+    return hipGetLastError();
+}
+
+hipError_t launch_build_line_tables(const DevHeader &h, uint8_t *d_tables, hipStream_t s)
+{
+    if (h.off_voigt == 0) return hipSuccess;
+    build_voigt_table<<<(kVoigtN + 255) / 256, 256, 0, s>>>(reinterpret_cast<float *>(d_tables + h.off_voigt));
+    build_u0_table<<<(kU0NA * kU0NX + 255) / 256, 256, 0, s>>>(reinterpret_cast<float *>(d_tables + h.off_u0));
     return hipGetLastError();
 }
 

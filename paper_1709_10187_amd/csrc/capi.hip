@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <climits>
 #include <cstring>
 #include <map>
 #include <string>
@@ -83,6 +84,7 @@ struct Layout {
     std::vector<uint64_t> prefix;
     std::vector<std::vector<int32_t>> src_state;
     std::vector<std::vector<double>> src_cdf;
+    std::vector<std::vector<float>> src_pos;     // 3D: {x, y, z, frequency} per emission entry
     uint64_t table_bytes = 0;
     uint64_t tally_words = 0;
     bool any_moving = false;
@@ -135,6 +137,7 @@ rddmc_status make_layout(const rddmc_batch *b, Layout &L)
     L.prefix.assign(n + 1, 0);
     L.src_state.assign(n, {});
     L.src_cdf.assign(n, {});
+    L.src_pos.assign(n, {});
     const int geom = b->clouds[0].geometry;
     uint64_t off = 0;
     L.h.n_clouds = n;
@@ -144,13 +147,18 @@ rddmc_status make_layout(const rddmc_batch *b, Layout &L)
     off = align_up(off + sizeof(DevCloud) * n);
     L.h.off_prefix = off;
     off = align_up(off + sizeof(uint64_t) * (n + 1));
+    if (geom == RDDMC_CART3D) {   // FP32 line tables of the continuous-MC step
+        L.h.off_voigt = off;
+        off = align_up(off + 4ull * kVoigtN);
+        L.h.off_u0 = off;
+        off = align_up(off + 4ull * kU0NA * kU0NX);
+    }
     uint64_t tally = 0;
     for (int ci = 0; ci < n; ++ci) {
         const rddmc_medium &m = b->clouds[ci];
         rddmc_status st = validate_cloud(m, ci);
         if (st != RDDMC_OK) return st;
         if (m.geometry != geom) return fail(RDDMC_EUNSUPPORTED, "mixed geometries in one batch");
-        if (m.geometry == RDDMC_CART3D) return fail(RDDMC_EUNSUPPORTED, "3D Cartesian transport is not built yet");
         DevCloud &c = L.clouds[ci];
         c.geometry = m.geometry;
         c.nb = m.n_bins;
@@ -187,24 +195,46 @@ rddmc_status make_layout(const rddmc_batch *b, Layout &L)
         }
         c.f_mu = m.f_mu;
         c.lambda = m.lambda;
-        // sources -> (state, probability)
+        // sources -> (state, probability); 3D keeps one entry per (source, state) with the
+        // source's position and frequency (a packet starting in a thin state needs them)
         std::map<int32_t, double> acc;
         std::vector<std::pair<int, double>> bins, cx, cy, cz;
+        double cum3 = 0.0;
         for (int s = 0; s < m.n_src; ++s) {
             if (!split_coord(m.bin_edges, m.n_bins, m.src_x[s], bins))
                 return fail(RDDMC_EINVAL, "cloud %d: source %d frequency outside the grid", ci, s);
             const double *p = m.src_pos + 3 * s;
             if (!split_coord(m.faces[0], m.n_cells[0], p[0], cx))
                 return fail(RDDMC_EINVAL, "cloud %d: source %d outside the grid", ci, s);
-            for (auto &a : cx)
-                for (auto &bb : bins)
-                    acc[a.first * m.n_bins + bb.first] += a.second * bb.second / m.n_src;
+            if (m.geometry != RDDMC_CART3D) {
+                for (auto &a : cx)
+                    for (auto &bb : bins)
+                        acc[a.first * m.n_bins + bb.first] += a.second * bb.second / m.n_src;
+                continue;
+            }
+            if (!split_coord(m.faces[1], m.n_cells[1], p[1], cy) || !split_coord(m.faces[2], m.n_cells[2], p[2], cz))
+                return fail(RDDMC_EINVAL, "cloud %d: source %d outside the grid", ci, s);
+            for (auto &ax : cx)
+                for (auto &ay : cy)
+                    for (auto &az : cz)
+                        for (auto &bb : bins) {
+                            const int64_t cell = ((int64_t)az.first * m.n_cells[1] + ay.first) * m.n_cells[0] + ax.first;
+                            const int64_t st = cell * m.n_bins + bb.first;
+                            if (st > INT32_MAX) return fail(RDDMC_ESIZE, "cloud %d: source state index >= 2^31", ci);
+                            cum3 += ax.second * ay.second * az.second * bb.second / m.n_src;
+                            L.src_state[ci].push_back((int32_t)st);
+                            L.src_cdf[ci].push_back(cum3);
+                            for (int d = 0; d < 3; ++d) L.src_pos[ci].push_back((float)p[d]);
+                            L.src_pos[ci].push_back((float)m.src_x[s]);
+                        }
         }
-        double cum = 0.0;
-        for (auto &kv : acc) {
-            cum += kv.second;
-            L.src_state[ci].push_back(kv.first);
-            L.src_cdf[ci].push_back(cum);
+        if (m.geometry != RDDMC_CART3D) {
+            double cum = 0.0;
+            for (auto &kv : acc) {
+                cum += kv.second;
+                L.src_state[ci].push_back(kv.first);
+                L.src_cdf[ci].push_back(cum);
+            }
         }
         L.src_cdf[ci].back() = 1.0;
         c.n_src = (int32_t)L.src_state[ci].size();
@@ -221,6 +251,7 @@ rddmc_status make_layout(const rddmc_batch *b, Layout &L)
         c.off_vel = take(8ull * c.nc * (m.geometry == RDDMC_CART3D ? 3 : 1));
         c.off_src_state = take(4ull * c.n_src);
         c.off_src_cdf = take(8ull * c.n_src);
+        c.off_src_pos = take(16ull * c.n_src);
         c.off_k = take(8ull * c.n_states);
         c.off_hot = take(sizeof(HotRecord) * c.n_states);
         c.off_lo_words = take(16ull * c.n_states);
@@ -228,8 +259,13 @@ rddmc_status make_layout(const rddmc_batch *b, Layout &L)
         c.off_rates = c.keep_rates ? take(8ull * c.n_states * (c.nf + 2)) : 0;
         c.off_map = take(8ull * 3 * c.nc * c.nf);
         c.off_cmap = take(16ull * c.nc);
+        c.off_mcell = m.geometry == RDDMC_CART3D ? take(32ull * c.nc) : 0;
+        c.n_pix = m.geometry == RDDMC_CART3D
+                      ? 2ull * ((uint64_t)c.n[1] * c.n[2] + (uint64_t)c.n[0] * c.n[2] + (uint64_t)c.n[0] * c.n[1])
+                      : 0;
         c.tally_off = tally;
-        c.tally_words = kTallyHeader + (uint64_t)c.n_rows * (c.nb + 2) + (RDDMC_TIME_BINS + 2) + RDDMC_STEP_BINS;
+        c.tally_words = kTallyHeader + (uint64_t)c.n_rows * (c.nb + 2) + (RDDMC_TIME_BINS + 2) + RDDMC_STEP_BINS +
+                        c.n_pix;
         tally += c.tally_words;
     }
     L.h.total_packets = L.prefix[n];
@@ -311,7 +347,7 @@ rddmc_status rddmc_build_leakage(const rddmc_batch *batch, void *d_tables, size_
     for (int ci = 0; ci < L.h.n_clouds; ++ci) {
         const rddmc_medium &m = batch->clouds[ci];
         const DevCloud &c = L.clouds[ci];
-        const uint64_t a = c.off_edges, z = c.off_src_cdf + 8ull * c.n_src;
+        const uint64_t a = c.off_edges, z = c.off_src_pos + 16ull * c.n_src;
         bufs.emplace_back(z - a, 0);
         auto &buf = bufs.back();
         put(buf, c.off_edges - a, m.bin_edges, 8ull * (c.nb + 1));
@@ -328,6 +364,7 @@ rddmc_status rddmc_build_leakage(const rddmc_batch *batch, void *d_tables, size_
         if (m.vel) put(buf, c.off_vel - a, m.vel, 8ull * c.nc * (c.geometry == RDDMC_CART3D ? 3 : 1));
         put(buf, c.off_src_state - a, L.src_state[ci].data(), 4ull * c.n_src);
         put(buf, c.off_src_cdf - a, L.src_cdf[ci].data(), 8ull * c.n_src);
+        if (c.geometry == RDDMC_CART3D) put(buf, c.off_src_pos - a, L.src_pos[ci].data(), 16ull * c.n_src);
         if ((e = hipMemcpyAsync(static_cast<uint8_t *>(d_tables) + a, buf.data(), z - a, hipMemcpyHostToDevice,
                                 s)) != hipSuccess)
             return hip_fail(e, "hipMemcpyAsync(inputs)");
@@ -335,6 +372,8 @@ rddmc_status rddmc_build_leakage(const rddmc_batch *batch, void *d_tables, size_
     for (int ci = 0; ci < L.h.n_clouds; ++ci)
         if ((e = launch_build(L.clouds[ci], ci, static_cast<uint8_t *>(d_tables), s)) != hipSuccess)
             return hip_fail(e, "build kernels");
+    if ((e = launch_build_line_tables(L.h, static_cast<uint8_t *>(d_tables), s)) != hipSuccess)
+        return hip_fail(e, "line-table kernels");
     uint32_t flags = 0;
     if ((e = hipMemcpyAsync(&flags, &reinterpret_cast<DevHeader *>(d_tables)->error_flags, 4,
                             hipMemcpyDeviceToHost, s)) != hipSuccess)
@@ -342,7 +381,9 @@ rddmc_status rddmc_build_leakage(const rddmc_batch *batch, void *d_tables, size_
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
     if (flags & BE_NONFINITE) return fail(RDDMC_ENUMERIC, "a leakage table entry is non-finite or non-positive");
     if (flags & BE_THIN)
-        return fail(RDDMC_EUNSUPPORTED, "thin (continuous Monte Carlo) states are not built yet; use tau_threshold = 0");
+        return fail(RDDMC_EUNSUPPORTED,
+                    "thin (continuous Monte Carlo) states are walked on 3D Cartesian grids only; 1D geometries "
+                    "need tau_threshold = 0 or every state thick");
     return RDDMC_OK;
 }
 
@@ -376,6 +417,12 @@ rddmc_status rddmc_transport(const rddmc_batch *batch, const void *d_tables, con
     const uint64_t count = run->count ? run->count : total - run->first;
     if (count > total - run->first) return fail(RDDMC_EINVAL, "first + count beyond the batch's packets");
     if (count == 0) return RDDMC_OK;
+    if (L.h.geometry == RDDMC_CART3D) {
+        hipError_t e = launch_walk3d(static_cast<const uint8_t *>(d_tables), L.h, *run, run->first, count,
+                                     static_cast<unsigned long long *>(d_tally),
+                                     static_cast<unsigned long long *>(d_work), reinterpret_cast<hipStream_t>(stream));
+        return e == hipSuccess ? RDDMC_OK : hip_fail(e, "3D walk kernel");
+    }
     hipError_t e = launch_walk(static_cast<const uint8_t *>(d_tables), L.h, L.clouds.data(), *run, run->first,
                                count, static_cast<unsigned long long *>(d_tally),
                                static_cast<unsigned long long *>(d_work), work_bytes,
@@ -405,6 +452,9 @@ rddmc_status rddmc_tally(const rddmc_batch *batch, const void *d_tally, size_t t
             std::memcpy(out->time_hist[ci], w + kTallyHeader + nspec, 8 * (RDDMC_TIME_BINS + 2));
         if (out->step_hist && out->step_hist[ci])
             std::memcpy(out->step_hist[ci], w + kTallyHeader + nspec + RDDMC_TIME_BINS + 2, 8 * RDDMC_STEP_BINS);
+        if (out->pixels && out->pixels[ci] && c.n_pix)
+            std::memcpy(out->pixels[ci], w + kTallyHeader + nspec + RDDMC_TIME_BINS + 2 + RDDMC_STEP_BINS,
+                        8 * c.n_pix);
         if (out->stats) {
             rddmc_cloud_stats &z = out->stats[ci];
             z.launched = w[TW_LAUNCHED];
@@ -422,6 +472,11 @@ rddmc_status rddmc_tally(const rddmc_batch *batch, const void *d_tally, size_t t
             z.t_var = ne > 0 ? (double)(t2 / (long double)ne) - z.t_mean * z.t_mean : 0.0;
             z.n_rows = c.n_rows;
             z.n_slots = c.nb + 2;
+            z.to_mc = w[TW_TO_MC];
+            z.to_ddmc = w[TW_TO_DDMC];
+            z.reflected = w[TW_REFLECTED];
+            z.mc_steps = w[TW_MC_STEPS];
+            z.n_pix = c.n_pix;
         }
     }
     return RDDMC_OK;

@@ -22,7 +22,28 @@ enum TallyWord {
     TW_T2_LO = 5,     // 128-bit sum of round(t^2 * 2^20): low word
     TW_T2_HI = 6,     //                                   high word
     TW_LAUNCHED = 7,
+    TW_TO_MC = 8,     // hybrid: DDMC -> continuous MC conversions
+    TW_TO_DDMC = 9,   //         MC -> DDMC conversions
+    TW_REFLECTED = 10,//         MC packets reflected at a thick interface
+    TW_MC_STEPS = 11, //         MC events (scatterings and face crossings)
 };
+
+// 3D cells: the fourth word of the hot record holds flags instead of F.
+constexpr uint32_t kFlagThick = 1u;             // the state is a DDMC state (tau >= tau_th)
+constexpr int kFlagFaceShift = 1;               // bit 1+f: a leak through face f enters a thin
+                                                // state or vacuum (interface rate, conversion)
+constexpr uint32_t kFlagDnThin = 1u << 7;       // bin j-1 of the cell is thin
+constexpr uint32_t kFlagUpThin = 1u << 8;       // bin j+1 of the cell is thin
+
+// Shared FP32 line tables for the continuous-MC states (built once per table buffer).
+//   voigt: H1(x) = (2/sqrt(pi)) (2 x F(x) - 1) on x = i/256, i < kVoigtN (F = Dawson), so
+//          that H(a,x) = exp(-x^2)(1 + a^2 (1 - 2x^2)) + a H1(|x|) (eq. 12);
+//   u0:    split point of the atom-velocity rejection sampler on log10(a) = -6 + i/8,
+//          |x| = k/8 (any u0 >= 0 is exact; the table's minimises the proposal mass).
+constexpr int kVoigtN = 4097;
+constexpr float kVoigtScale = 256.0f;
+constexpr int kU0NA = 49, kU0NX = 257;
+constexpr float kU0Scale = 8.0f;
 
 // The per-state record every DDMC step reads: one 16-byte load.  A uniform u64 U picks the
 // event against three u64 thresholds D <= S <= F:
@@ -35,7 +56,7 @@ struct alignas(16) HotRecord {
     float ln2_over_K;      // ln(2) / K, K = total leakage rate of the state [1/length]
     uint32_t d_hi;         // high word of D
     uint32_t s_hi;         // high word of S
-    uint32_t f_hi;         // high word of F
+    uint32_t f_hi;         // high word of F (1D); flags (3D: kFlagThick, face bits)
 };
 static_assert(sizeof(HotRecord) == 16, "hot record must be 16 bytes");
 
@@ -61,8 +82,11 @@ struct alignas(16) DevCloud {
     uint64_t off_rates;          // f64 [n_states * (nf+2)]  (only with keep_rates)
     uint64_t off_map;            // f64 [nc * nf * 3]: rho, shift, u_n per (cell, face)
     uint64_t off_cmap;           // f32x4 [nc] (1D): rho and shift of face 0, then of face 1
+    uint64_t off_src_pos;        // f32x4 [n_src] (3D): source position and frequency
+    uint64_t off_mcell;          // f32x4 [2 nc] (3D): {k0, a, sqrt(T), w_min}, {u_x, u_y, u_z, 0}
     uint64_t tally_off;          // int64 word offset of this cloud's tally block
     uint64_t tally_words;
+    uint64_t n_pix;              // 3D: escape pixels 2 (ny nz + nx nz + nx ny), after the step histogram
     double tau_th, f_mu, lambda;
     float x0, dx, inv_dx;        // uniform bin grid: first edge, width, 1/width
     int32_t uniform_bins;        // 1 when every bin has the same width
@@ -76,6 +100,8 @@ struct alignas(16) DevHeader {
     uint64_t off_prefix;         // u64 [n_clouds+1] flattened packet prefix
     uint32_t error_flags;        // set by the build kernels (see BuildError)
     uint32_t pad;
+    uint64_t off_voigt;          // f32 [kVoigtN] (3D batches)
+    uint64_t off_u0;             // f32 [kU0NA * kU0NX] (3D batches)
 };
 
 enum BuildError : uint32_t {
@@ -90,6 +116,9 @@ hipError_t launch_walk(const uint8_t *d_tables, const DevHeader &h, const DevClo
                        unsigned long long *d_tally, unsigned long long *d_work, uint64_t work_bytes,
                        hipStream_t s);
 hipError_t launch_zero(void *d, size_t words64, hipStream_t s);
+hipError_t launch_build_line_tables(const DevHeader &h, uint8_t *d_tables, hipStream_t s);
+hipError_t launch_walk3d(const uint8_t *d_tables, const DevHeader &h, const rddmc_run &run, uint64_t first,
+                         uint64_t count, unsigned long long *d_tally, unsigned long long *d_work, hipStream_t s);
 hipError_t launch_philox_fill(uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1, uint32_t c2,
                               uint32_t c3, uint64_t n, uint32_t *d_out, hipStream_t s);
 int device_cu_count();

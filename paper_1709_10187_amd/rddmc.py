@@ -55,12 +55,17 @@ class CloudStats_t(C.Structure):
     _fields_ = [("launched", C.c_uint64), ("escaped", C.c_uint64), ("capped", C.c_uint64),
                 ("steps_total", C.c_uint64), ("steps_max", C.c_uint64), ("steps_mean", C.c_double),
                 ("t_mean", C.c_double), ("t_var", C.c_double), ("n_rows", C.c_int32),
-                ("n_slots", C.c_int32)]
+                ("n_slots", C.c_int32), ("to_mc", C.c_uint64), ("to_ddmc", C.c_uint64),
+                ("reflected", C.c_uint64), ("mc_steps", C.c_uint64), ("n_pix", C.c_uint64)]
 
 
 class TallyOut_t(C.Structure):
     _fields_ = [("spectrum", C.POINTER(C.c_void_p)), ("time_hist", C.POINTER(C.c_void_p)),
-                ("step_hist", C.POINTER(C.c_void_p)), ("stats", C.POINTER(CloudStats_t))]
+                ("step_hist", C.POINTER(C.c_void_p)), ("stats", C.POINTER(CloudStats_t)),
+                ("pixels", C.POINTER(C.c_void_p))]
+
+
+ABI_VERSION = 2
 
 
 EXPORTS = ["rddmc_abi_version", "rddmc_last_error", "rddmc_table_bytes", "rddmc_tally_bytes",
@@ -80,6 +85,8 @@ def load(path: str = LIB_PATH):
     lib = C.CDLL(path)
     vp, sz = C.c_void_p, C.c_size_t
     lib.rddmc_abi_version.restype = C.c_int32
+    if lib.rddmc_abi_version() != ABI_VERSION:
+        raise RuntimeError(f"{path} has ABI {lib.rddmc_abi_version()}, the binding expects {ABI_VERSION}: rebuild it")
     lib.rddmc_last_error.restype = C.c_char_p
     for name in ("rddmc_table_bytes", "rddmc_tally_bytes", "rddmc_work_bytes"):
         getattr(lib, name).argtypes = [C.POINTER(Batch_t), C.POINTER(sz)]
@@ -213,6 +220,18 @@ class CloudTally:
     steps_mean: float
     t_mean: float
     t_var: float
+    to_mc: int = 0
+    to_ddmc: int = 0
+    reflected: int = 0
+    mc_steps: int = 0
+    pixels: Optional[np.ndarray] = None   # 3D: escape counts per boundary cell (see include/rddmc.h)
+
+
+def n_pixels(m) -> int:
+    if m.geometry != 2:
+        return 0
+    nx, ny, nz = (int(v) for v in m.n_cells)
+    return 2 * (ny * nz + nx * nz + nx * ny)
 
 
 def tally(b: Batch, d_tally, stream=None) -> List[CloudTally]:
@@ -224,15 +243,18 @@ def tally(b: Batch, d_tally, stream=None) -> List[CloudTally]:
     sp_ptrs = (C.c_void_p * n)(*[a.ctypes.data for a in specs])
     th_ptrs = (C.c_void_p * n)(*[a.ctypes.data for a in th])
     sh_ptrs = (C.c_void_p * n)(*[a.ctypes.data for a in sh])
+    pix = [np.zeros(n_pixels(b.meds[i]), dtype=np.int64) for i in range(n)]
+    px_ptrs = (C.c_void_p * n)(*[a.ctypes.data if a.size else None for a in pix])
     stats = (CloudStats_t * n)()
-    out = TallyOut_t(sp_ptrs, th_ptrs, sh_ptrs, stats)
+    out = TallyOut_t(sp_ptrs, th_ptrs, sh_ptrs, stats, px_ptrs)
     _check(lib.rddmc_tally(b.ref(), C.c_void_p(d_tally.data_ptr()), d_tally.numel() * d_tally.element_size(),
                            C.byref(out), _stream(stream)))
     res = []
     for i in range(n):
         z = stats[i]
         res.append(CloudTally(specs[i], th[i], sh[i], z.launched, z.escaped, z.capped, z.steps_total,
-                              z.steps_max, z.steps_mean, z.t_mean, z.t_var))
+                              z.steps_max, z.steps_mean, z.t_mean, z.t_var, z.to_mc, z.to_ddmc, z.reflected,
+                              z.mc_steps, pix[i] if pix[i].size else None))
     return res
 
 

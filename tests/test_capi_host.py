@@ -26,7 +26,17 @@ def test_library_exports_every_declared_symbol():
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) == set(rddmc.EXPORTS)
-    assert lib.rddmc_abi_version() == 1
+    assert lib.rddmc_abi_version() == rddmc.ABI_VERSION == 2
+
+
+def test_cart3d_size_queries():
+    m = media.cube(n=6, n_bins=32, n_sources=4)
+    b = rddmc.Batch([m])
+    # tally: header, 6 face rows of nb+2 slots, time and step histograms, boundary pixels
+    assert rddmc.tally_bytes(b) == 8 * (16 + 6 * 34 + 130 + 64 + 6 * 36)
+    assert rddmc.n_pixels(m) == 6 * 36
+    # tables: at least the hot records, low words, k and the five face-split words per state
+    assert rddmc.table_bytes(b) > 6 ** 3 * 32 * (16 + 16 + 8 + 20)
 
 
 def test_size_queries():

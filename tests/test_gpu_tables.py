@@ -68,3 +68,58 @@ def test_static_table_symmetry_on_gpu():
     np.testing.assert_allclose(k, k[:, ::-1], rtol=1e-13)
     lk = hot["ln2_over_K"].reshape(64, 128)
     np.testing.assert_array_equal(lk, lk[::-1, :])
+
+
+def _cases_3d():
+    rng = np.random.default_rng(12)
+    box = media.cube(n=4, seed=3, mean_tau_cell=200.0, n_bins=12, dv_bin=30.0, tau_threshold=0.0,
+                     n_sources=1)
+    faces = [np.concatenate([[0.0], np.cumsum(rng.uniform(0.5, 1.5, size=4))]) for _ in range(3)]
+    box = box.replace(faces=faces, temp=np.geomspace(3e3, 3e4, 64), name="box_pure_moving_nonuniform")
+    return {
+        "cube_hybrid": media.cube(n=6, seed=2, n_bins=48, n_sources=2),
+        "cube_hybrid_static_dirichlet": media.cube(n=5, seed=4, n_bins=20, sigma_v=0.0, n_sources=2,
+                                                   tau_threshold=3.0).replace(flags=media.FLAG_DIRICHLET),
+        "box_pure_moving_nonuniform": box,
+    }
+
+
+CASES_3D = _cases_3d()
+
+
+@pytest.mark.parametrize("name", sorted(CASES_3D))
+def test_tables_3d_match_oracle(name):
+    """3D Cartesian tables: k, rates, ln2/K and thresholds of the DDMC states; the flag word
+    (thick, interface faces, thin neighbour bins) against the oracle's classification."""
+    m = CASES_3D[name]
+    print(f"[tables] {name} cells={m.n_cells} bins={m.n_bins} tau_th={m.tau_threshold}", flush=True)
+    prob = rddmc.Problem(m, keep_rates=True)
+    k, rates, hot, D, S, _ = prob.read_tables(0)
+    t = tb.build(m)
+    nc, nb = t.nc, t.nb
+    ns = nc * nb
+    np.testing.assert_allclose(k, t.k.reshape(ns), rtol=1e-6)
+    ref_rates = np.concatenate([t.rate_face.reshape(ns, 6), t.rate_dn.reshape(ns, 1),
+                                t.rate_up.reshape(ns, 1)], axis=1)
+    np.testing.assert_allclose(rates, ref_rates, rtol=1e-6, atol=0)
+    thick = t.thick.reshape(ns)
+    flags = hot["f_hi"]
+    np.testing.assert_array_equal((flags & 1) == 1, thick)
+    assert np.all(flags[~thick] == 0) and np.all(hot["ln2_over_K"][~thick] == 0)
+    iface = (flags >> 1) & 63
+    ref_iface = (t.face_is_mc.reshape(ns, 6) * (1 << np.arange(6))).sum(axis=1)
+    np.testing.assert_array_equal(iface[thick], ref_iface[thick])
+    th2 = t.thick
+    dn_thin = np.zeros((nc, nb), dtype=bool)
+    up_thin = np.zeros((nc, nb), dtype=bool)
+    dn_thin[:, 1:] = ~th2[:, :-1]
+    up_thin[:, :-1] = ~th2[:, 1:]
+    np.testing.assert_array_equal(((flags >> 7) & 1)[thick] == 1, dn_thin.reshape(ns)[thick])
+    np.testing.assert_array_equal(((flags >> 8) & 1)[thick] == 1, up_thin.reshape(ns)[thick])
+    K = t.K.reshape(ns)[thick]
+    np.testing.assert_allclose(hot["ln2_over_K"][thick], LN2 / K, rtol=1e-6)
+    two64 = 2.0 ** 64
+    p_dn = D[thick].astype(np.float64) / two64
+    p_up = (S[thick].astype(np.float64) - D[thick].astype(np.float64)) / two64
+    np.testing.assert_allclose(p_dn, t.rate_dn.reshape(ns)[thick] / K, rtol=1e-6, atol=2.0 ** -52)
+    np.testing.assert_allclose(p_up, t.rate_up.reshape(ns)[thick] / K, rtol=1e-6, atol=2.0 ** -52)
