@@ -283,6 +283,44 @@ rddmc_status rddmc_read_tables(const rddmc_batch *batch, const void *d_tables, i
 rddmc_status rddmc_philox_fill(uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1, uint32_t c2,
                                uint32_t c3, uint64_t n, uint32_t *d_out, void *stream);
 
+/* ---- learned escape surrogate: mixture-density network --------------------------------
+ *
+ * A multilayer perceptron 16 -> 256 -> 256 -> 256 -> 128 with exact GELU whose outputs are
+ * a 16-component mixture over (exit face of a thick DDMC cell, y1 = asinh-scaled exit
+ * frequency, y2 = log time spent); it learns the law of a packet's exit from one cell from
+ * sub-walks of the DDMC walk itself (the surrogate calls below).  Products run on BF16
+ * matrix cores with FP32 accumulation; parameters, gradients and the Adam state are FP32.
+ *
+ * d_params   device buffer of param_bytes (caller-owned): FP32 theta (n_params values in
+ *            the order W1 [16,256], b1, W2 [256,256], b2, W3, b3, W4 [256,128], b4, each W
+ *            input-major), Adam moments, gradient, BF16 weight copies.
+ * d_work     device buffer of work_bytes for batches of up to max_batch samples.
+ * d_x        FP32 [n, 16] inputs; d_y FP32 [n, 3] targets (face as 0/1, y1, y2).
+ * Errors: EINVAL (NULL, sizes), EHIP.
+ */
+rddmc_status rddmc_mdn_bytes(int64_t max_batch, size_t *param_bytes, size_t *work_bytes, int64_t *n_params);
+
+/* Glorot-uniform weights, zero biases and Adam state from `seed`. */
+rddmc_status rddmc_mdn_init(void *d_params, uint64_t seed, void *stream);
+
+/* Upload theta (FP32, n_params values) and reset the optimiser; synchronises. */
+rddmc_status rddmc_mdn_set(void *d_params, const float *h_theta, void *stream);
+
+/* Copy theta and / or the last gradient (each may be NULL) to the host; synchronises. */
+rddmc_status rddmc_mdn_get(const void *d_params, float *h_theta, float *h_grad, void *stream);
+
+/* Raw outputs (FP32 [n, 128]) of the network for n inputs. */
+rddmc_status rddmc_mdn_forward(void *d_params, void *d_work, int64_t max_batch, const float *d_x, int32_t n,
+                               float *d_out, void *stream);
+
+/* Mean negative log-likelihood of (d_x, d_y) into *d_loss (device FP32, may be NULL) and its
+ * gradient with respect to theta into the parameter buffer's gradient slot. */
+rddmc_status rddmc_mdn_loss_grad(void *d_params, void *d_work, int64_t max_batch, const float *d_x,
+                                 const float *d_y, int32_t n, float *d_loss, void *stream);
+
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8) with the stored gradient; `step` counts from 1. */
+rddmc_status rddmc_mdn_adam(void *d_params, int64_t step, float lr, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -512,6 +512,78 @@ rddmc_status rddmc_read_tables(const rddmc_batch *batch, const void *d_tables, i
     return RDDMC_OK;
 }
 
+/* ---- mixture-density network of the escape surrogate --------------------------------- */
+
+rddmc_status rddmc_mdn_bytes(int64_t max_batch, size_t *param_bytes, size_t *work_bytes, int64_t *n_params)
+{
+    if (max_batch < 1 || max_batch > (1ll << 24)) return fail(RDDMC_EINVAL, "max_batch must be in [1, 2^24]");
+    const int64_t cap = (max_batch + 31) & ~31ll;
+    if (param_bytes) *param_bytes = mdn_param_bytes();
+    if (work_bytes) *work_bytes = mdn_work_bytes(cap);
+    if (n_params) *n_params = mdn_n_params();
+    return RDDMC_OK;
+}
+
+rddmc_status rddmc_mdn_init(void *d_params, uint64_t seed, void *stream)
+{
+    if (!d_params) return fail(RDDMC_EINVAL, "d_params is NULL");
+    hipError_t e = mdn_init(d_params, seed, reinterpret_cast<hipStream_t>(stream));
+    return e == hipSuccess ? RDDMC_OK : hip_fail(e, "mdn init");
+}
+
+rddmc_status rddmc_mdn_set(void *d_params, const float *h_theta, void *stream)
+{
+    if (!d_params || !h_theta) return fail(RDDMC_EINVAL, "NULL argument");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int64_t n = mdn_n_params();
+    hipError_t e = mdn_init(d_params, 0, s);        // zero the optimiser state
+    if (e == hipSuccess) e = hipMemcpyAsync(d_params, h_theta, 4ull * n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = mdn_refresh(d_params, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return e == hipSuccess ? RDDMC_OK : hip_fail(e, "mdn set");
+}
+
+rddmc_status rddmc_mdn_get(const void *d_params, float *h_theta, float *h_grad, void *stream)
+{
+    if (!d_params) return fail(RDDMC_EINVAL, "d_params is NULL");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int64_t n = mdn_n_params();
+    const float *f = static_cast<const float *>(d_params);
+    hipError_t e = hipSuccess;
+    if (h_theta) e = hipMemcpyAsync(h_theta, f, 4ull * n, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && h_grad) e = hipMemcpyAsync(h_grad, f + 3 * n, 4ull * n, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return e == hipSuccess ? RDDMC_OK : hip_fail(e, "mdn get");
+}
+
+rddmc_status rddmc_mdn_forward(void *d_params, void *d_work, int64_t max_batch, const float *d_x, int32_t n,
+                               float *d_out, void *stream)
+{
+    if (!d_params || !d_work || !d_x) return fail(RDDMC_EINVAL, "NULL argument");
+    if (n < 1 || n > max_batch) return fail(RDDMC_EINVAL, "n must be in [1, max_batch]");
+    const int64_t cap = (max_batch + 31) & ~31ll;
+    hipError_t e = mdn_forward(d_params, d_work, cap, d_x, n, d_out, reinterpret_cast<hipStream_t>(stream));
+    return e == hipSuccess ? RDDMC_OK : hip_fail(e, "mdn forward");
+}
+
+rddmc_status rddmc_mdn_loss_grad(void *d_params, void *d_work, int64_t max_batch, const float *d_x,
+                                 const float *d_y, int32_t n, float *d_loss, void *stream)
+{
+    if (!d_params || !d_work || !d_x || !d_y) return fail(RDDMC_EINVAL, "NULL argument");
+    if (n < 1 || n > max_batch) return fail(RDDMC_EINVAL, "n must be in [1, max_batch]");
+    const int64_t cap = (max_batch + 31) & ~31ll;
+    hipError_t e = mdn_loss_grad(d_params, d_work, cap, d_x, d_y, n, d_loss, reinterpret_cast<hipStream_t>(stream));
+    return e == hipSuccess ? RDDMC_OK : hip_fail(e, "mdn loss/grad");
+}
+
+rddmc_status rddmc_mdn_adam(void *d_params, int64_t step, float lr, void *stream)
+{
+    if (!d_params) return fail(RDDMC_EINVAL, "d_params is NULL");
+    if (step < 1 || !(lr > 0.0f)) return fail(RDDMC_EINVAL, "step >= 1 and lr > 0 required");
+    hipError_t e = mdn_adam(d_params, step, lr, reinterpret_cast<hipStream_t>(stream));
+    return e == hipSuccess ? RDDMC_OK : hip_fail(e, "mdn adam");
+}
+
 rddmc_status rddmc_philox_fill(uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                uint64_t n, uint32_t *d_out, void *stream)
 {

@@ -116,6 +116,18 @@ hipError_t launch_walk(const uint8_t *d_tables, const DevHeader &h, const DevClo
                        unsigned long long *d_tally, unsigned long long *d_work, uint64_t work_bytes,
                        hipStream_t s);
 hipError_t launch_zero(void *d, size_t words64, hipStream_t s);
+// mixture-density network (mdn.hip)
+uint64_t mdn_param_bytes();
+uint64_t mdn_work_bytes(int64_t cap);
+int64_t mdn_n_params();
+hipError_t mdn_init(void *d_params, uint64_t seed, hipStream_t s);
+hipError_t mdn_refresh(void *d_params, hipStream_t s);
+hipError_t mdn_forward(void *d_params, void *d_work, int64_t cap, const float *d_x, int n, float *d_out,
+                       hipStream_t s);
+hipError_t mdn_loss_grad(void *d_params, void *d_work, int64_t cap, const float *d_x, const float *d_y, int n,
+                         float *d_loss, hipStream_t s);
+hipError_t mdn_adam(void *d_params, int64_t step, float lr, hipStream_t s);
+const float *mdn_outputs(void *d_work, int64_t cap);
 hipError_t launch_build_line_tables(const DevHeader &h, uint8_t *d_tables, hipStream_t s);
 hipError_t launch_walk3d(const uint8_t *d_tables, const DevHeader &h, const rddmc_run &run, uint64_t first,
                          uint64_t count, unsigned long long *d_tally, unsigned long long *d_work, hipStream_t s);

@@ -70,7 +70,8 @@ ABI_VERSION = 2
 
 EXPORTS = ["rddmc_abi_version", "rddmc_last_error", "rddmc_table_bytes", "rddmc_tally_bytes",
            "rddmc_work_bytes", "rddmc_build_leakage", "rddmc_transport", "rddmc_tally_reset",
-           "rddmc_tally", "rddmc_read_tables", "rddmc_philox_fill"]
+           "rddmc_tally", "rddmc_read_tables", "rddmc_philox_fill", "rddmc_mdn_bytes", "rddmc_mdn_init",
+           "rddmc_mdn_set", "rddmc_mdn_get", "rddmc_mdn_forward", "rddmc_mdn_loss_grad", "rddmc_mdn_adam"]
 
 _lib = None
 
@@ -97,8 +98,17 @@ def load(path: str = LIB_PATH):
     lib.rddmc_tally.argtypes = [C.POINTER(Batch_t), vp, sz, C.POINTER(TallyOut_t), vp]
     lib.rddmc_read_tables.argtypes = [C.POINTER(Batch_t), vp, C.c_int32, vp, vp, vp, vp, vp]
     lib.rddmc_philox_fill.argtypes = [C.c_uint32] * 6 + [C.c_uint64, vp, vp]
+    lib.rddmc_mdn_bytes.argtypes = [C.c_int64, C.POINTER(sz), C.POINTER(sz), C.POINTER(C.c_int64)]
+    lib.rddmc_mdn_init.argtypes = [vp, C.c_uint64, vp]
+    lib.rddmc_mdn_set.argtypes = [vp, vp, vp]
+    lib.rddmc_mdn_get.argtypes = [vp, vp, vp, vp]
+    lib.rddmc_mdn_forward.argtypes = [vp, vp, C.c_int64, vp, C.c_int32, vp, vp]
+    lib.rddmc_mdn_loss_grad.argtypes = [vp, vp, C.c_int64, vp, vp, C.c_int32, vp, vp]
+    lib.rddmc_mdn_adam.argtypes = [vp, C.c_int64, C.c_float, vp]
     for name in ("rddmc_build_leakage", "rddmc_transport", "rddmc_tally_reset", "rddmc_tally",
-                 "rddmc_read_tables", "rddmc_philox_fill"):
+                 "rddmc_read_tables", "rddmc_philox_fill", "rddmc_mdn_bytes", "rddmc_mdn_init",
+                 "rddmc_mdn_set", "rddmc_mdn_get", "rddmc_mdn_forward", "rddmc_mdn_loss_grad",
+                 "rddmc_mdn_adam"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -325,3 +335,63 @@ class Problem:
 
     def read_tables(self, cloud=0, want_rates=True):
         return read_tables(self.batch, self.tables, cloud, want_rates, self.stream)
+
+
+def mdn_bytes(max_batch):
+    lib = load()
+    pb, wb, npar = C.c_size_t(), C.c_size_t(), C.c_int64()
+    _check(lib.rddmc_mdn_bytes(int(max_batch), C.byref(pb), C.byref(wb), C.byref(npar)))
+    return pb.value, wb.value, npar.value
+
+
+class Mdn:
+    """Device buffers of the escape-surrogate network (parameters, optimiser state, work)."""
+
+    def __init__(self, max_batch=4096, seed=0, device="cuda", stream=None):
+        import torch
+        self.max_batch = int(max_batch)
+        pb, wb, self.n_params = mdn_bytes(self.max_batch)
+        self.params = torch.zeros(pb // 4, dtype=torch.float32, device=device)
+        self.work = torch.zeros(wb // 4 + 64, dtype=torch.float32, device=device)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=device)
+        self.stream = stream
+        self.step = 0
+        _check(load().rddmc_mdn_init(C.c_void_p(self.params.data_ptr()), int(seed), _stream(stream)))
+
+    def set_theta(self, theta):
+        th = np.ascontiguousarray(theta, dtype=np.float32)
+        assert th.size == self.n_params
+        _check(load().rddmc_mdn_set(C.c_void_p(self.params.data_ptr()), th.ctypes.data, _stream(self.stream)))
+        self.step = 0
+
+    def get(self):
+        th = np.zeros(self.n_params, dtype=np.float32)
+        g = np.zeros(self.n_params, dtype=np.float32)
+        _check(load().rddmc_mdn_get(C.c_void_p(self.params.data_ptr()), th.ctypes.data, g.ctypes.data,
+                                    _stream(self.stream)))
+        return th, g
+
+    def forward(self, x):
+        import torch
+        n = int(x.shape[0])
+        out = torch.empty((n, 128), dtype=torch.float32, device=x.device)
+        _check(load().rddmc_mdn_forward(C.c_void_p(self.params.data_ptr()), C.c_void_p(self.work.data_ptr()),
+                                        self.max_batch, C.c_void_p(x.data_ptr()), n, C.c_void_p(out.data_ptr()),
+                                        _stream(self.stream)))
+        return out
+
+    def loss_grad(self, x, y):
+        n = int(x.shape[0])
+        _check(load().rddmc_mdn_loss_grad(C.c_void_p(self.params.data_ptr()), C.c_void_p(self.work.data_ptr()),
+                                          self.max_batch, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), n,
+                                          C.c_void_p(self.loss.data_ptr()), _stream(self.stream)))
+        return self.loss
+
+    def adam(self, lr):
+        self.step += 1
+        _check(load().rddmc_mdn_adam(C.c_void_p(self.params.data_ptr()), self.step, float(lr), _stream(self.stream)))
+
+    def train_step(self, x, y, lr):
+        loss = self.loss_grad(x, y)
+        self.adam(lr)
+        return loss
