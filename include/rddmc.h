@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define RDDMC_ABI_VERSION 2
+#define RDDMC_ABI_VERSION 3
 
 typedef enum {
     RDDMC_OK = 0,
@@ -127,6 +127,10 @@ typedef struct {
  *                packets left hands them to a cooperative walk in which a whole wave
  *                advances one packet (0 = automatic (16), < 0 = never).  Results are
  *                bit-identical either way.
+ *   surrogate    1D clouds: learned escape surrogate (rddmc_surrogate_attach) or NULL for
+ *                plain rDDMC; with it, a packet in a state of its cloud's surrogate window
+ *                leaves the cell by one exit drawn from the learned law (no cooperative
+ *                tail walk).
  */
 typedef struct {
     uint64_t seed;
@@ -137,6 +141,7 @@ typedef struct {
     int32_t grid;
     int32_t chunk;
     int32_t tail_lanes;
+    const void *surrogate;   /* device buffer written by rddmc_surrogate_attach, or NULL */
 } rddmc_run;
 
 /* Per-cloud summary filled by rddmc_tally (FP64 host-side normalisation of the exact
@@ -158,6 +163,8 @@ typedef struct {
     uint64_t mc_steps;       /* hybrid (3D): MC events (scatterings and face crossings),  */
                              /* included in steps_total                                  */
     uint64_t n_pix;          /* 3D: escape pixels 2 (ny nz + nx nz + nx ny); else 0       */
+    uint64_t surrogate_calls;/* cell exits drawn from the learned surrogate (each counted  */
+                             /* as two steps in steps_total)                             */
 } rddmc_cloud_stats;
 
 /*
@@ -282,6 +289,56 @@ rddmc_status rddmc_read_tables(const rddmc_batch *batch, const void *d_tables, i
  */
 rddmc_status rddmc_philox_fill(uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1, uint32_t c2,
                                uint32_t c3, uint64_t n, uint32_t *d_out, void *stream);
+
+/* ---- learned escape surrogate: training data and per-state tables ---------------------
+ *
+ * The surrogate replaces the rest of a packet's DDMC walk inside one thick cell of a 1D
+ * cloud (all the frequency steps until the first spatial leak, Sec. 2.3) by one exit
+ * (face, exit frequency, time spent) drawn from a learned law.  The law is a function of
+ * the state: cell optical width tau_c = k0 w, damping a, entry bin (centre, width), the
+ * Doppler shifts into the two neighbours (eq. 20) and the face geometry (A_f/dV) w.
+ *
+ * Domain of the trained network (states outside it walk plainly): */
+typedef struct {
+    double tau_min, tau_max;   /* cell optical width k0 w                                  */
+    double a_min, a_max;       /* damping parameter                                         */
+    double dx_min, dx_max;     /* entry-bin width                                           */
+    double shift_max;          /* |Doppler shift| across either face                        */
+    double g_min, g_max;       /* face geometry (A_f / dV) w (1 for slabs)                  */
+    double x_core;             /* entry-bin centres within |x| <= x_core                    */
+} rddmc_surrogate_cfg;
+
+/*
+ * Training data from the walk itself: sample q starts in state h_state[q] (cell * n_bins +
+ * bin) of cloud h_cloud[q] (a cell with two neighbours; host arrays) and takes DDMC steps
+ * until its first spatial leak.  Writes the state's network inputs d_x [n, 16] and the exit
+ * d_y [n, 3] = (face 0/1, asinh(x_out / S), ln(dt / w)) with x_out uniform in the exit bin
+ * (cell frame), S = (a tau_c)^(1/3), w the cell width; face = -1 if max_steps ran out.
+ * d_steps [n] receives each sub-walk's step count.  d_scratch >= 8 n bytes.  Synchronises.
+ * Errors: EINVAL (bad start, 3D), ESIZE, EHIP.
+ */
+rddmc_status rddmc_surrogate_samples(const rddmc_batch *batch, const void *d_tables, const int32_t *h_cloud,
+                                     const int32_t *h_state, int64_t n, uint64_t seed, uint64_t max_steps,
+                                     void *d_scratch, size_t scratch_bytes, float *d_x, float *d_y,
+                                     uint64_t *d_steps, void *stream);
+
+/* Bytes of the surrogate buffer for a batch (windows, staging for max_batch states, one
+ * 512-byte sampling record per window state) and the number of window states. */
+rddmc_status rddmc_surrogate_bytes(const rddmc_batch *batch, const rddmc_surrogate_cfg *cfg, int64_t max_batch,
+                                   size_t *bytes, uint64_t *n_states);
+
+/* The window {i_lo, i_hi, j_lo, j_hi} of cloud `cloud` (empty when i_hi < i_lo): interior
+ * cells of a uniform cloud inside the domain (longest contiguous run) x the bins around 0. */
+rddmc_status rddmc_surrogate_window(const rddmc_batch *batch, const rddmc_surrogate_cfg *cfg, int32_t cloud,
+                                    int32_t *window);
+
+/* Evaluate the network (rddmc_mdn_*) on every window state in batches of max_batch (BF16
+ * matrix cores) and store the sampling records in d_surr (>= rddmc_surrogate_bytes,
+ * 256-byte aligned); pass d_surr as rddmc_run.surrogate.  Synchronises.
+ * Errors: EINVAL, ESIZE, EHIP. */
+rddmc_status rddmc_surrogate_attach(const rddmc_batch *batch, const void *d_tables, void *d_params, void *d_work,
+                                    int64_t max_batch, const rddmc_surrogate_cfg *cfg, void *d_surr, size_t bytes,
+                                    void *stream);
 
 /* ---- learned escape surrogate: mixture-density network --------------------------------
  *

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "rddmc_internal.h"
+#include "surrogate_dev.h"
 
 using namespace rddmc;
 
@@ -476,6 +477,7 @@ rddmc_status rddmc_tally(const rddmc_batch *batch, const void *d_tally, size_t t
             z.to_ddmc = w[TW_TO_DDMC];
             z.reflected = w[TW_REFLECTED];
             z.mc_steps = w[TW_MC_STEPS];
+            z.surrogate_calls = w[TW_SURR_CALLS];
             z.n_pix = c.n_pix;
         }
     }
@@ -510,6 +512,213 @@ rddmc_status rddmc_read_tables(const rddmc_batch *batch, const void *d_tables, i
         return hip_fail(e, "read lo words");
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
     return RDDMC_OK;
+}
+
+/* ---- learned escape surrogate: data, windows, per-state tables ------------------------- */
+
+namespace {
+
+// The surrogate window of one 1D cloud: interior cells of a uniform (k0, T) cloud whose
+// optical width, face geometry and Doppler shifts lie in the trained domain (the longest
+// contiguous run), times the contiguous bins around x = 0 with centres within x_core and
+// widths in the domain.  Empty (i_hi < i_lo) when nothing qualifies.
+SurrCloud surrogate_window(const rddmc_medium &m, const rddmc_surrogate_cfg &cfg)
+{
+    SurrCloud w{0, -1, 0, -1, 0, 0};
+    if (m.geometry != RDDMC_SLAB && m.geometry != RDDMC_SPHERE) return w;
+    const int nc = m.n_cells[0], nb = m.n_bins;
+    if (nc < 3) return w;
+    for (int i = 1; i < nc; ++i)
+        if (m.k0[i] != m.k0[0] || m.temp[i] != m.temp[0]) return w;
+    const double T = m.temp[0];
+    const double a = 4.702e-4 * std::sqrt(1.0e4 / T), vth = 12.85 * std::sqrt(T / 1.0e4);
+    if (!(a >= cfg.a_min && a <= cfg.a_max)) return w;
+    const double *f = m.faces[0];
+    int best_lo = 0, best_len = 0, run_lo = 0, run_len = 0;
+    for (int i = 1; i <= nc - 2; ++i) {
+        const double lo = f[i], hi = f[i + 1], wd = hi - lo;
+        const double tau = m.k0[i] * wd;
+        double g0 = 1.0, g1 = 1.0;
+        if (m.geometry == RDDMC_SPHERE) {
+            const double v3 = (hi * hi * hi - lo * lo * lo) / 3.0;
+            g0 = lo * lo / v3 * wd;
+            g1 = hi * hi / v3 * wd;
+        }
+        double s0 = 0.0, s1 = 0.0;
+        if (m.vel) {
+            s0 = -m.f_mu * (m.vel[i] - m.vel[i - 1]) / vth;
+            s1 = -m.f_mu * (m.vel[i + 1] - m.vel[i]) / vth;
+        }
+        const bool ok = tau >= cfg.tau_min && tau <= cfg.tau_max && g0 >= cfg.g_min && g0 <= cfg.g_max &&
+                        g1 >= cfg.g_min && g1 <= cfg.g_max && std::fabs(s0) <= cfg.shift_max &&
+                        std::fabs(s1) <= cfg.shift_max;
+        if (ok) {
+            if (run_len == 0) run_lo = i;
+            ++run_len;
+            if (run_len > best_len) {
+                best_len = run_len;
+                best_lo = run_lo;
+            }
+        } else {
+            run_len = 0;
+        }
+    }
+    if (best_len == 0) return w;
+    const double *e = m.bin_edges;
+    int j0 = 0;      // bin whose centre is nearest x = 0
+    for (int j = 1; j < nb; ++j)
+        if (std::fabs(0.5 * (e[j] + e[j + 1])) < std::fabs(0.5 * (e[j0] + e[j0 + 1]))) j0 = j;
+    auto bin_ok = [&](int j) {
+        const double c = 0.5 * (e[j] + e[j + 1]), dx = e[j + 1] - e[j];
+        return std::fabs(c) <= cfg.x_core && dx >= cfg.dx_min && dx <= cfg.dx_max;
+    };
+    if (!bin_ok(j0)) return w;
+    int jl = j0, jh = j0;
+    while (jl > 0 && bin_ok(jl - 1)) --jl;
+    while (jh < nb - 1 && bin_ok(jh + 1)) ++jh;
+    w.i_lo = best_lo;
+    w.i_hi = best_lo + best_len - 1;
+    w.j_lo = jl;
+    w.j_hi = jh;
+    return w;
+}
+
+struct SurrLayout {
+    SurrHeader h{};
+    std::vector<SurrCloud> clouds;
+    uint64_t off_x = 0, off_sw = 0, bytes = 0;
+};
+
+rddmc_status surrogate_layout(const rddmc_batch *b, const rddmc_surrogate_cfg *cfg, int64_t max_batch,
+                              SurrLayout &S)
+{
+    if (!cfg) return fail(RDDMC_EINVAL, "cfg is NULL");
+    if (max_batch < 1 || max_batch > (1ll << 24)) return fail(RDDMC_EINVAL, "max_batch must be in [1, 2^24]");
+    Layout L;
+    rddmc_status st = make_layout(b, L);
+    if (st != RDDMC_OK) return st;
+    const int n = b->n_clouds;
+    S.clouds.resize(n);
+    uint64_t rec = 0;
+    for (int c = 0; c < n; ++c) {
+        SurrCloud w = surrogate_window(b->clouds[c], *cfg);
+        w.rec_off = rec;
+        if (w.i_hi >= w.i_lo) rec += (uint64_t)(w.i_hi - w.i_lo + 1) * (w.j_hi - w.j_lo + 1);
+        S.clouds[c] = w;
+    }
+    const int64_t cap = (max_batch + 31) & ~31ll;
+    uint64_t off = align_up(sizeof(SurrHeader));
+    S.h.n_clouds = n;
+    S.h.off_clouds = off;
+    off = align_up(off + sizeof(SurrCloud) * n);
+    S.off_x = off;
+    off = align_up(off + 4ull * kSurrIn * cap);
+    S.off_sw = off;
+    off = align_up(off + 8ull * cap);
+    S.h.off_records = off;
+    S.h.n_records = rec;
+    S.bytes = off + 4ull * kSurrRec * rec;
+    return RDDMC_OK;
+}
+
+}  // namespace
+
+rddmc_status rddmc_surrogate_bytes(const rddmc_batch *batch, const rddmc_surrogate_cfg *cfg, int64_t max_batch,
+                                   size_t *bytes, uint64_t *n_states)
+{
+    if (!bytes) return fail(RDDMC_EINVAL, "bytes is NULL");
+    SurrLayout S;
+    rddmc_status st = surrogate_layout(batch, cfg, max_batch, S);
+    if (st != RDDMC_OK) return st;
+    *bytes = S.bytes;
+    if (n_states) *n_states = S.h.n_records;
+    return RDDMC_OK;
+}
+
+rddmc_status rddmc_surrogate_window(const rddmc_batch *batch, const rddmc_surrogate_cfg *cfg, int32_t cloud,
+                                    int32_t *window)
+{
+    if (!batch || !window || cloud < 0 || cloud >= batch->n_clouds) return fail(RDDMC_EINVAL, "bad arguments");
+    if (!cfg) return fail(RDDMC_EINVAL, "cfg is NULL");
+    const SurrCloud w = surrogate_window(batch->clouds[cloud], *cfg);
+    window[0] = w.i_lo;
+    window[1] = w.i_hi;
+    window[2] = w.j_lo;
+    window[3] = w.j_hi;
+    return RDDMC_OK;
+}
+
+rddmc_status rddmc_surrogate_attach(const rddmc_batch *batch, const void *d_tables, void *d_params, void *d_work,
+                                    int64_t max_batch, const rddmc_surrogate_cfg *cfg, void *d_surr, size_t bytes,
+                                    void *stream)
+{
+    SurrLayout S;
+    rddmc_status st = surrogate_layout(batch, cfg, max_batch, S);
+    if (st != RDDMC_OK) return st;
+    if (!d_tables || !d_params || !d_work || !d_surr) return fail(RDDMC_EINVAL, "NULL argument");
+    if ((uintptr_t)d_surr % kAlign) return fail(RDDMC_EINVAL, "d_surr must be 256-byte aligned");
+    if (bytes < S.bytes) return fail(RDDMC_ESIZE, "surrogate buffer %zu < required %llu", bytes,
+                                     (unsigned long long)S.bytes);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    std::vector<uint8_t> hdr(S.off_x, 0);
+    std::memcpy(hdr.data(), &S.h, sizeof S.h);
+    std::memcpy(hdr.data() + S.h.off_clouds, S.clouds.data(), sizeof(SurrCloud) * S.clouds.size());
+    uint8_t *base = static_cast<uint8_t *>(d_surr);
+    hipError_t e = hipMemcpyAsync(base, hdr.data(), hdr.size(), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(surrogate header)");
+    const int64_t cap = (max_batch + 31) & ~31ll;
+    float *X = reinterpret_cast<float *>(base + S.off_x);
+    float *SW = reinterpret_cast<float *>(base + S.off_sw);
+    float *R = reinterpret_cast<float *>(base + S.h.off_records);
+    for (uint64_t first = 0; first < S.h.n_records; first += (uint64_t)max_batch) {
+        const uint64_t cnt = std::min<uint64_t>((uint64_t)max_batch, S.h.n_records - first);
+        if ((e = launch_surr_features(static_cast<const uint8_t *>(d_tables), base, first, cnt, X, SW, s)) !=
+            hipSuccess)
+            return hip_fail(e, "surrogate features");
+        if ((e = mdn_forward(d_params, d_work, cap, X, (int)cnt, nullptr, s)) != hipSuccess)
+            return hip_fail(e, "surrogate inference");
+        if ((e = launch_surr_records(mdn_outputs(d_work, cap), SW, cnt, R + first * kSurrRec, s)) != hipSuccess)
+            return hip_fail(e, "surrogate records");
+    }
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    return RDDMC_OK;
+}
+
+rddmc_status rddmc_surrogate_samples(const rddmc_batch *batch, const void *d_tables, const int32_t *h_cloud,
+                                     const int32_t *h_state, int64_t n, uint64_t seed, uint64_t max_steps,
+                                     void *d_scratch, size_t scratch_bytes, float *d_x, float *d_y,
+                                     uint64_t *d_steps, void *stream)
+{
+    Layout L;
+    rddmc_status st = make_layout(batch, L);
+    if (st != RDDMC_OK) return st;
+    if (!d_tables || !h_cloud || !h_state || !d_scratch || !d_x || !d_y || !d_steps)
+        return fail(RDDMC_EINVAL, "NULL argument");
+    if (n < 1) return fail(RDDMC_EINVAL, "n < 1");
+    if (scratch_bytes < 8ull * (uint64_t)n) return fail(RDDMC_ESIZE, "scratch needs 8 n bytes");
+    if (max_steps < 1) return fail(RDDMC_EINVAL, "max_steps must be >= 1");
+    if (L.h.geometry == RDDMC_CART3D) return fail(RDDMC_EUNSUPPORTED, "sub-walk data is built for 1D clouds");
+    bool moving = false;
+    for (int64_t q = 0; q < n; ++q) {
+        const int c = h_cloud[q];
+        if (c < 0 || c >= batch->n_clouds) return fail(RDDMC_EINVAL, "sample %lld: bad cloud", (long long)q);
+        const DevCloud &dc = L.clouds[c];
+        const int i = h_state[q] / dc.nb;
+        if (h_state[q] < 0 || (uint64_t)h_state[q] >= dc.n_states || i < 1 || i > dc.nc - 2)
+            return fail(RDDMC_EINVAL, "sample %lld: the start state must lie in a cell with two neighbours",
+                        (long long)q);
+        moving |= dc.moving != 0;
+    }
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    int32_t *dc = static_cast<int32_t *>(d_scratch);
+    int32_t *ds = dc + n;
+    hipError_t e = hipMemcpyAsync(dc, h_cloud, 4ull * n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(ds, h_state, 4ull * n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = launch_subwalk(static_cast<const uint8_t *>(d_tables), moving, seed, max_steps, dc, ds, n, d_x, d_y,
+                           reinterpret_cast<unsigned long long *>(d_steps), s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);   // the host start arrays are read asynchronously
+    return e == hipSuccess ? RDDMC_OK : hip_fail(e, "sub-walk kernel");
 }
 
 /* ---- mixture-density network of the escape surrogate --------------------------------- */

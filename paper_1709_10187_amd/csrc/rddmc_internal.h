@@ -26,6 +26,7 @@ enum TallyWord {
     TW_TO_DDMC = 9,   //         MC -> DDMC conversions
     TW_REFLECTED = 10,//         MC packets reflected at a thick interface
     TW_MC_STEPS = 11, //         MC events (scatterings and face crossings)
+    TW_SURR_CALLS = 12, // exits drawn from the learned surrogate
 };
 
 // 3D cells: the fourth word of the hot record holds flags instead of F.
@@ -116,6 +117,12 @@ hipError_t launch_walk(const uint8_t *d_tables, const DevHeader &h, const DevClo
                        unsigned long long *d_tally, unsigned long long *d_work, uint64_t work_bytes,
                        hipStream_t s);
 hipError_t launch_zero(void *d, size_t words64, hipStream_t s);
+hipError_t launch_subwalk(const uint8_t *d_tables, bool moving, uint64_t seed, uint64_t max_steps,
+                          const int32_t *d_cloud, const int32_t *d_state, int64_t n, float *d_x, float *d_y,
+                          unsigned long long *d_steps, hipStream_t s);
+hipError_t launch_surr_features(const uint8_t *d_tables, const uint8_t *d_surr, uint64_t first, uint64_t count,
+                                float *d_x, float *d_sw, hipStream_t s);
+hipError_t launch_surr_records(const float *d_out, const float *d_sw, uint64_t count, float *d_rec, hipStream_t s);
 // mixture-density network (mdn.hip)
 uint64_t mdn_param_bytes();
 uint64_t mdn_work_bytes(int64_t cap);

@@ -21,6 +21,7 @@
 
 #include "philox.h"
 #include "rddmc_internal.h"
+#include "surrogate_dev.h"
 
 namespace rddmc {
 
@@ -36,6 +37,7 @@ struct WalkArgs {
     int32_t tail_lanes;    // export a wave's packets once the queue is empty and <= this many remain
     int32_t pad;
     uint64_t tail_capacity;
+    const uint8_t *surr;   // learned escape surrogate (windows and records) or null
 };
 
 // Work area: u64 words [0] packet queue counter, [1] exported packets, [2] next exported
@@ -52,6 +54,8 @@ struct TailPacket {        // 32 bytes
 // Domain tags in the second counter word (high bits of the step index never reach them).
 constexpr uint32_t kDomAux = 0x80000000u;   // extra draws inside step k (re-binning, escape)
 constexpr uint32_t kDomEmit = 0xC0000000u;  // emission draw
+constexpr uint32_t kDomSurr = 0x40000000u;  // surrogate exit draws (per pair slot)
+constexpr uint32_t kDomSub = 0x20000000u;   // sub-walk data: exit frequency inside the exit bin
 
 __device__ __forceinline__ double u01_open_low(uint32_t r)
 {   // (r + 0.5) / 2^32 in (0, 1)
@@ -135,7 +139,72 @@ struct Packet1D {
     bool uniform;
     bool moving;               // the cloud has bulk velocity (one Philox block per step)
     bool active;
+    uint32_t surr_calls;       // exits taken from the learned surrogate
 };
+
+// The cloud's surrogate window (empty: i_hi < i_lo).
+struct SurrWin {
+    int i_lo, i_hi, j_lo, j_hi;
+    uint64_t rec_off;
+};
+
+__device__ __forceinline__ bool in_window(const Packet1D &p, const SurrWin &w)
+{
+    return (unsigned)(p.i - w.i_lo) <= (unsigned)(w.i_hi - w.i_lo) &&
+           (unsigned)(p.j - w.j_lo) <= (unsigned)(w.j_hi - w.j_lo);
+}
+
+// Replace the rest of the packet's walk inside its cell by one exit drawn from the learned
+// law of the state: mixture component, face, then (y1, y2) from the component's correlated
+// Gaussian; x_out = S sinh(y1) in the cell's frame, dt = w exp(y2).  The exit crosses the
+// face like a spatial leak (Doppler map of eq. 20 applied to x_out).  It takes a whole
+// Philox pair slot (the step count is rounded up to even, then advanced by 2), drawn in
+// its own counter domain.
+template <bool MOVING>
+__device__ void surrogate_exit(Packet1D &p, const SurrWin &sw, const float *__restrict__ recs,
+                               const uint8_t *__restrict__ tb, const DevCloud &c, const WalkArgs &a)
+{
+    p.steps = (p.steps + 1ull) & ~1ull;
+    const uint64_t pair = p.steps >> 1;
+    const u32x4 r = philox4x32_10((uint32_t)pair, kDomSurr | (uint32_t)(pair >> 32), p.pid, p.key, a.key0, a.key1);
+    const int64_t idx = (int64_t)sw.rec_off + (int64_t)(p.i - sw.i_lo) * (sw.j_hi - sw.j_lo + 1) + (p.j - sw.j_lo);
+    const float *q = recs + idx * kSurrRec;
+    const float u0 = ((float)(r.x >> 8) + 0.5f) * 5.9604644775390625e-8f;
+    int k = 0;
+    while (k < 15 && u0 >= q[kRecCdf + k]) ++k;
+    const float uf = ((float)(r.y >> 8) + 0.5f) * 5.9604644775390625e-8f;
+    const int face = uf < q[kRecPf0 + k] ? 0 : 1;
+    const float ua = ((float)(r.z >> 8) + 0.5f) * 5.9604644775390625e-8f;
+    const float ub = ((float)(r.w >> 8) + 0.5f) * 5.9604644775390625e-8f;
+    const float rad = sqrtf(-2.0f * __logf(ua));
+    float sn, cs;
+    sincosf(6.28318530717959f * ub, &sn, &cs);
+    const float n1 = rad * cs, n2 = rad * sn;
+    const float rho = q[kRecRho + k];
+    float y1 = fmaf(q[kRecSg1 + k], n1, q[kRecMu1 + k]);
+    float y2 = q[kRecMu2 + k] + q[kRecSg2 + k] * fmaf(rho, n1, sqrtf(fmaxf(0.0f, 1.0f - rho * rho)) * n2);
+    y1 = fminf(fmaxf(y1, -20.0f), 20.0f);
+    y2 = fminf(y2, 80.0f);
+    const float xo = q[kRecS] * sinhf(y1);
+    p.t += (double)(q[kRecW] * __expf(y2));
+    float xn = xo;
+    if (MOVING && p.moving) {
+        const float4 cm = p.cmap[p.i];
+        xn = fmaf(face ? cm.z : cm.x, xo, face ? cm.w : cm.y);
+    }
+    int jn;
+    if (p.uniform) {
+        const float fj = (xn - p.x0) * p.inv_dx;
+        jn = !(fj >= 0.0f) ? 0 : (fj >= (float)(p.nb - 1) ? p.nb - 1 : (int)fj);
+    } else {
+        jn = locate_bin(reinterpret_cast<const double *>(tb + c.off_edges), p.nb, (double)xn);
+        jn = jn < 0 ? 0 : (jn > p.nb - 1 ? p.nb - 1 : jn);
+    }
+    p.j = jn;
+    p.i += face ? 1 : -1;
+    p.steps += 2ull;
+    ++p.surr_calls;
+}
 
 // Random words of one step.  Static clouds: one Philox block serves two steps (time and
 // event words); moving clouds: one block per step (time, event, re-binning, escape mu).
@@ -269,11 +338,14 @@ __device__ void single_steps(Packet1D &p, int n, const uint8_t *__restrict__ tb,
 // escape frequencies.  Static media take one Philox block per pair of steps ((x, y) for the
 // even step and (z, w) for the odd one; all active lanes of a wave are at even step counts
 // between pairs); moving media take one block per step.
-template <bool MOVING>
+template <bool MOVING, bool SURR>
 __global__ __launch_bounds__(256) void walk1d(const uint8_t *__restrict__ tb, WalkArgs a,
                                               unsigned long long *__restrict__ tally,
                                               unsigned long long *__restrict__ work)
 {
+    const SurrHeader *SH = SURR ? reinterpret_cast<const SurrHeader *>(a.surr) : nullptr;
+    const float *recs = SURR ? reinterpret_cast<const float *>(a.surr + SH->off_records) : nullptr;
+    SurrWin sw{0, -1, 0, -1, 0ull};
     const DevHeader *H = reinterpret_cast<const DevHeader *>(tb);
     const DevCloud *clouds = reinterpret_cast<const DevCloud *>(tb + H->off_clouds);
     const uint64_t *prefix = reinterpret_cast<const uint64_t *>(tb + H->off_prefix);
@@ -285,6 +357,7 @@ __global__ __launch_bounds__(256) void walk1d(const uint8_t *__restrict__ tb, Wa
     p.hot = nullptr;
     p.cmap = nullptr;
     p.x0 = 0.f; p.dx = 1.f; p.inv_dx = 1.f; p.uniform = false; p.moving = false;
+    p.surr_calls = 0u;
     int last_state = 0;
     bool exhausted = false;       // wave-uniform: the queue is empty
 
@@ -337,6 +410,11 @@ __global__ __launch_bounds__(256) void walk1d(const uint8_t *__restrict__ tb, Wa
                         p.t = 0.0;
                         p.steps = 0;
                         p.active = true;
+                        p.surr_calls = 0u;
+                        if (SURR) {
+                            const SurrCloud *scl = reinterpret_cast<const SurrCloud *>(a.surr + SH->off_clouds) + lo;
+                            sw = SurrWin{scl->i_lo, scl->i_hi, scl->j_lo, scl->j_hi, scl->rec_off};
+                        }
                         atomicAdd(&tally[c.tally_off + TW_LAUNCHED], 1ull);
                     }
                 }
@@ -369,11 +447,19 @@ __global__ __launch_bounds__(256) void walk1d(const uint8_t *__restrict__ tb, Wa
         }
 
         // ---- walk up to `chunk` pairs of steps ---------------------------------------
+        const bool was_active = p.active;
         const uint64_t left = p.active ? (a.max_steps - p.steps) : 0ull;
         if (!(MOVING && p.moving)) {
             const uint64_t pairs = (left + 1) >> 1;
             const int budget = pairs < (uint64_t)a.chunk ? (int)pairs : a.chunk;
             for (int k = 0; k < budget; ++k) {
+                if (SURR) {
+                    if (p.steps >= a.max_steps) break;
+                    if (p.steps + 3ull <= a.max_steps && in_window(p, sw)) {
+                        surrogate_exit<MOVING>(p, sw, recs, tb, clouds[p.cl], a);
+                        continue;
+                    }
+                }
                 const int s = p.i * p.nb + p.j;
                 const uint4 rm = p.hot[s > 0 ? s - 1 : 0];
                 const uint4 r0 = p.hot[s];
@@ -396,6 +482,13 @@ __global__ __launch_bounds__(256) void walk1d(const uint8_t *__restrict__ tb, Wa
             const uint64_t lim = 2ull * (uint64_t)a.chunk;
             const int budget = left < lim ? (int)left : (int)lim;
             for (int k = 0; k < budget; ++k) {
+                if (SURR) {
+                    if (p.steps >= a.max_steps) break;
+                    if (p.steps + 3ull <= a.max_steps && in_window(p, sw)) {
+                        surrogate_exit<MOVING>(p, sw, recs, tb, clouds[p.cl], a);
+                        continue;
+                    }
+                }
                 const uint4 rec = p.hot[p.i * p.nb + p.j];
                 const float4 cm = p.cmap[p.i];
                 const u32x4 r = philox4x32_10((uint32_t)p.steps, (uint32_t)(p.steps >> 32), p.pid, p.key,
@@ -408,6 +501,8 @@ __global__ __launch_bounds__(256) void walk1d(const uint8_t *__restrict__ tb, Wa
             tally_finish(tally, clouds[p.cl], false, 0, 0, p.t, p.steps);
             p.active = false;
         }
+        if (SURR && was_active && !p.active && p.surr_calls)
+            atomicAdd(&tally[clouds[p.cl].tally_off + TW_SURR_CALLS], (unsigned long long)p.surr_calls);
     }
 }
 
@@ -563,6 +658,68 @@ __global__ __launch_bounds__(64) void walk1d_coop(const uint8_t *__restrict__ tb
     }
 }
 
+// Sub-walks for the surrogate's training data: sample q starts in state s_state[q] of
+// cloud s_cloud[q] (a cell with two neighbours) and takes DDMC steps until its first
+// spatial leak.  Writes the state's features X[q, 16] and the exit Y[q] = (face, y1, y2),
+// face -1 when max_steps ran out first, and the number of steps.
+template <bool MOVING>
+__global__ __launch_bounds__(256) void subwalk1d(const uint8_t *__restrict__ tb, WalkArgs a,
+                                                 const int32_t *__restrict__ s_cloud,
+                                                 const int32_t *__restrict__ s_state, int64_t n,
+                                                 float *__restrict__ X, float *__restrict__ Y,
+                                                 unsigned long long *__restrict__ steps_out)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const DevHeader *H = reinterpret_cast<const DevHeader *>(tb);
+    const DevCloud *clouds = reinterpret_cast<const DevCloud *>(tb + H->off_clouds);
+    const int cl = s_cloud[q];
+    const DevCloud &c = clouds[cl];
+    Packet1D p;
+    p.cl = cl;
+    p.nb = c.nb;
+    p.nc = c.nc;
+    p.geom = c.geometry;
+    p.pid = (uint32_t)q;
+    p.key = c.stream;
+    p.i = s_state[q] / c.nb;
+    p.j = s_state[q] - p.i * c.nb;
+    p.t = 0.0;
+    p.steps = 0;
+    p.hot = reinterpret_cast<const uint4 *>(tb + c.off_hot);
+    p.cmap = reinterpret_cast<const float4 *>(tb + c.off_cmap);
+    p.x0 = c.x0;
+    p.dx = c.dx;
+    p.inv_dx = c.inv_dx;
+    p.uniform = c.uniform_bins != 0;
+    p.moving = c.moving != 0;
+    p.active = true;
+    p.surr_calls = 0u;
+    float f[kSurrIn], S, w;
+    surr_features(c, tb, p.i, p.j, f, S, w);
+    for (int k = 0; k < kSurrIn; ++k) X[q * kSurrIn + k] = f[k];
+    int face = -1, jexit = p.j;
+    while (p.steps < a.max_steps) {
+        const int i0 = p.i, j0 = p.j;
+        const StepWords wd = words_of_step<MOVING>(p, p.steps, a);
+        const uint4 rec = p.hot[p.i * p.nb + p.j];
+        const float4 cm = (MOVING && p.moving) ? p.cmap[p.i] : make_float4(1.f, 0.f, 1.f, 0.f);
+        one_step<MOVING>(p, wd, rec, cm, tb, clouds, a, nullptr);
+        if (p.i != i0) {
+            face = p.i > i0 ? 1 : 0;
+            jexit = j0;
+            break;
+        }
+    }
+    const double *e = reinterpret_cast<const double *>(tb + c.off_edges);
+    const u32x4 r = philox4x32_10((uint32_t)q, kDomSub | (uint32_t)((uint64_t)q >> 32), p.pid, p.key, a.key0, a.key1);
+    const double xo = e[jexit] + (e[jexit + 1] - e[jexit]) * u01_open_low(r.x);
+    Y[3 * q] = (float)face;
+    Y[3 * q + 1] = (float)asinh(xo / (double)S);
+    Y[3 * q + 2] = (float)log(p.t / (double)w);
+    steps_out[q] = p.steps;
+}
+
 __global__ void philox_fill_kernel(uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1, uint32_t c2,
                                    uint32_t c3, uint64_t n, uint32_t *out)
 {
@@ -626,11 +783,17 @@ hipError_t launch_walk(const uint8_t *d_tables, const DevHeader &h, const DevClo
     }
     bool moving = false;
     for (int c = 0; c < h.n_clouds; ++c) moving |= host_clouds[c].moving != 0;
+    a.surr = static_cast<const uint8_t *>(run.surrogate);
+    if (a.surr) a.tail_lanes = 0;   // the cooperative tail walk has no surrogate exits
     reset_work<<<1, 64, 0, s>>>(d_work);
-    if (moving)
-        walk1d<true><<<(unsigned)grid, block, 0, s>>>(d_tables, a, d_tally, d_work);
+    if (moving && a.surr)
+        walk1d<true, true><<<(unsigned)grid, block, 0, s>>>(d_tables, a, d_tally, d_work);
+    else if (moving)
+        walk1d<true, false><<<(unsigned)grid, block, 0, s>>>(d_tables, a, d_tally, d_work);
+    else if (a.surr)
+        walk1d<false, true><<<(unsigned)grid, block, 0, s>>>(d_tables, a, d_tally, d_work);
     else
-        walk1d<false><<<(unsigned)grid, block, 0, s>>>(d_tables, a, d_tally, d_work);
+        walk1d<false, false><<<(unsigned)grid, block, 0, s>>>(d_tables, a, d_tally, d_work);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || a.tail_lanes == 0) return e;
     const unsigned cgrid = (unsigned)device_cu_count() * 16;   // one wave per block
@@ -638,6 +801,22 @@ hipError_t launch_walk(const uint8_t *d_tables, const DevHeader &h, const DevClo
         walk1d_coop<true><<<cgrid, 64, 0, s>>>(d_tables, a, d_tally, d_work);
     else
         walk1d_coop<false><<<cgrid, 64, 0, s>>>(d_tables, a, d_tally, d_work);
+    return hipGetLastError();
+}
+
+hipError_t launch_subwalk(const uint8_t *d_tables, bool moving, uint64_t seed, uint64_t max_steps,
+                          const int32_t *d_cloud, const int32_t *d_state, int64_t n, float *d_x, float *d_y,
+                          unsigned long long *d_steps, hipStream_t s)
+{
+    WalkArgs a{};
+    a.max_steps = max_steps;
+    a.key0 = (uint32_t)seed;
+    a.key1 = (uint32_t)(seed >> 32);
+    const unsigned grid = (unsigned)((n + 255) / 256);
+    if (moving)
+        subwalk1d<true><<<grid, 256, 0, s>>>(d_tables, a, d_cloud, d_state, n, d_x, d_y, d_steps);
+    else
+        subwalk1d<false><<<grid, 256, 0, s>>>(d_tables, a, d_cloud, d_state, n, d_x, d_y, d_steps);
     return hipGetLastError();
 }
 

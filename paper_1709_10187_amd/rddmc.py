@@ -48,7 +48,13 @@ class Batch_t(C.Structure):
 class Run_t(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("first", C.c_uint64), ("count", C.c_uint64),
                 ("max_steps", C.c_uint64), ("block", C.c_int32), ("grid", C.c_int32),
-                ("chunk", C.c_int32), ("tail_lanes", C.c_int32)]
+                ("chunk", C.c_int32), ("tail_lanes", C.c_int32), ("surrogate", C.c_void_p)]
+
+
+class SurrogateCfg_t(C.Structure):
+    _fields_ = [("tau_min", C.c_double), ("tau_max", C.c_double), ("a_min", C.c_double), ("a_max", C.c_double),
+                ("dx_min", C.c_double), ("dx_max", C.c_double), ("shift_max", C.c_double),
+                ("g_min", C.c_double), ("g_max", C.c_double), ("x_core", C.c_double)]
 
 
 class CloudStats_t(C.Structure):
@@ -56,7 +62,8 @@ class CloudStats_t(C.Structure):
                 ("steps_total", C.c_uint64), ("steps_max", C.c_uint64), ("steps_mean", C.c_double),
                 ("t_mean", C.c_double), ("t_var", C.c_double), ("n_rows", C.c_int32),
                 ("n_slots", C.c_int32), ("to_mc", C.c_uint64), ("to_ddmc", C.c_uint64),
-                ("reflected", C.c_uint64), ("mc_steps", C.c_uint64), ("n_pix", C.c_uint64)]
+                ("reflected", C.c_uint64), ("mc_steps", C.c_uint64), ("n_pix", C.c_uint64),
+                ("surrogate_calls", C.c_uint64)]
 
 
 class TallyOut_t(C.Structure):
@@ -65,13 +72,14 @@ class TallyOut_t(C.Structure):
                 ("pixels", C.POINTER(C.c_void_p))]
 
 
-ABI_VERSION = 2
+ABI_VERSION = 3
 
 
 EXPORTS = ["rddmc_abi_version", "rddmc_last_error", "rddmc_table_bytes", "rddmc_tally_bytes",
            "rddmc_work_bytes", "rddmc_build_leakage", "rddmc_transport", "rddmc_tally_reset",
            "rddmc_tally", "rddmc_read_tables", "rddmc_philox_fill", "rddmc_mdn_bytes", "rddmc_mdn_init",
-           "rddmc_mdn_set", "rddmc_mdn_get", "rddmc_mdn_forward", "rddmc_mdn_loss_grad", "rddmc_mdn_adam"]
+           "rddmc_mdn_set", "rddmc_mdn_get", "rddmc_mdn_forward", "rddmc_mdn_loss_grad", "rddmc_mdn_adam",
+           "rddmc_surrogate_samples", "rddmc_surrogate_bytes", "rddmc_surrogate_window", "rddmc_surrogate_attach"]
 
 _lib = None
 
@@ -105,10 +113,18 @@ def load(path: str = LIB_PATH):
     lib.rddmc_mdn_forward.argtypes = [vp, vp, C.c_int64, vp, C.c_int32, vp, vp]
     lib.rddmc_mdn_loss_grad.argtypes = [vp, vp, C.c_int64, vp, vp, C.c_int32, vp, vp]
     lib.rddmc_mdn_adam.argtypes = [vp, C.c_int64, C.c_float, vp]
+    cfgp = C.POINTER(SurrogateCfg_t)
+    lib.rddmc_surrogate_samples.argtypes = [C.POINTER(Batch_t), vp, vp, vp, C.c_int64, C.c_uint64, C.c_uint64,
+                                            vp, sz, vp, vp, vp, vp]
+    lib.rddmc_surrogate_bytes.argtypes = [C.POINTER(Batch_t), cfgp, C.c_int64, C.POINTER(sz),
+                                          C.POINTER(C.c_uint64)]
+    lib.rddmc_surrogate_window.argtypes = [C.POINTER(Batch_t), cfgp, C.c_int32, vp]
+    lib.rddmc_surrogate_attach.argtypes = [C.POINTER(Batch_t), vp, vp, vp, C.c_int64, cfgp, vp, sz, vp]
     for name in ("rddmc_build_leakage", "rddmc_transport", "rddmc_tally_reset", "rddmc_tally",
                  "rddmc_read_tables", "rddmc_philox_fill", "rddmc_mdn_bytes", "rddmc_mdn_init",
                  "rddmc_mdn_set", "rddmc_mdn_get", "rddmc_mdn_forward", "rddmc_mdn_loss_grad",
-                 "rddmc_mdn_adam"):
+                 "rddmc_mdn_adam", "rddmc_surrogate_samples", "rddmc_surrogate_bytes",
+                 "rddmc_surrogate_window", "rddmc_surrogate_attach"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -207,10 +223,10 @@ def tally_reset(b: Batch, d_tally, stream=None):
 
 
 def transport(b: Batch, d_tables, d_tally, d_work, seed=0, first=0, count=0, max_steps=(1 << 62),
-              block=0, grid=0, chunk=0, tail_lanes=0, stream=None):
+              block=0, grid=0, chunk=0, tail_lanes=0, stream=None, surrogate=None):
     lib = load()
     run = Run_t(int(seed), int(first), int(count), int(max_steps), int(block), int(grid), int(chunk),
-                int(tail_lanes))
+                int(tail_lanes), C.c_void_p(surrogate.data_ptr()) if surrogate is not None else None)
     _check(lib.rddmc_transport(b.ref(), C.c_void_p(d_tables.data_ptr()), C.byref(run),
                                C.c_void_p(d_tally.data_ptr()), d_tally.numel() * d_tally.element_size(),
                                C.c_void_p(d_work.data_ptr()), d_work.numel() * d_work.element_size(),
@@ -235,6 +251,7 @@ class CloudTally:
     reflected: int = 0
     mc_steps: int = 0
     pixels: Optional[np.ndarray] = None   # 3D: escape counts per boundary cell (see include/rddmc.h)
+    surrogate_calls: int = 0
 
 
 def n_pixels(m) -> int:
@@ -264,7 +281,7 @@ def tally(b: Batch, d_tally, stream=None) -> List[CloudTally]:
         z = stats[i]
         res.append(CloudTally(specs[i], th[i], sh[i], z.launched, z.escaped, z.capped, z.steps_total,
                               z.steps_max, z.steps_mean, z.t_mean, z.t_var, z.to_mc, z.to_ddmc, z.reflected,
-                              z.mc_steps, pix[i] if pix[i].size else None))
+                              z.mc_steps, pix[i] if pix[i].size else None, z.surrogate_calls))
     return res
 
 

@@ -35,7 +35,7 @@ def _merge(expected_counts, *arrays, min_count=10.0):
 def compare_exact(counts, p, n=None):
     """counts: observed integer counts per slot; p: exact probabilities per slot."""
     counts = np.asarray(counts, dtype=np.float64).ravel()
-    p = np.asarray(p, dtype=np.float64).ravel()
+    p = np.maximum(np.asarray(p, dtype=np.float64).ravel(), 0.0)   # exact zeros may round to -1e-17
     N = counts.sum() if n is None else n
     c, q = _merge(p * N, counts, p)
     f = c / N
