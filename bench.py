@@ -7,6 +7,13 @@ contiguous block of that job's packet ids (block k = ids [k B, (k+1) B)) through
 whole hot path: every leakage step, re-binning, escape and tally of those packets runs
 inside the timed rddmc_transport launch; the tables are built (untimed) once before.
 
+Other workloads (``--workload``):
+  cube       the 128^3 lognormal cube (256 bins of 25 km/s, hybrid DDMC / MC at tau = 10,
+             2^24 packets from the 64 densest cells): one block of packet ids;
+  surrogate  the learned escape surrogate: sub-walk data and training on the GPU (timed
+             apart), then the sweep clouds inside the trained domain as one batch, with
+             the surrogate and plain, same packet ids, packets/s of each.
+
 Prints one JSON line.  ``--gpus`` must be 1 (the path runs on one GPU).
 """
 import argparse
@@ -43,7 +50,110 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-packets", type=int, default=12)
     ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--workload", choices=["sphere", "cube", "surrogate"], default="sphere")
+    ap.add_argument("--tail-lanes", type=int, default=0,
+                    help="hand a wave's packets to the cooperative walk at <= this many (0 = library default)")
+    ap.add_argument("--surrogate-packets", type=int, default=2048, help="packets per cloud, surrogate run")
+    ap.add_argument("--plain-packets", type=int, default=256, help="packets per cloud, plain run")
     return ap.parse_args()
+
+
+def _timed(prob, **kw):
+    import torch
+    stream = torch.cuda.current_stream()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    prob.run(**kw)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop) / 1e3
+
+
+def bench_cube(args):
+    """128^3 hybrid cube: one block of packet ids (the hot path is walk3d)."""
+    from paper_1709_10187_amd import media, rddmc
+    m = media.cube()
+    B = int(args.block_packets)
+    print(f"[bench] building tables for the 128^3 x 256 cube", file=sys.stderr, flush=True)
+    prob = rddmc.Problem(m)
+    sec = 0.0
+    for k in range(args.steps):
+        sec += _timed(prob, seed=0, first=k * B, count=B)
+    res = prob.results()[0]
+    ddmc = res.steps_total - res.mc_steps
+    return {
+        "metric": METRIC, "value": res.launched / sec, "unit": "packets/s",
+        "packet_steps_per_s": res.steps_total / sec, "n_gpus": 1, "steps": args.steps, "warmup": 0,
+        "ms_per_step": 1e3 * sec / args.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "3D cube 128^3 lognormal (sigma_ln 1, mean tau_cell 1e3), T=1e4K, 20 km/s "
+                               "Gaussian velocities, 256 bins of 25 km/s, hybrid at tau_th=10, 64 densest-cell "
+                               f"sources, job of 2^24 packets; timed: {args.steps} block(s) of {B} ids",
+                   "packets_timed": int(res.launched), "steps_mean": res.steps_mean,
+                   "ddmc_steps": int(ddmc), "mc_events": int(res.mc_steps), "to_mc": int(res.to_mc),
+                   "to_ddmc": int(res.to_ddmc), "reflected": int(res.reflected), "t_mean": res.t_mean,
+                   "table_gib": prob.tables.numel() / 2 ** 30},
+        "roofline": None,
+    }
+
+
+# Sweep clouds (media.sweep_parameters(), 256 clouds) with cells in the surrogate's trained
+# domain whose plain rDDMC walk takes <= 5e7 expected steps per packet (exact-chain values;
+# the 10 costlier in-domain clouds, up to 5e8 steps per packet, would make the plain leg's
+# slowest packets run for minutes).
+SURROGATE_CLOUDS = [9, 18, 48, 58, 68, 74, 75, 96, 101, 103, 125, 131, 144, 149, 151, 155, 156, 176, 181, 184,
+                    188, 195, 199, 203, 205, 226, 235, 250]
+
+
+def bench_surrogate(args):
+    """Learned escape surrogate against plain rDDMC on the in-domain sweep clouds."""
+    import torch
+    from paper_1709_10187_amd import media, rddmc
+    from paper_1709_10187_amd import surrogate as sg
+    dom = sg.Domain(tau_min=1.0e5, tau_max=1.0e6, dx_min=0.5, dx_max=4.5)
+    t0 = time.perf_counter()
+    probes = sg.sample_probes(2048, dom, seed=11)
+    print("[bench] surrogate: 2048 x 128 sub-walks", file=sys.stderr, flush=True)
+    data = sg.generate(probes, 128, dom, seed=12, max_steps=1 << 30)
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    net = rddmc.Mdn(max_batch=4096, seed=0)
+    t1 = time.perf_counter()
+    print(f"[bench] surrogate: training on {data.n} samples", file=sys.stderr, flush=True)
+    hist = sg.train(net, data, epochs=60, lr=2e-3, lr_final=1e-4)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    clouds = [media.sweep_cloud_medium(c) for c in media.sweep_parameters()]
+    ids = [i for i in SURROGATE_CLOUDS if sg.window(clouds[i], dom)[1] >= sg.window(clouds[i], dom)[0]]
+    surr = rddmc.Problem([clouds[i].with_packets(args.surrogate_packets) for i in ids], streams=ids)
+    att = sg.Attached(surr, net, dom)
+    print(f"[bench] surrogate: {len(ids)} clouds, {att.n_states} window states", file=sys.stderr, flush=True)
+    ts = _timed(surr, seed=1, surrogate=att.buffer)
+    rs = surr.results()
+    plain = rddmc.Problem([clouds[i].with_packets(args.plain_packets) for i in ids], streams=ids)
+    print("[bench] plain rDDMC on the same clouds", file=sys.stderr, flush=True)
+    tp = _timed(plain, seed=1)
+    rp = plain.results()
+    ns, npl = sum(r.launched for r in rs), sum(r.launched for r in rp)
+    v_s, v_p = ns / ts, npl / tp
+    return {
+        "metric": METRIC, "value": v_s, "unit": "packets/s", "plain_packets_per_s": v_p, "speedup": v_s / v_p,
+        "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": 1e3 * ts, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16 network (f32 accumulate), f32 walk",
+        "data": "synthetic",
+        "config": {"workload": f"{len(ids)} sweep clouds with cells in the trained domain and <= 5e7 plain steps/packet "
+                               f"(tau_c {dom.tau_min:g}-{dom.tau_max:g}, dx {dom.dx_min}-{dom.dx_max}), one batch; "
+                               f"{args.surrogate_packets} packets per cloud with the surrogate, "
+                               f"{args.plain_packets} plain",
+                   "clouds": ids, "window_states": int(att.n_states),
+                   "surrogate_calls_per_packet": sum(r.surrogate_calls for r in rs) / ns,
+                   "steps_per_packet_surrogate": sum(r.steps_total for r in rs) / ns,
+                   "steps_per_packet_plain": sum(r.steps_total for r in rp) / npl,
+                   "data_s": t_data, "train_s": t_train, "train_samples": data.n, "final_nll": hist[-1],
+                   "accuracy": "spectrum vs the exact chain in tests/test_gpu_surrogate.py"},
+        "roofline": None,
+    }
 
 
 def cpu_baseline(m, n_packets, threads):
@@ -69,6 +179,10 @@ def main():
     from paper_1709_10187_amd import media, rddmc
     assert torch.cuda.is_available()
     torch.cuda.set_device(0)
+    if args.workload != "sphere":
+        out = bench_cube(args) if args.workload == "cube" else bench_surrogate(args)
+        print(json.dumps(out))
+        return
     m = media.config_sphere()
     B = int(args.block_packets)
     n_blocks = m.n_packets // B
@@ -81,7 +195,7 @@ def main():
     for w in range(args.warmup):
         first = (n_blocks - 1 - w) * B
         print(f"[bench] warmup block {w} (ids {first}..{first + B - 1})", file=sys.stderr, flush=True)
-        prob.run(seed=0, first=first, count=B)
+        prob.run(seed=0, first=first, count=B, tail_lanes=args.tail_lanes)
         torch.cuda.synchronize()
     prob.reset()
     torch.cuda.synchronize()
@@ -89,7 +203,10 @@ def main():
     t0 = time.perf_counter()
     start.record(stream)
     for k in range(args.steps):
-        prob.run(seed=0, first=k * B, count=B)
+        prob.run(seed=0, first=k * B, count=B, tail_lanes=args.tail_lanes)
+        if args.steps > 1:   # the block has finished: report it (the next block starts at once)
+            torch.cuda.synchronize()
+            print(f"[bench] block {k} done ({time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
     stop.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
