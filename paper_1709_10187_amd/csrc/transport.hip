@@ -528,6 +528,7 @@ __device__ void coop_walk(Packet1D &q, const uint8_t *__restrict__ tb, const Dev
 {
     constexpr int WB = 16;
     int wi = -1, jw = 0;
+    int short_run = 0;   // consecutive blocks stopped by a slow-path step within 16 steps
     uint32_t v_lk = 0u, v_dhi = 0u, v_shi = 0u, v_fhi = 0u;
     while (q.active) {
         const uint64_t left = a.max_steps - q.steps;
@@ -592,9 +593,11 @@ __device__ void coop_walk(Packet1D &q, const uint8_t *__restrict__ tb, const Dev
         q.t = t;
         q.steps += (uint64_t)l;
         q.j = jj;
+        short_run = special && l < 16 ? short_run + 1 : 0;
         if (special) {
-            // the step at l in lane 0 with the lane walk's arithmetic; then, if this block
-            // stopped early (spatial leaks dominate here), a run of single steps in lane 0
+            // the step at l in lane 0 with the lane walk's arithmetic; then, if several
+            // blocks in a row stopped early (spatial leaks dominate here), a run of single
+            // steps in lane 0
             const int b = jj - jw;
             const StepWords ws = {rl(tw, l), rl(ew, l), rl(wl.z, l), rl(wl.w, l)};
             const uint4 rec = make_uint4(rl(v_lk, b), rl(v_dhi, b), rl(v_shi, b), rl(v_fhi, b));
@@ -602,7 +605,7 @@ __device__ void coop_walk(Packet1D &q, const uint8_t *__restrict__ tb, const Dev
             if (lane == 0) {
                 const float4 cm = (MOVING && s1.moving) ? s1.cmap[s1.i] : make_float4(1.f, 0.f, 1.f, 0.f);
                 one_step<MOVING>(s1, ws, rec, cm, tb, clouds, a, tally);
-                if (l < 16) single_steps<MOVING>(s1, 256, tb, clouds, a, tally);
+                if (short_run >= 3) single_steps<MOVING>(s1, 64, tb, clouds, a, tally);
             }
             q.i = (int)rl((uint32_t)s1.i, 0);
             q.j = (int)rl((uint32_t)s1.j, 0);
