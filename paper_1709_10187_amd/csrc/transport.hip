@@ -559,39 +559,57 @@ __device__ void coop_walk(Packet1D &q, const uint8_t *__restrict__ tb, const Dev
         const StepWords wl = words_of_step<MOVING>(q, q.steps + (uint64_t)lane, a);
         const uint32_t tw = wl.t;
         const uint32_t ew = wl.e;
-        uint32_t pk = 0u;
+        // per window bin b: bit b = "a move from b goes down", bit 16+b = "stop at b" (a
+        // slow-path step, or a move out of the window); ps bit b = slow-path step only
+        uint32_t pk = 0u, ps = 0u;
 #pragma unroll
         for (int b = 0; b < WB; ++b) {
             const uint32_t dh = rl(v_dhi, b), sh = rl(v_shi, b);
-            pk |= (ew < dh ? 1u : 0u) << b;
-            pk |= ((ew >= sh) || (ew == dh) ? 1u : 0u) << (WB + b);
+            const uint32_t dn = ew < dh ? 1u : 0u;
+            const uint32_t sp = (ew >= sh) || (ew == dh) ? 1u : 0u;
+            const uint32_t out = b == 0 ? dn : (b == WB - 1 ? dn ^ 1u : 0u);
+            pk |= dn << b;
+            pk |= (sp | out) << (WB + b);
+            ps |= sp << b;
         }
-        uint32_t P = 1u << (q.j - jw);     // one-hot window position
-        int jj = q.j, l = 0;
-        uint32_t pst = 0u;                 // lane l: position before step l
-        bool special = false;
+        // sequential part, scalar only: the window position and a mask of down moves
+        const int pos0 = q.j - jw;
+        int pos = pos0, l = 0;
+        uint64_t dmask = 0ull;
         for (; l < m; ++l) {
-            const uint32_t k = rl(pk, l);
-            if ((k >> WB) & P) {
-                special = true;
-                break;
-            }
-            pst = (lane == l) ? P : pst;
-            const bool dn = (k & P) != 0u;
-            P = dn ? (P >> 1) : (P << 1);
-            jj += dn ? -1 : 1;
-            if ((P & ((1u << WB) - 1u)) == 0u) {   // left the window: this step is done
+            const uint32_t k = rl(pk, l) >> pos;
+            if ((k >> WB) & 1u) break;
+            const uint32_t dn = k & 1u;
+            dmask |= (uint64_t)dn << l;
+            pos += 1 - 2 * (int)dn;
+        }
+        bool special = false;
+        if (l < m) {
+            if ((rl(ps, l) >> pos) & 1u) {
+                special = true;                    // step l takes the slow path
+            } else {                               // step l leaves the window: it is done
+                const uint32_t dn = (rl(pk, l) >> pos) & 1u;
+                dmask |= (uint64_t)dn << l;
+                pos += 1 - 2 * (int)dn;
                 ++l;
-                break;
             }
         }
-        const int bl = __ffs((int)pst) - 1;
-        const uint32_t lk_bits = (uint32_t)__shfl((int)v_lk, bl & 63);
+        // lane l's bin before step l, from the moves before it
+        const int pl = pos0 + lane - 2 * __popcll(dmask & ((1ull << lane) - 1ull));
+        const uint32_t lk_bits = (uint32_t)__shfl((int)v_lk, pl & 63);
         const float dl = path_length(tw, __uint_as_float(lk_bits));
-        double t = q.t;
-        for (int k = 0; k < l; ++k) t += (double)__uint_as_float(rl(__float_as_uint(dl), k));
+        double t = q.t;                    // the lane walk's order of FP64 additions
+        int k = 0;
+        for (; k + 4 <= l; k += 4) {
+            t += (double)__uint_as_float(rl(__float_as_uint(dl), k));
+            t += (double)__uint_as_float(rl(__float_as_uint(dl), k + 1));
+            t += (double)__uint_as_float(rl(__float_as_uint(dl), k + 2));
+            t += (double)__uint_as_float(rl(__float_as_uint(dl), k + 3));
+        }
+        for (; k < l; ++k) t += (double)__uint_as_float(rl(__float_as_uint(dl), k));
         q.t = t;
         q.steps += (uint64_t)l;
+        const int jj = jw + pos;
         q.j = jj;
         short_run = special && l < 16 ? short_run + 1 : 0;
         if (special) {
