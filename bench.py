@@ -54,7 +54,7 @@ def parse():
     ap.add_argument("--tail-lanes", type=int, default=0,
                     help="hand a wave's packets to the cooperative walk at <= this many (0 = library default)")
     ap.add_argument("--surrogate-packets", type=int, default=2048, help="packets per cloud, surrogate run")
-    ap.add_argument("--plain-packets", type=int, default=256, help="packets per cloud, plain run")
+    ap.add_argument("--plain-packets", type=int, default=64, help="packets per cloud, plain run")
     return ap.parse_args()
 
 
