@@ -74,7 +74,8 @@ enum { RDDMC_SLAB = 0, RDDMC_SPHERE = 1, RDDMC_CART3D = 2 };
  *                per cell), Cartesian (vx,vy,vz) (three values per cell) [km/s].
  *   tau_threshold  0 selects pure DDMC (every state diffusive); > 0 (must be >= 2, the
  *                hybrid section's validity bound) makes states with k_ij dz_i below it
- *                continuous Monte Carlo states.  (Hybrid states: see RDDMC_EUNSUPPORTED.)
+ *                continuous Monte Carlo states (walked on RDDMC_CART3D grids; a 1D cloud
+ *                with a thin state is refused with RDDMC_EUNSUPPORTED).
  *   f_mu         Doppler averaging factor of eq. 20 (1/2 for isotropic escape).
  *   lambda       extrapolation distance of the vacuum/thin-face rate (0.7104).
  *   n_src, src_pos, src_x  source positions (3 doubles each: slab z; sphere r; Cartesian
@@ -220,20 +221,28 @@ rddmc_status rddmc_work_bytes(const rddmc_batch *batch, size_t *bytes);
  *   frequency rates 1 / (dx_j (dx_j/k_ij + dx_j'/k_ij'))             (eq. 11), zero past
  *            the first and last bin (reflecting frequency edges);
  * and stores, per state, a 16-byte hot record {ln2/K (f32), high words of the u64
- * categorical thresholds D = P(lower bin) 2^64 and S = (1 - P(spatial)) 2^64} plus cold
- * arrays (their low words, the face split, k_ij, Doppler maps).
+ * categorical thresholds D = P(lower bin) 2^64 and S = (1 - P(spatial)) 2^64, w3} with
+ * w3 = high word of F = S + P(face 0) 2^64 on 1D grids, and on 3D grids a flag word (bit 0
+ * thick, bit 1+f face f leads into a thin state or vacuum, bits 7 / 8 bin j-1 / j+1 thin);
+ * plus cold arrays (low words, the face split, k_ij, Doppler maps), and for 3D the per-cell
+ * FP32 record of the continuous-MC step and the FP32 Voigt (H1 of eq. 12) and
+ * atom-velocity sampler tables.
  *   batch        host description, read during the call.
  *   d_tables     device buffer of >= rddmc_table_bytes bytes, 256-byte aligned.
  *   stream       hipStream_t (NULL = default stream); the call synchronises it.
  * Errors: EINVAL (bad grid or inputs), ESIZE (buffer), ENUMERIC (non-finite table entry),
- * EUNSUPPORTED (mixed geometries in one batch, 3D, or hybrid states), EHIP.
+ * EUNSUPPORTED (mixed geometries in one batch, thin states in a 1D cloud), EHIP.
  */
 rddmc_status rddmc_build_leakage(const rddmc_batch *batch, void *d_tables, size_t table_bytes,
                                  void *stream);
 
 /*
  * rddmc_transport -- the walk of Sec. 2.3 (eqs. 15-16), emission as an initial flash
- * (Sec. 2.3), Doppler re-binning across faces (Sec. 2.5) and removal at the boundary.
+ * (Sec. 2.3), Doppler re-binning across faces (Sec. 2.5) and removal at the boundary; on
+ * 3D grids the hybrid scheme (conversions, eq. 39 acceptance, continuous MC with the
+ * Voigt opacity of eq. 12 and the redistribution of eq. 41), one lane per packet drawing
+ * its words in order from its own Philox stream; on 1D clouds optionally the learned
+ * escape surrogate (run.surrogate).
  * A persistent kernel: every lane carries one packet; every run.chunk steps finished
  * lanes take new packet ids from a work counter.  One Philox4x32-10 block serves two
  * steps; each step takes one 32-bit word for the exponential path length (time advances
@@ -275,10 +284,11 @@ rddmc_status rddmc_tally(const rddmc_batch *batch, const void *d_tally, size_t t
  *   k         [n_states]          FP64 bin-averaged opacity (eq. 14)
  *   rates     [n_states * (nf+2)] FP64 face rates (nf = 2 for 1D, 6 for 3D), then the
  *             lower and upper frequency rates; only with RDDMC_FLAG_KEEP_RATES (else EINVAL)
- *   hot       [n_states * 16 bytes] hot records {ln2/K f32, D>>32 u32, S>>32 u32, 0}
- *   lo_words  [n_states * 8 bytes] {D & 0xffffffff, S & 0xffffffff}
- * where D = P(lower bin) * 2^64 and S = (1 - P(spatial)) * 2^64 (rounded).  Any pointer
- * may be NULL.  Synchronises the stream.
+ *   hot       [n_states * 16 bytes] hot records {ln2/K f32, D>>32 u32, S>>32 u32, w3 u32}
+ *             (w3: F>>32 on 1D grids, the flag word on 3D grids; thin states: all zero)
+ *   lo_words  [n_states * 16 bytes] {D & 0xffffffff, S & 0xffffffff, F & 0xffffffff (1D), 0}
+ * where D = P(lower bin) * 2^64, S = (1 - P(spatial)) * 2^64 and F = S + P(face 0) * 2^64
+ * (rounded).  Any pointer may be NULL.  Synchronises the stream.
  */
 rddmc_status rddmc_read_tables(const rddmc_batch *batch, const void *d_tables, int32_t cloud,
                                double *k, double *rates, void *hot, void *lo_words, void *stream);
