@@ -203,7 +203,7 @@ rddmc_status rddmc_table_bytes(const rddmc_batch *batch, size_t *bytes);
  * rddmc_tally_reset or any fill before the first run; runs accumulate). */
 rddmc_status rddmc_tally_bytes(const rddmc_batch *batch, size_t *bytes);
 
-/* Device bytes for the transport work area: queue counters and one 32-byte slot per
+/* Device bytes for the transport work area: queue counters and one 48-byte slot per
  * resident lane for packets handed to the cooperative tail walk. */
 rddmc_status rddmc_work_bytes(const rddmc_batch *batch, size_t *bytes);
 

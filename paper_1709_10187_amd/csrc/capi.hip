@@ -314,10 +314,10 @@ rddmc_status rddmc_work_bytes(const rddmc_batch *batch, size_t *bytes)
     Layout L;
     rddmc_status st = make_layout(batch, L);
     if (st != RDDMC_OK) return st;
-    // queue counters, then one 32-byte slot per lane that may hand its packet to the
+    // queue counters, then one 48-byte slot per lane that may hand its packet to the
     // cooperative tail walk (at most 2^20 lanes are ever resident)
     const uint64_t lanes = L.h.total_packets < (1ull << 20) ? L.h.total_packets : (1ull << 20);
-    *bytes = 256 + 32 * lanes;
+    *bytes = 256 + 48 * lanes;
     return RDDMC_OK;
 }
 

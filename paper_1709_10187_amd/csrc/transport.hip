@@ -38,18 +38,33 @@ struct WalkArgs {
     int32_t pad;
     uint64_t tail_capacity;
     const uint8_t *surr;   // learned escape surrogate (windows and records) or null
+    uint32_t producer_blocks;   // blocks [0, producer_blocks) walk packets from the queue;
+    uint32_t producer_waves;    // later blocks walk handed-over packets cooperatively
 };
 
-// Work area: u64 words [0] packet queue counter, [1] exported packets, [2] next exported
-// packet to walk cooperatively; exported packet states start at byte kWorkHeaderBytes.
+// Work area (u64 words, the polled ones on their own 128-byte lines): [0] packet queue
+// counter, [16] export slots handed out, [17] slots claimed by consumer waves of the
+// lane-walk launch, [18] producer waves finished, [24] slots claimed by the closing
+// cooperative kernel; export slots start at byte kWorkHeaderBytes.
 constexpr uint64_t kWorkHeaderBytes = 256;
+constexpr int kWGiven = 16, kWClaimed = 17, kWDone = 18, kWSweep = 24;
 
-struct TailPacket {        // 32 bytes
+// One exported packet.  `flag` moves empty -> ready (published by the exporting lane) ->
+// taken (claimed by a walking wave), or empty -> abandoned (a consumer claimed the slot
+// before its packet was published and moved on; the exporter then walks it itself).
+struct TailPacket {        // 48 bytes
     uint32_t cl, pid;
     int32_t i, j;
     uint64_t steps;
     double t;
+    uint32_t flag, pad0;
+    uint64_t pad1;
 };
+constexpr uint32_t kSlotEmpty = 0u, kSlotReady = 1u, kSlotTaken = 2u, kSlotAbandoned = 3u;
+// A consumer wave with nothing to claim polls every 32 x s_sleep 127 (about 0.1 ms) and
+// gives up after this many polls in a row (about 100 s); in normal operation it leaves
+// much earlier, as soon as every producer wave has finished.
+constexpr int kConsumerIdlePolls = 1000000;
 
 // Domain tags in the second counter word (high bits of the step index never reach them).
 constexpr uint32_t kDomAux = 0x80000000u;   // extra draws inside step k (re-binning, escape)
@@ -338,6 +353,113 @@ __device__ void single_steps(Packet1D &p, int n, const uint8_t *__restrict__ tb,
 // escape frequencies.  Static media take one Philox block per pair of steps ((x, y) for the
 // even step and (z, w) for the odd one; all active lanes of a wave are at even step counts
 // between pairs); moving media take one block per step.
+template <bool MOVING>
+__device__ void coop_walk(Packet1D &q, const uint8_t *__restrict__ tb, const DevCloud *__restrict__ clouds,
+                          const WalkArgs &a, unsigned long long *__restrict__ tally, int lane);
+
+__device__ __forceinline__ uint32_t rl(uint32_t v, int lane)
+{
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, lane);
+}
+
+__device__ __forceinline__ TailPacket *slots_of(unsigned long long *work)
+{
+    return reinterpret_cast<TailPacket *>(reinterpret_cast<uint8_t *>(work) + kWorkHeaderBytes);
+}
+
+// The packet of an export slot as a wave-uniform state.
+__device__ Packet1D load_slot(const TailPacket *ts, const uint8_t *__restrict__ tb,
+                              const DevCloud *__restrict__ clouds)
+{
+    const TailPacket tk = *ts;
+    Packet1D q;
+    q.cl = (int)rl(tk.cl, 0);
+    const DevCloud &c = clouds[q.cl];
+    q.pid = rl(tk.pid, 0);
+    q.key = c.stream;
+    q.i = (int)rl((uint32_t)tk.i, 0);
+    q.j = (int)rl((uint32_t)tk.j, 0);
+    q.steps = ((uint64_t)rl((uint32_t)(tk.steps >> 32), 0) << 32) | rl((uint32_t)tk.steps, 0);
+    const uint64_t tb64 = ((uint64_t)rl((uint32_t)(__double_as_longlong(tk.t) >> 32), 0) << 32) |
+                          rl((uint32_t)__double_as_longlong(tk.t), 0);
+    q.t = __longlong_as_double((long long)tb64);
+    q.nb = c.nb;
+    q.nc = c.nc;
+    q.geom = c.geometry;
+    q.hot = reinterpret_cast<const uint4 *>(tb + c.off_hot);
+    q.cmap = reinterpret_cast<const float4 *>(tb + c.off_cmap);
+    q.x0 = c.x0;
+    q.dx = c.dx;
+    q.inv_dx = c.inv_dx;
+    q.uniform = c.uniform_bins != 0;
+    q.moving = c.moving != 0;
+    q.active = true;
+    q.surr_calls = 0u;
+    return q;
+}
+
+// A consumer wave (a block past the producers) walks handed-over packets cooperatively,
+// one after another.  It claims only slot indices already handed out (a CAS on the claim
+// counter bounded by the hand-out counter: each failed CAS means another wave claimed one,
+// so the retries end); a claimed slot whose packet is not yet published is marked abandoned
+// (its exporter walks it).  With nothing to claim it exits once every producer wave has
+// finished, or after kConsumerIdlePolls polls; what it leaves, the closing kernel walks.
+template <bool MOVING>
+__device__ void consume_exported(const uint8_t *__restrict__ tb, const DevCloud *__restrict__ clouds,
+                                 const WalkArgs &a, unsigned long long *__restrict__ tally,
+                                 unsigned long long *__restrict__ work, int lane)
+{
+    TailPacket *slots = slots_of(work);
+    constexpr uint64_t kNone = ~0ull;
+    int idle = 0;
+    for (;;) {
+        uint64_t idx = kNone;
+        uint32_t done = 0u;
+        if (lane == 0) {
+            for (;;) {
+                const uint64_t taken = __hip_atomic_load(&work[kWClaimed], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const uint64_t given = __hip_atomic_load(&work[kWGiven], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (taken >= given || taken >= a.tail_capacity) {
+                    done = __hip_atomic_load(&work[kWDone], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >=
+                                   (unsigned long long)a.producer_waves
+                               ? 1u
+                               : 0u;
+                    break;
+                }
+                unsigned long long expect = taken;
+                if (__hip_atomic_compare_exchange_strong(&work[kWClaimed], &expect, taken + 1ull, __ATOMIC_RELAXED,
+                                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                    idx = taken;
+                    break;
+                }
+            }
+        }
+        idx = shfl_u64(idx, 0);
+        if (idx == kNone) {
+            if (rl(done, 0) != 0u || ++idle > kConsumerIdlePolls) return;
+            for (int z = 0; z < 32; ++z) __builtin_amdgcn_s_sleep(127);
+            continue;
+        }
+        idle = 0;
+        uint32_t got = 0u;
+        if (lane == 0) {
+            uint32_t *f = &slots[idx].flag;
+            uint32_t expect = kSlotEmpty;
+            if (!__hip_atomic_compare_exchange_strong(f, &expect, kSlotAbandoned, __ATOMIC_ACQ_REL, __ATOMIC_ACQUIRE,
+                                                      __HIP_MEMORY_SCOPE_AGENT) &&
+                expect == kSlotReady) {
+                got = __hip_atomic_compare_exchange_strong(f, &expect, kSlotTaken, __ATOMIC_ACQ_REL, __ATOMIC_ACQUIRE,
+                                                           __HIP_MEMORY_SCOPE_AGENT)
+                          ? 1u
+                          : 0u;
+            }
+        }
+        if (rl(got, 0) == 0u) continue;
+        Packet1D q = load_slot(slots + idx, tb, clouds);
+        coop_walk<MOVING>(q, tb, clouds, a, tally, lane);
+    }
+}
+
 template <bool MOVING, bool SURR>
 __global__ __launch_bounds__(256) void walk1d(const uint8_t *__restrict__ tb, WalkArgs a,
                                               unsigned long long *__restrict__ tally,
@@ -350,6 +472,10 @@ __global__ __launch_bounds__(256) void walk1d(const uint8_t *__restrict__ tb, Wa
     const DevCloud *clouds = reinterpret_cast<const DevCloud *>(tb + H->off_clouds);
     const uint64_t *prefix = reinterpret_cast<const uint64_t *>(tb + H->off_prefix);
     const int lane = threadIdx.x & 63;
+    if (blockIdx.x >= a.producer_blocks) {   // a consumer block
+        consume_exported<MOVING>(tb, clouds, a, tally, work, lane);
+        return;
+    }
 
     Packet1D p;
     p.active = false;
@@ -428,19 +554,32 @@ __global__ __launch_bounds__(256) void walk1d(const uint8_t *__restrict__ tb, Wa
             if (__popcll(live) <= a.tail_lanes) {
                 const int leader = __ffsll((unsigned long long)live) - 1;
                 uint64_t base = 0;
-                if (lane == leader) base = atomicAdd(&work[1], (unsigned long long)__popcll(live));
+                if (lane == leader) base = atomicAdd(&work[kWGiven], (unsigned long long)__popcll(live));
                 base = shfl_u64(base, leader);
+                bool keep = false;
                 if (p.active) {
                     const uint64_t slot = base + __popcll(live & ((1ull << lane) - 1ull));
-                    TailPacket *tp = reinterpret_cast<TailPacket *>(reinterpret_cast<uint8_t *>(work) +
-                                                                    kWorkHeaderBytes) + slot;
+                    TailPacket *tp = slots_of(work) + slot;
                     tp->cl = (uint32_t)p.cl;
                     tp->pid = p.pid;
                     tp->i = p.i;
                     tp->j = p.j;
                     tp->steps = p.steps;
                     tp->t = p.t;
+                    __threadfence();
+                    uint32_t expect = kSlotEmpty;
+                    keep = !__hip_atomic_compare_exchange_strong(&tp->flag, &expect, kSlotReady, __ATOMIC_RELEASE,
+                                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     p.active = false;
+                }
+                // slots a consumer claimed before they were published: walk them here
+                uint64_t mine = __ballot(keep);
+                while (mine) {
+                    const int l = __ffsll((unsigned long long)mine) - 1;
+                    mine &= mine - 1ull;
+                    const uint64_t slot = base + __popcll(live & ((1ull << l) - 1ull));
+                    Packet1D q = load_slot(slots_of(work) + slot, tb, clouds);
+                    coop_walk<MOVING>(q, tb, clouds, a, tally, lane);
                 }
                 break;
             }
@@ -504,11 +643,7 @@ __global__ __launch_bounds__(256) void walk1d(const uint8_t *__restrict__ tb, Wa
         if (SURR && was_active && !p.active && p.surr_calls)
             atomicAdd(&tally[clouds[p.cl].tally_off + TW_SURR_CALLS], (unsigned long long)p.surr_calls);
     }
-}
-
-__device__ __forceinline__ uint32_t rl(uint32_t v, int lane)
-{
-    return (uint32_t)__builtin_amdgcn_readlane((int)v, lane);
+    if (lane == 0) __hip_atomic_fetch_add(&work[kWDone], 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Cooperative walk of ONE packet by a whole wave (the packet state is wave-uniform).
@@ -644,37 +779,23 @@ __global__ __launch_bounds__(64) void walk1d_coop(const uint8_t *__restrict__ tb
     const DevHeader *H = reinterpret_cast<const DevHeader *>(tb);
     const DevCloud *clouds = reinterpret_cast<const DevCloud *>(tb + H->off_clouds);
     const int lane = threadIdx.x & 63;
-    const uint64_t n = work[1];
-    const TailPacket *tp = reinterpret_cast<const TailPacket *>(reinterpret_cast<const uint8_t *>(work) +
-                                                                kWorkHeaderBytes);
-    for (;;) {
+    const uint64_t n = work[kWGiven] < a.tail_capacity ? work[kWGiven] : a.tail_capacity;
+    TailPacket *slots = slots_of(work);
+    for (;;) {   // the packets still published once the lane-walk launch has ended
         uint64_t idx = 0;
-        if (lane == 0) idx = atomicAdd(&work[2], 1ull);
+        if (lane == 0) idx = atomicAdd(&work[kWSweep], 1ull);
         idx = shfl_u64(idx, 0);
         if (idx >= n) break;
-        const TailPacket tk = tp[idx];
-        Packet1D q;
-        q.cl = (int)rl(tk.cl, 0);
-        const DevCloud &c = clouds[q.cl];
-        q.pid = rl(tk.pid, 0);
-        q.key = c.stream;
-        q.i = (int)rl((uint32_t)tk.i, 0);
-        q.j = (int)rl((uint32_t)tk.j, 0);
-        q.steps = ((uint64_t)rl((uint32_t)(tk.steps >> 32), 0) << 32) | rl((uint32_t)tk.steps, 0);
-        const uint64_t tb64 = ((uint64_t)rl((uint32_t)(__double_as_longlong(tk.t) >> 32), 0) << 32) |
-                              rl((uint32_t)__double_as_longlong(tk.t), 0);
-        q.t = __longlong_as_double((long long)tb64);
-        q.nb = c.nb;
-        q.nc = c.nc;
-        q.geom = c.geometry;
-        q.hot = reinterpret_cast<const uint4 *>(tb + c.off_hot);
-        q.cmap = reinterpret_cast<const float4 *>(tb + c.off_cmap);
-        q.x0 = c.x0;
-        q.dx = c.dx;
-        q.inv_dx = c.inv_dx;
-        q.uniform = c.uniform_bins != 0;
-        q.moving = c.moving != 0;
-        q.active = true;
+        uint32_t got = 0u;
+        if (lane == 0) {
+            uint32_t expect = kSlotReady;
+            got = __hip_atomic_compare_exchange_strong(&slots[idx].flag, &expect, kSlotTaken, __ATOMIC_ACQ_REL,
+                                                       __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)
+                      ? 1u
+                      : 0u;
+        }
+        if (rl(got, 0) == 0u) continue;
+        Packet1D q = load_slot(slots + idx, tb, clouds);
         coop_walk<MOVING>(q, tb, clouds, a, tally, lane);
     }
 }
@@ -753,9 +874,13 @@ __global__ void philox_fill_kernel(uint32_t k0, uint32_t k1, uint32_t c0, uint32
     out[4 * i + 3] = r.w;
 }
 
-__global__ void reset_work(unsigned long long *work)
+// Clears the counters and every export slot's flag (a kernel, so that the call can be
+// captured in a graph).
+__global__ void reset_work(unsigned long long *work, uint64_t capacity)
 {
-    if (blockIdx.x == 0 && threadIdx.x < 4) work[threadIdx.x] = 0ull;
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < kWorkHeaderBytes / 8) work[i] = 0ull;
+    if (i < capacity) slots_of(work)[i].flag = kSlotEmpty;
 }
 
 }  // namespace
@@ -806,7 +931,16 @@ hipError_t launch_walk(const uint8_t *d_tables, const DevHeader &h, const DevClo
     for (int c = 0; c < h.n_clouds; ++c) moving |= host_clouds[c].moving != 0;
     a.surr = static_cast<const uint8_t *>(run.surrogate);
     if (a.surr) a.tail_lanes = 0;   // the cooperative tail walk has no surrogate exits
-    reset_work<<<1, 64, 0, s>>>(d_work);
+    a.producer_blocks = (uint32_t)grid;
+    a.producer_waves = (uint32_t)(grid * (uint64_t)(block / 64));
+    // consumer blocks after the producers: 16 waves per CU walk handed-over packets as soon
+    // as lane-walk blocks finish and free their slots
+    const uint64_t consumers = a.tail_lanes > 0 ? ((uint64_t)device_cu_count() * 16 * 64 + block - 1) / block : 0;
+    {
+        const uint64_t n = a.tail_capacity > kWorkHeaderBytes / 8 ? a.tail_capacity : kWorkHeaderBytes / 8;
+        reset_work<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(d_work, a.tail_capacity);
+    }
+    grid += consumers;
     if (moving && a.surr)
         walk1d<true, true><<<(unsigned)grid, block, 0, s>>>(d_tables, a, d_tally, d_work);
     else if (moving)

@@ -45,8 +45,8 @@ def test_size_queries():
     # hot records alone: 64 * 128 * 16 bytes
     assert tb > 64 * 128 * 16
     assert rddmc.tally_bytes(b) == 8 * (16 + 2 * 130 + 130 + 64)
-    assert rddmc.work_bytes(b) == 256 + 32 * (1 << 16)
-    assert rddmc.work_bytes(rddmc.Batch([media.config_sphere()])) == 256 + 32 * (1 << 20)
+    assert rddmc.work_bytes(b) == 256 + 48 * (1 << 16)
+    assert rddmc.work_bytes(rddmc.Batch([media.config_sphere()])) == 256 + 48 * (1 << 20)
     b2 = rddmc.Batch([media.config_sphere(), media.config_sphere()])
     assert rddmc.tally_bytes(b2) == 2 * 8 * (16 + 514 + 130 + 64)
     kb = rddmc.Batch([media.config_slab()], keep_rates=True)
