@@ -37,6 +37,10 @@ METRIC = "packets/s & packet-steps/s at 1 GPU; surrogate vs plain speedup at ≤
 OPS_PER_STEP = 32.0
 # VALU lane-op issue rate of the chip: 256 CUs x 4 SIMDs x 64 lanes per 4 cycles x 2.4 GHz.
 PEAK_OPS = 256 * 4 * 16 * 2.4e9
+# HBM bytes of one launch on the default block (2^16 packets of the sphere), from the
+# FETCH_SIZE and WRITE_SIZE counters scaled by a plain copy of known size
+# (profiles/walk1d_sphere_tau1e7_block65536_pmc.md); None for any other block.
+TRAFFIC_DEFAULT_BLOCK = 4.85e7
 
 
 def parse():
@@ -51,6 +55,9 @@ def parse():
     ap.add_argument("--cpu-packets", type=int, default=12)
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--workload", choices=["sphere", "cube", "surrogate"], default="sphere")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first copy this many MiB device to device (a plain copy of known size that "
+                         "calibrates hardware byte counters read in the same run)")
     ap.add_argument("--tail-lanes", type=int, default=0,
                     help="hand a wave's packets to the cooperative walk at <= this many (0 = library default)")
     ap.add_argument("--surrogate-packets", type=int, default=2048, help="packets per cloud, surrogate run")
@@ -183,6 +190,15 @@ def main():
         out = bench_cube(args) if args.workload == "cube" else bench_surrogate(args)
         print(json.dumps(out))
         return
+    if args.copy_probe_mib > 0:
+        n = args.copy_probe_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] copy probe: {args.copy_probe_mib} MiB read, {args.copy_probe_mib} MiB written",
+              file=sys.stderr, flush=True)
+        del src, dst
     m = media.config_sphere()
     B = int(args.block_packets)
     n_blocks = m.n_packets // B
@@ -240,7 +256,7 @@ def main():
                    "precision": "f32 walk, f64 tables and clock, i64 tallies, Philox4x32-10"},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_OPS / 1e12,
                      "unit": "T VALU lane-ops/s", "frac": achieved / PEAK_OPS,
-                     "traffic": None},
+                     "traffic": TRAFFIC_DEFAULT_BLOCK if (B == 1 << 16 and args.steps == 1) else None},
     }
     if not args.no_cpu_baseline:
         threads = args.cpu_threads or min(16, os.cpu_count() or 1)
