@@ -65,6 +65,9 @@ constexpr uint32_t kSlotEmpty = 0u, kSlotReady = 1u, kSlotTaken = 2u, kSlotAband
 // gives up after this many polls in a row (about 100 s); in normal operation it leaves
 // much earlier, as soon as every producer wave has finished.
 constexpr int kConsumerIdlePolls = 1000000;
+// A consumer that claims a slot not yet published re-reads its flag at most this many times
+// (s_sleep 2 apart, ~0.2 ms in all) before leaving the packet to its exporter.
+constexpr int kPublishWaitPolls = 4096;
 
 // Domain tags in the second counter word (high bits of the step index never reach them).
 constexpr uint32_t kDomAux = 0x80000000u;   // extra draws inside step k (re-binning, escape)
@@ -443,7 +446,13 @@ __device__ void consume_exported(const uint8_t *__restrict__ tb, const DevCloud 
         idle = 0;
         uint32_t got = 0u;
         if (lane == 0) {
+            // the exporter hands the slot out just before it writes and publishes it: give it
+            // a bounded moment, then take the packet or leave it to the exporter
             uint32_t *f = &slots[idx].flag;
+            int tries = 0;
+            while (__hip_atomic_load(f, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == kSlotEmpty &&
+                   ++tries < kPublishWaitPolls)
+                __builtin_amdgcn_s_sleep(2);
             uint32_t expect = kSlotEmpty;
             if (!__hip_atomic_compare_exchange_strong(f, &expect, kSlotAbandoned, __ATOMIC_ACQ_REL, __ATOMIC_ACQUIRE,
                                                       __HIP_MEMORY_SCOPE_AGENT) &&
@@ -711,7 +720,24 @@ __device__ void coop_walk(Packet1D &q, const uint8_t *__restrict__ tb, const Dev
         const int pos0 = q.j - jw;
         int pos = pos0, l = 0;
         uint64_t dmask = 0ull;
-        for (; l < m; ++l) {
+        // four steps per pass while no stop occurs among them (one test for the four)
+        for (; l + 4 <= m; l += 4) {
+            const uint32_t k0 = rl(pk, l), k1 = rl(pk, l + 1), k2 = rl(pk, l + 2), k3 = rl(pk, l + 3);
+            const uint32_t s0 = k0 >> pos;
+            const int p1 = pos + 1 - 2 * (int)(s0 & 1u);
+            const uint32_t s1 = k1 >> (p1 & 31);
+            const int p2 = p1 + 1 - 2 * (int)(s1 & 1u);
+            const uint32_t s2 = k2 >> (p2 & 31);
+            const int p3 = p2 + 1 - 2 * (int)(s2 & 1u);
+            const uint32_t s3 = k3 >> (p3 & 31);
+            // a stop at step l+i (i > 0) counts only if the steps before it stayed in the
+            // window, which the stops before it guarantee (moving out of the window is a stop)
+            if (((s0 | s1 | s2 | s3) >> WB) & 1u) break;
+            const uint32_t d4 = (s0 & 1u) | ((s1 & 1u) << 1) | ((s2 & 1u) << 2) | ((s3 & 1u) << 3);
+            dmask |= (uint64_t)d4 << l;
+            pos = p3 + 1 - 2 * (int)(s3 & 1u);
+        }
+        for (; l < m; ++l) {   // one step at a time from the pass that saw a stop, and the rest
             const uint32_t k = rl(pk, l) >> pos;
             if ((k >> WB) & 1u) break;
             const uint32_t dn = k & 1u;
