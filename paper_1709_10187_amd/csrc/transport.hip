@@ -656,22 +656,71 @@ __global__ __launch_bounds__(256) void walk1d(const uint8_t *__restrict__ tb, Wa
 }
 
 // Cooperative walk of ONE packet by a whole wave (the packet state is wave-uniform).
-// Per block of up to 64 steps:
-//   * lane l draws the Philox words of step steps+l (all 64 blocks in parallel);
-//   * the records of a 16-bin window of the current cell sit in lanes 0..15;
-//   * lane l packs, for every window bin b, "a move from b would go to the lower bin"
-//     (bit b) and "a step from b needs the slow path" (bit 16+b) into one word;
-//   * the sequential part then costs one readlane and a few scalar bit operations per
-//     step on a one-hot position, stopping at a window exit or a slow-path step, which one
-//     lane executes (tie resolution, spatial leak, escape tally).
+//   * The 64 lanes hold the hot records of 64 consecutive bins of the packet's cell (the
+//     band); each block of up to 64 steps walks a 15-bin window of it, centred on the
+//     packet's bin.
+//   * Lane l draws the Philox words of step steps+l and builds the step's transition table
+//     over the window: 4 bits per window position giving the next position, or 15 ("stop")
+//     for a slow-path step (a tie with a threshold, a spatial leak) or a move out of the
+//     window; position 15 maps to itself.
+//   * The sequential part is a scalar chain of two instructions per step (a 4-bit field
+//     extract addressed by the position, a shift-add back to an address); every lane
+//     receives the position its step starts from.
+//   * The lane whose step stops classifies it: a move out of the window completes, a
+//     slow-path step runs in lane 0 with the lane walk's arithmetic.
 // The clock adds the same f32 path lengths in the same order as the lane walk, so every
 // tally is bit-identical to walking the packet in a single lane.
+constexpr int kCoopWin = 15;
+// scan state: 4 x window position in bits 0..5, field width 4 in bits 16..22 (the operand
+// layout of s_bfe_u64); kScanStop is the state of the stop position
+constexpr uint32_t kScanWidth = 4u << 16;
+constexpr uint32_t kScanStop = kScanWidth | (15u << 2);
+
+// Step L of the chain: hand lane L its starting state, then move to the next position.
+template <int L>
+__device__ __forceinline__ void scan_step(uint32_t &st, int &vst, uint32_t tlo, uint32_t thi)
+{
+    const uint64_t tab = ((uint64_t)rl(thi, L) << 32) | rl(tlo, L);
+    uint64_t f;
+    asm("v_writelane_b32 %0, %1, %2" : "+v"(vst) : "s"(st), "n"(L));
+    asm("s_bfe_u64 %0, %1, %2" : "=s"(f) : "s"(tab), "s"(st) : "scc");
+    asm("s_lshl2_add_u32 %0, %1, %2" : "=s"(st) : "s"((uint32_t)f), "s"(kScanWidth) : "scc");
+}
+
+template <int G>
+__device__ __forceinline__ void scan_from(uint32_t &st, int &vst, uint32_t tlo, uint32_t thi)
+{
+    scan_step<8 * G + 0>(st, vst, tlo, thi);
+    scan_step<8 * G + 1>(st, vst, tlo, thi);
+    scan_step<8 * G + 2>(st, vst, tlo, thi);
+    scan_step<8 * G + 3>(st, vst, tlo, thi);
+    scan_step<8 * G + 4>(st, vst, tlo, thi);
+    scan_step<8 * G + 5>(st, vst, tlo, thi);
+    scan_step<8 * G + 6>(st, vst, tlo, thi);
+    scan_step<8 * G + 7>(st, vst, tlo, thi);
+    if constexpr (G < 7) {
+        if (st != kScanStop) scan_from<G + 1>(st, vst, tlo, thi);
+    }
+}
+
+// Clock of a block: t += the FP64 path lengths of lanes 0, 1, ... in order (lanes at or
+// beyond `done` hold +0, which leaves t unchanged).
+template <int G>
+__device__ __forceinline__ void clock_from(double &t, uint32_t dlo, uint32_t dhi, int done)
+{
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+        t += __longlong_as_double((long long)(((uint64_t)rl(dhi, 8 * G + u) << 32) | rl(dlo, 8 * G + u)));
+    if constexpr (G < 7) {
+        if (done > 8 * (G + 1)) clock_from<G + 1>(t, dlo, dhi, done);
+    }
+}
+
 template <bool MOVING>
 __device__ void coop_walk(Packet1D &q, const uint8_t *__restrict__ tb, const DevCloud *__restrict__ clouds,
                           const WalkArgs &a, unsigned long long *__restrict__ tally, int lane)
 {
-    constexpr int WB = 16;
-    int wi = -1, jw = 0;
+    int wi = -1, jb = 0;
     int short_run = 0;   // consecutive blocks stopped by a slow-path step within 16 steps
     uint32_t v_lk = 0u, v_dhi = 0u, v_shi = 0u, v_fhi = 0u;
     while (q.active) {
@@ -682,103 +731,97 @@ __device__ void coop_walk(Packet1D &q, const uint8_t *__restrict__ tb, const Dev
             break;
         }
         const int m = left < 64 ? (int)left : 64;
-        if (q.i != wi || (q.j - jw < 2 && jw > 0) || (q.j - jw > WB - 3 && jw < q.nb - WB)) {
-            jw = q.j - WB / 2;
-            if (jw > q.nb - WB) jw = q.nb - WB;
-            if (jw < 0) jw = 0;
+        // band of 64 bins around the packet (reloaded on a new cell or near its edges)
+        if (q.i != wi || (q.j - jb < kCoopWin / 2 && jb > 0) ||
+            (q.j - jb > 63 - kCoopWin / 2 && jb < q.nb - 64)) {
+            jb = q.j - 32;
+            if (jb > q.nb - 64) jb = q.nb - 64;
+            if (jb < 0) jb = 0;
             wi = q.i;
-            // sentinel bins beyond a small grid: every event there is "slow" (never reached)
+            // bins beyond the grid: every event there is "slow" (never reached)
             v_lk = 0u;
             v_dhi = 0u;
             v_shi = 0u;
             v_fhi = 0u;
-            if (lane < WB && jw + lane < q.nb) {
-                const uint4 r = q.hot[q.i * q.nb + jw + lane];
+            if (jb + lane < q.nb) {
+                const uint4 r = q.hot[q.i * q.nb + jb + lane];
                 v_lk = r.x;
                 v_dhi = r.y;
                 v_shi = r.z;
                 v_fhi = r.w;
             }
         }
+        int jw = q.j - kCoopWin / 2;
+        if (jw > jb + 64 - kCoopWin) jw = jb + 64 - kCoopWin;
+        if (jw < jb) jw = jb;
+        const int wb = jw - jb;   // band lane of window position 0
         const StepWords wl = words_of_step<MOVING>(q, q.steps + (uint64_t)lane, a);
-        const uint32_t tw = wl.t;
         const uint32_t ew = wl.e;
-        // per window bin b: bit b = "a move from b goes down", bit 16+b = "stop at b" (a
-        // slow-path step, or a move out of the window); ps bit b = slow-path step only
-        uint32_t pk = 0u, ps = 0u;
+        // the step's table: field b = next window position from position b
+        uint32_t tlo = 0u, thi = 15u << 28;
 #pragma unroll
-        for (int b = 0; b < WB; ++b) {
-            const uint32_t dh = rl(v_dhi, b), sh = rl(v_shi, b);
-            const uint32_t dn = ew < dh ? 1u : 0u;
-            const uint32_t sp = (ew >= sh) || (ew == dh) ? 1u : 0u;
-            const uint32_t out = b == 0 ? dn : (b == WB - 1 ? dn ^ 1u : 0u);
-            pk |= dn << b;
-            pk |= (sp | out) << (WB + b);
-            ps |= sp << b;
+        for (int b = 0; b < kCoopWin; ++b) {
+            const uint32_t dh = rl(v_dhi, wb + b), sh = rl(v_shi, wb + b);
+            const bool dn = ew < dh;
+            const bool slow = (ew >= sh) || (ew == dh);
+            const uint32_t mv = dn ? (b == 0 ? 15u : (uint32_t)(b - 1)) : (b == kCoopWin - 1 ? 15u : (uint32_t)(b + 1));
+            const uint32_t nx = slow ? 15u : mv;
+            if (b < 8) tlo |= nx << (4 * b);
+            else thi |= nx << (4 * (b - 8));
         }
-        // sequential part, scalar only: the window position and a mask of down moves
-        const int pos0 = q.j - jw;
-        int pos = pos0, l = 0;
-        uint64_t dmask = 0ull;
-        // four steps per pass while no stop occurs among them (one test for the four)
-        for (; l + 4 <= m; l += 4) {
-            const uint32_t k0 = rl(pk, l), k1 = rl(pk, l + 1), k2 = rl(pk, l + 2), k3 = rl(pk, l + 3);
-            const uint32_t s0 = k0 >> pos;
-            const int p1 = pos + 1 - 2 * (int)(s0 & 1u);
-            const uint32_t s1 = k1 >> (p1 & 31);
-            const int p2 = p1 + 1 - 2 * (int)(s1 & 1u);
-            const uint32_t s2 = k2 >> (p2 & 31);
-            const int p3 = p2 + 1 - 2 * (int)(s2 & 1u);
-            const uint32_t s3 = k3 >> (p3 & 31);
-            // a stop at step l+i (i > 0) counts only if the steps before it stayed in the
-            // window, which the stops before it guarantee (moving out of the window is a stop)
-            if (((s0 | s1 | s2 | s3) >> WB) & 1u) break;
-            const uint32_t d4 = (s0 & 1u) | ((s1 & 1u) << 1) | ((s2 & 1u) << 2) | ((s3 & 1u) << 3);
-            dmask |= (uint64_t)d4 << l;
-            pos = p3 + 1 - 2 * (int)(s3 & 1u);
+        if (lane >= m) {   // no step: stop there
+            tlo = 0xffffffffu;
+            thi = 0xffffffffu;
         }
-        for (; l < m; ++l) {   // one step at a time from the pass that saw a stop, and the rest
-            const uint32_t k = rl(pk, l) >> pos;
-            if ((k >> WB) & 1u) break;
-            const uint32_t dn = k & 1u;
-            dmask |= (uint64_t)dn << l;
-            pos += 1 - 2 * (int)dn;
-        }
+        // sequential part: the chain of positions, in scalar registers
+        uint32_t st = kScanWidth | ((uint32_t)(q.j - jw) << 2);
+        int vst = (int)kScanStop;
+        scan_from<0>(st, vst, tlo, thi);
+        // each lane's starting position; the first lane whose step stops
+        const int pl = (int)(((uint32_t)vst & 63u) >> 2);
+        const uint64_t tab = ((uint64_t)thi << 32) | tlo;
+        const bool stops = pl != 15 && ((uint32_t)(tab >> (4 * pl)) & 15u) == 15u;
+        const uint64_t sb = __ballot(stops);
+        const int ls = sb ? __ffsll((unsigned long long)sb) - 1 : 64;
+        // the records of the lane's bin
+        const int src = (wb + (pl < 15 ? pl : 0)) & 63;
+        const uint32_t lk = (uint32_t)__shfl((int)v_lk, src);
+        const uint32_t dhl = (uint32_t)__shfl((int)v_dhi, src);
+        const uint32_t shl = (uint32_t)__shfl((int)v_shi, src);
+        int done, pos;
         bool special = false;
-        if (l < m) {
-            if ((rl(ps, l) >> pos) & 1u) {
-                special = true;                    // step l takes the slow path
-            } else {                               // step l leaves the window: it is done
-                const uint32_t dn = (rl(pk, l) >> pos) & 1u;
-                dmask |= (uint64_t)dn << l;
-                pos += 1 - 2 * (int)dn;
-                ++l;
+        if (ls >= m) {                         // m steps, no stop
+            done = m;
+            pos = ls < 64 ? (int)rl((uint32_t)pl, ls) : (int)((st & 63u) >> 2);
+        } else {
+            const uint32_t slow = ((ew >= shl) || (ew == dhl)) ? 1u : 0u;
+            const int p = (int)rl((uint32_t)pl, ls);
+            if (rl(slow, ls)) {                // step ls takes the slow path
+                special = true;
+                done = ls;
+                pos = p;
+            } else {                           // step ls leaves the window: it is done
+                done = ls + 1;
+                pos = p + (rl(ew < dhl ? 1u : 0u, ls) ? -1 : 1);
             }
         }
-        // lane l's bin before step l, from the moves before it
-        const int pl = pos0 + lane - 2 * __popcll(dmask & ((1ull << lane) - 1ull));
-        const uint32_t lk_bits = (uint32_t)__shfl((int)v_lk, pl & 63);
-        const float dl = path_length(tw, __uint_as_float(lk_bits));
+        const float dl = lane < done ? path_length(wl.t, __uint_as_float(lk)) : 0.0f;
+        const double dd = (double)dl;
+        const uint32_t dlo = (uint32_t)__double_as_longlong(dd);
+        const uint32_t dhi = (uint32_t)((uint64_t)__double_as_longlong(dd) >> 32);
         double t = q.t;                    // the lane walk's order of FP64 additions
-        int k = 0;
-        for (; k + 4 <= l; k += 4) {
-            t += (double)__uint_as_float(rl(__float_as_uint(dl), k));
-            t += (double)__uint_as_float(rl(__float_as_uint(dl), k + 1));
-            t += (double)__uint_as_float(rl(__float_as_uint(dl), k + 2));
-            t += (double)__uint_as_float(rl(__float_as_uint(dl), k + 3));
-        }
-        for (; k < l; ++k) t += (double)__uint_as_float(rl(__float_as_uint(dl), k));
+        if (done > 0) clock_from<0>(t, dlo, dhi, done);
         q.t = t;
-        q.steps += (uint64_t)l;
+        q.steps += (uint64_t)done;
         const int jj = jw + pos;
         q.j = jj;
-        short_run = special && l < 16 ? short_run + 1 : 0;
+        short_run = special && done < 16 ? short_run + 1 : 0;
         if (special) {
-            // the step at l in lane 0 with the lane walk's arithmetic; then, if several
+            // the step at `done` in lane 0 with the lane walk's arithmetic; then, if several
             // blocks in a row stopped early (spatial leaks dominate here), a run of single
             // steps in lane 0
-            const int b = jj - jw;
-            const StepWords ws = {rl(tw, l), rl(ew, l), rl(wl.z, l), rl(wl.w, l)};
+            const int b = (jj - jb) & 63;
+            const StepWords ws = {rl(wl.t, done), rl(ew, done), rl(wl.z, done), rl(wl.w, done)};
             const uint4 rec = make_uint4(rl(v_lk, b), rl(v_dhi, b), rl(v_shi, b), rl(v_fhi, b));
             Packet1D s1 = q;
             if (lane == 0) {
