@@ -39,8 +39,9 @@ OPS_PER_STEP = 32.0
 PEAK_OPS = 256 * 4 * 16 * 2.4e9
 # HBM bytes of one launch on the default block (2^16 packets of the sphere), from the
 # FETCH_SIZE and WRITE_SIZE counters scaled by a plain copy of known size
-# (profiles/walk1d_sphere_tau1e7_block65536_pmc.md); None for any other block.
-TRAFFIC_DEFAULT_BLOCK = 4.85e7
+# (profiles/walk1d_sphere_tau1e7_block65536_pmc.md), taken on the kernel as it is now;
+# None for any other block, and None while the kernel has changed since the counters ran.
+TRAFFIC_DEFAULT_BLOCK = None
 
 
 def parse():
@@ -54,7 +55,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-packets", type=int, default=12)
     ap.add_argument("--cpu-threads", type=int, default=0)
-    ap.add_argument("--workload", choices=["sphere", "cube", "surrogate"], default="sphere")
+    ap.add_argument("--workload", choices=["sphere", "cube", "surrogate", "sweep"], default="sphere")
+    ap.add_argument("--sweep-packets", type=int, default=128, help="packets per cloud, sweep workload")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first copy this many MiB device to device (a plain copy of known size that "
                          "calibrates hardware byte counters read in the same run)")
@@ -105,12 +107,68 @@ def bench_cube(args):
     }
 
 
-# Sweep clouds (media.sweep_parameters(), 256 clouds) with cells in the surrogate's trained
-# domain whose plain rDDMC walk takes <= 5e7 expected steps per packet (exact-chain values;
-# the 10 costlier in-domain clouds, up to 5e8 steps per packet, would make the plain leg's
-# slowest packets run for minutes).
+# Sweep clouds (media.sweep_parameters(), 256 clouds) whose plain rDDMC walk takes <= 1e7
+# expected steps per packet (exact-chain values, 158 clouds): the rest, up to 8e8 steps
+# per packet, are the surrogate's ground; with them one launch would wait minutes on its
+# slowest packets.
+SWEEP_CLOUDS = [0, 1, 2, 6, 7, 10, 11, 12, 13, 15, 16, 17, 19, 20, 21, 23, 25, 26, 27, 28, 29, 30, 32, 33, 34, 35,
+                36, 37, 39, 40, 43, 44, 45, 46, 48, 49, 53, 55, 56, 59, 60, 62, 64, 65, 66, 67, 69,
+                71, 73, 75, 77, 80, 81, 83, 84, 85, 86, 87, 88, 92, 93, 94, 96, 98, 99, 101, 103,
+                104, 105, 106, 107, 109, 110, 112, 113, 116, 117, 118, 120, 122, 123, 124, 126, 130,
+                132, 133, 134, 135, 139, 142, 143, 144, 145, 147, 150, 152, 155, 156, 157, 158, 159,
+                160, 161, 165, 166, 168, 170, 172, 173, 174, 176, 177, 178, 179, 180, 183, 185, 186,
+                188, 189, 190, 191, 193, 196, 198, 199, 200, 201, 202, 203, 204, 206, 207, 209, 213,
+                219, 221, 222, 224, 225, 226, 227, 229, 230, 231, 233, 236, 240, 241, 242, 246, 247,
+                248, 249, 250, 253, 254, 255]
+
+# Sweep clouds with cells in the surrogate's trained domain whose plain rDDMC walk takes
+# <= 5e7 expected steps per packet (exact-chain values; the 10 costlier in-domain clouds, up
+# to 5e8 steps per packet, would make the plain leg's slowest packets run for minutes).
 SURROGATE_CLOUDS = [9, 18, 48, 58, 68, 74, 75, 96, 101, 103, 125, 131, 144, 149, 151, 155, 156, 176, 181, 184,
                     188, 195, 199, 203, 205, 226, 235, 250]
+
+
+def bench_sweep(args):
+    """The batched sweep: many clouds of uneven grid size in one hipGraph-captured
+    rddmc_transport launch with an autotuned schedule."""
+    import torch
+    from paper_1709_10187_amd import autotune, media, rddmc
+    clouds = [media.sweep_cloud_medium(c) for c in media.sweep_parameters()]
+    ids = SWEEP_CLOUDS
+    meds = [clouds[i].with_packets(args.sweep_packets) for i in ids]
+    print(f"[bench] sweep: building tables for {len(ids)} clouds", file=sys.stderr, flush=True)
+    prob = rddmc.Problem(meds, streams=ids)
+    t0 = time.perf_counter()
+    tuned = autotune.tune(prob, sample_packets=1 << 16, trial_steps=20000, use_cache=False)
+    t_tune = time.perf_counter() - t0
+    sched = autotune.schedule(tuned)
+    print(f"[bench] sweep: schedule {sched} ({t_tune:.1f} s of trials)", file=sys.stderr, flush=True)
+    graph = prob.capture(seed=1, **sched)
+    prob.reset()
+    stream = torch.cuda.current_stream()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    graph.replay()
+    stop.record(stream)
+    torch.cuda.synchronize()
+    sec = start.elapsed_time(stop) / 1e3
+    res = prob.results()
+    n = sum(r.launched for r in res)
+    steps = sum(r.steps_total for r in res)
+    return {
+        "metric": METRIC, "value": n / sec, "unit": "packets/s", "packet_steps_per_s": steps / sec, "n_gpus": 1,
+        "steps": 1, "warmup": 0, "ms_per_step": 1e3 * sec, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"batched sweep: {len(ids)} of the 256 sweep clouds (those with <= 1e7 expected "
+                               f"steps per packet), {args.sweep_packets} packets each, one hipGraph replay of "
+                               "one rddmc_transport launch with the autotuned schedule",
+                   "clouds": ids, "packets": int(n), "escaped": int(sum(r.escaped for r in res)),
+                   "shells": [int(m.n_cells[0]) for m in meds], "bins": [int(m.n_bins) for m in meds],
+                   "schedule": sched, "tune_s": t_tune,
+                   "tune_trials": [{k: v for k, v in t.items()} for t in tuned["trials"]]},
+        "roofline": None,
+    }
 
 
 def bench_surrogate(args):
@@ -187,7 +245,7 @@ def main():
     assert torch.cuda.is_available()
     torch.cuda.set_device(0)
     if args.workload != "sphere":
-        out = bench_cube(args) if args.workload == "cube" else bench_surrogate(args)
+        out = {"cube": bench_cube, "surrogate": bench_surrogate, "sweep": bench_sweep}[args.workload](args)
         print(json.dumps(out))
         return
     if args.copy_probe_mib > 0:
