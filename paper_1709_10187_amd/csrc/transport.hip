@@ -352,6 +352,67 @@ __device__ void single_steps(Packet1D &p, int n, const uint8_t *__restrict__ tb,
     }
 }
 
+// One step's fast path as selects (no branches): the clock advances for every enabled lane;
+// a frequency move or a spatial move inside the grid is applied; returns true when the step
+// needs the slow path (a tie with a threshold's high word, or a leak out of the grid), which
+// the caller runs.  Disabled lanes change nothing.  The arithmetic is that of one_step.
+__device__ __forceinline__ bool select_step(Packet1D &p, bool en, uint32_t tw, uint32_t ew, uint4 rec, int &d)
+{
+    const double tn = p.t + (double)path_length(tw, __uint_as_float(rec.x));
+    p.t = en ? tn : p.t;
+    const bool tie = (ew == rec.y) | (ew == rec.z) | (ew == rec.w);
+    const bool freq = ew < rec.z;
+    const int dj = ew < rec.y ? -1 : 1;
+    const int ni = ew < rec.w ? p.i - 1 : p.i + 1;
+    const bool inside = (unsigned)ni < (unsigned)p.nc;
+    const bool slow = en & (tie | (!freq & !inside));
+    const bool fast = en & !slow;
+    p.j = (fast & freq) ? p.j + dj : p.j;
+    p.i = (fast & !freq) ? ni : p.i;
+    p.steps += fast ? 1ull : 0ull;
+    d = slow ? 0 : (freq ? dj : 2);
+    return slow;
+}
+
+// Pairs of static-medium steps with wave-uniform control flow: every lane evaluates both
+// steps of a pair with selects, lanes that are done or past their budget are disabled, and
+// the slow path and record reloads run under masks only when some lane needs them.  Same
+// records, random words and arithmetic as one_step, so the same bits.
+template <bool MOVING>
+__device__ __forceinline__ void static_pairs(Packet1D &p, int budget, int last_state,
+                                             const uint8_t *__restrict__ tb, const DevCloud *__restrict__ clouds,
+                                             const WalkArgs &a, unsigned long long *__restrict__ tally)
+{
+    const float4 nomap = make_float4(1.f, 0.f, 1.f, 0.f);
+    for (int k = 0; k < a.chunk; ++k) {
+        const bool en = p.active && k < budget;
+        if (!__any(en)) break;
+        // disabled lanes read the first records of the table buffer (always mapped; unused)
+        const uint4 *h = en ? p.hot : reinterpret_cast<const uint4 *>(tb);
+        const int s = en ? p.i * p.nb + p.j : 0;
+        const uint4 rm = h[s > 0 ? s - 1 : 0];
+        const uint4 r0 = h[s];
+        const uint4 rp = h[en && s < last_state ? s + 1 : s];
+        const uint64_t pair = p.steps >> 1;
+        const u32x4 r = philox4x32_10((uint32_t)pair, (uint32_t)(pair >> 32), p.pid, p.key, a.key0, a.key1);
+        int d;
+        const bool s1 = select_step(p, en, r.x, r.y, r0, d);
+        if (__any(s1)) {
+            if (s1) slow_step<MOVING>(p, StepWords{r.x, r.y, 0u, 0u}, r0, nomap, tb, clouds, a, tally);
+        }
+        const bool en2 = en && p.active && p.steps < a.max_steps;
+        uint4 rb = d == -1 ? rm : rp;
+        const bool reload = en2 && (d == 0 || d == 2);   // after a spatial move or a slow step
+        if (__any(reload)) {
+            if (reload) rb = p.hot[p.i * p.nb + p.j];
+        }
+        const bool s2 = select_step(p, en2, r.z, r.w, rb, d);
+        if (__any(s2)) {
+            if (s2) slow_step<MOVING>(p, StepWords{r.z, r.w, 0u, 0u}, rb, nomap, tb, clouds, a, tally);
+        }
+    }
+}
+
 // 1D walk (slab or sphere), pure DDMC; MOVING enables Doppler re-binning and lab-frame
 // escape frequencies.  Static media take one Philox block per pair of steps ((x, y) for the
 // even step and (z, w) for the odd one; all active lanes of a wave are at even step counts
@@ -597,7 +658,12 @@ __global__ __launch_bounds__(256) void walk1d(const uint8_t *__restrict__ tb, Wa
         // ---- walk up to `chunk` pairs of steps ---------------------------------------
         const bool was_active = p.active;
         const uint64_t left = p.active ? (a.max_steps - p.steps) : 0ull;
-        if (!(MOVING && p.moving)) {
+        if (!SURR && !(MOVING && p.moving)) {
+            const uint64_t pairs = (left + 1) >> 1;
+            const int budget = pairs < (uint64_t)a.chunk ? (int)pairs : a.chunk;
+            static_pairs<MOVING>(p, budget, last_state, tb, clouds, a, tally);
+        }
+        if (SURR && !(MOVING && p.moving)) {
             const uint64_t pairs = (left + 1) >> 1;
             const int budget = pairs < (uint64_t)a.chunk ? (int)pairs : a.chunk;
             for (int k = 0; k < budget; ++k) {
