@@ -774,9 +774,12 @@ __device__ __forceinline__ void scan_from(uint32_t &st, int &vst, uint32_t tlo, 
 template <int G>
 __device__ __forceinline__ void clock_from(double &t, uint32_t dlo, uint32_t dhi, int done)
 {
+    double v[8];   // read the group's eight values first, then add them in order
 #pragma unroll
     for (int u = 0; u < 8; ++u)
-        t += __longlong_as_double((long long)(((uint64_t)rl(dhi, 8 * G + u) << 32) | rl(dlo, 8 * G + u)));
+        v[u] = __longlong_as_double((long long)(((uint64_t)rl(dhi, 8 * G + u) << 32) | rl(dlo, 8 * G + u)));
+#pragma unroll
+    for (int u = 0; u < 8; ++u) t += v[u];
     if constexpr (G < 7) {
         if (done > 8 * (G + 1)) clock_from<G + 1>(t, dlo, dhi, done);
     }
@@ -823,11 +826,14 @@ __device__ void coop_walk(Packet1D &q, const uint8_t *__restrict__ tb, const Dev
         const int wb = jw - jb;   // band lane of window position 0
         const StepWords wl = words_of_step<MOVING>(q, q.steps + (uint64_t)lane, a);
         const uint32_t ew = wl.e;
+        // the window's thresholds rotated into lanes 0..14
+        const uint32_t wdh = (uint32_t)__shfl((int)v_dhi, (wb + lane) & 63);
+        const uint32_t wsh = (uint32_t)__shfl((int)v_shi, (wb + lane) & 63);
         // the step's table: field b = next window position from position b
         uint32_t tlo = 0u, thi = 15u << 28;
 #pragma unroll
         for (int b = 0; b < kCoopWin; ++b) {
-            const uint32_t dh = rl(v_dhi, wb + b), sh = rl(v_shi, wb + b);
+            const uint32_t dh = rl(wdh, b), sh = rl(wsh, b);
             const bool dn = ew < dh;
             const bool slow = (ew >= sh) || (ew == dh);
             const uint32_t mv = dn ? (b == 0 ? 15u : (uint32_t)(b - 1)) : (b == kCoopWin - 1 ? 15u : (uint32_t)(b + 1));
