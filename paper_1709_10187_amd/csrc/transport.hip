@@ -729,9 +729,10 @@ __global__ __launch_bounds__(256) void walk1d(const uint8_t *__restrict__ tb, Wa
 //     over the window: 4 bits per window position giving the next position, or 15 ("stop")
 //     for a slow-path step (a tie with a threshold, a spatial leak) or a move out of the
 //     window; position 15 maps to itself.
-//   * The sequential part is a scalar chain of two instructions per step (a 4-bit field
-//     extract addressed by the position, a shift-add back to an address); every lane
-//     receives the position its step starts from.
+//   * Each even lane composes its table with the next lane's (two steps per table); the
+//     sequential part is a scalar chain of two instructions per pair of steps (a 4-bit
+//     field extract addressed by the position, a shift-add back to an address); even
+//     lanes receive the position their step starts from, odd lanes take one step from it.
 //   * The lane whose step stops classifies it: a move out of the window completes, a
 //     slow-path step runs in lane 0 with the lane walk's arithmetic.
 // The clock adds the same f32 path lengths in the same order as the lane walk, so every
@@ -753,17 +754,15 @@ __device__ __forceinline__ void scan_step(uint32_t &st, int &vst, uint32_t tlo, 
     asm("s_lshl2_add_u32 %0, %1, %2" : "=s"(st) : "s"((uint32_t)f), "s"(kScanWidth) : "scc");
 }
 
+// The chain over two-step tables held by the even lanes (lane 2k: steps 2k and 2k+1),
+// eight steps per group, leaving once the stop is reached.
 template <int G>
 __device__ __forceinline__ void scan_from(uint32_t &st, int &vst, uint32_t tlo, uint32_t thi)
 {
     scan_step<8 * G + 0>(st, vst, tlo, thi);
-    scan_step<8 * G + 1>(st, vst, tlo, thi);
     scan_step<8 * G + 2>(st, vst, tlo, thi);
-    scan_step<8 * G + 3>(st, vst, tlo, thi);
     scan_step<8 * G + 4>(st, vst, tlo, thi);
-    scan_step<8 * G + 5>(st, vst, tlo, thi);
     scan_step<8 * G + 6>(st, vst, tlo, thi);
-    scan_step<8 * G + 7>(st, vst, tlo, thi);
     if constexpr (G < 7) {
         if (st != kScanStop) scan_from<G + 1>(st, vst, tlo, thi);
     }
@@ -845,13 +844,27 @@ __device__ void coop_walk(Packet1D &q, const uint8_t *__restrict__ tb, const Dev
             tlo = 0xffffffffu;
             thi = 0xffffffffu;
         }
-        // sequential part: the chain of positions, in scalar registers
+        // even lanes: the table of two steps (this lane's, then the next lane's)
+        const uint64_t tab = ((uint64_t)thi << 32) | tlo;
+        const uint64_t nxt = ((uint64_t)(uint32_t)__shfl_down((int)thi, 1) << 32) | (uint32_t)__shfl_down((int)tlo, 1);
+        uint32_t clo = 0u, chi = 0u;
+#pragma unroll
+        for (int b = 0; b < 16; ++b) {
+            const uint32_t mid = (uint32_t)(tab >> (4 * b)) & 15u;
+            const uint32_t two = (uint32_t)(nxt >> (4 * mid)) & 15u;
+            if (b < 8) clo |= two << (4 * b);
+            else chi |= two << (4 * (b - 8));
+        }
+        // sequential part: the chain of positions, in scalar registers, two steps at a time
         uint32_t st = kScanWidth | ((uint32_t)(q.j - jw) << 2);
         int vst = (int)kScanStop;
-        scan_from<0>(st, vst, tlo, thi);
-        // each lane's starting position; the first lane whose step stops
-        const int pl = (int)(((uint32_t)vst & 63u) >> 2);
-        const uint64_t tab = ((uint64_t)thi << 32) | tlo;
+        scan_from<0>(st, vst, clo, chi);
+        // each lane's starting position (odd lanes: one step from the even lane before);
+        // the first lane whose step stops
+        const int pe = (int)(((uint32_t)vst & 63u) >> 2);
+        const uint32_t ne = (uint32_t)(tab >> (4 * pe)) & 15u;
+        const uint32_t from_even = (uint32_t)__shfl_up((int)ne, 1);
+        const int pl = (lane & 1) ? (int)from_even : pe;
         const bool stops = pl != 15 && ((uint32_t)(tab >> (4 * pl)) & 15u) == 15u;
         const uint64_t sb = __ballot(stops);
         const int ls = sb ? __ffsll((unsigned long long)sb) - 1 : 64;
