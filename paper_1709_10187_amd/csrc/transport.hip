@@ -234,6 +234,15 @@ struct StepWords {
 
 // Comoving re-binning across face `face` (Sec. 2.5, eq. 20): x uniform in bin j, mapped to
 // the neighbour's frame x' = rho x + shift, re-binned and clamped to the grid.
+// The neighbour's bin on a uniform grid (before clamping), with explicit rounding so that
+// every walker computes the same bits.
+__device__ __forceinline__ int rebin_uniform(const Packet1D &p, float rho, float sh, uint32_t zw)
+{
+    const float u = __fmul_rn(__fadd_rn((float)(zw >> 8), 0.5f), 5.9604644775390625e-8f);   // 24-bit uniform
+    const float x = __fmaf_rn(__fadd_rn((float)p.j, u), p.dx, p.x0);
+    return (int)floorf(__fmul_rn(__fsub_rn(__fmaf_rn(rho, x, sh), p.x0), p.inv_dx));
+}
+
 __device__ __forceinline__ void rebin(Packet1D &p, int face, float4 cm, uint32_t zw,
                                       const DevCloud &c, const uint8_t *__restrict__ tb)
 {
@@ -242,9 +251,7 @@ __device__ __forceinline__ void rebin(Packet1D &p, int face, float4 cm, uint32_t
     if (rho == 1.0f && sh == 0.0f) return;
     int jn;
     if (p.uniform) {
-        const float u = ((float)(zw >> 8) + 0.5f) * 5.9604644775390625e-8f;   // 24-bit uniform
-        const float x = p.x0 + ((float)p.j + u) * p.dx;
-        jn = (int)floorf((fmaf(rho, x, sh) - p.x0) * p.inv_dx);
+        jn = rebin_uniform(p, rho, sh, zw);
     } else {
         const double *e = reinterpret_cast<const double *>(tb + c.off_edges);
         const double x = e[p.j] + (e[p.j + 1] - e[p.j]) * u01_open_low(zw);
@@ -409,6 +416,61 @@ __device__ __forceinline__ void static_pairs(Packet1D &p, int budget, int last_s
         const bool s2 = select_step(p, en2, r.z, r.w, rb, d);
         if (__any(s2)) {
             if (s2) slow_step<MOVING>(p, StepWords{r.z, r.w, 0u, 0u}, rb, nomap, tb, clouds, a, tally);
+        }
+    }
+}
+
+// One moving-medium step as selects: like select_step, with the Doppler re-binning of a
+// spatial move (eq. 20) computed inline on uniform grids; on other grids the lanes that
+// moved spatially re-bin under a mask.  The arithmetic is that of one_step.
+__device__ __forceinline__ bool select_step_moving(Packet1D &p, bool en, StepWords w, uint4 rec, float4 cm,
+                                                   const DevCloud *__restrict__ clouds,
+                                                   const uint8_t *__restrict__ tb)
+{
+    const double tn = p.t + (double)path_length(w.t, __uint_as_float(rec.x));
+    p.t = en ? tn : p.t;
+    const uint32_t ew = w.e;
+    const bool tie = (ew == rec.y) | (ew == rec.z) | (ew == rec.w);
+    const bool freq = ew < rec.z;
+    const int dj = ew < rec.y ? -1 : 1;
+    const bool up = ew >= rec.w;   // face 1 (upper / outer)
+    const int ni = up ? p.i + 1 : p.i - 1;
+    const bool inside = (unsigned)ni < (unsigned)p.nc;
+    const bool slow = en & (tie | (!freq & !inside));
+    const bool fast = en & !slow;
+    const bool spatial = fast & !freq;
+    const float rho = up ? cm.z : cm.x;
+    const float sh = up ? cm.w : cm.y;
+    const bool ident = (rho == 1.0f) & (sh == 0.0f);
+    int jn = rebin_uniform(p, rho, sh, w.z);
+    jn = jn < 0 ? 0 : (jn > p.nb - 1 ? p.nb - 1 : jn);
+    const bool other_grid = spatial & !ident & !p.uniform;
+    p.j = (fast & freq) ? p.j + dj : ((spatial & !ident & p.uniform) ? jn : p.j);
+    if (__any(other_grid)) {
+        if (other_grid) rebin(p, up ? 1 : 0, cm, w.z, clouds[p.cl], tb);
+    }
+    p.i = spatial ? ni : p.i;
+    p.steps += fast ? 1ull : 0ull;
+    return slow;
+}
+
+// Moving-medium steps (one Philox block each) with wave-uniform control flow.
+__device__ __forceinline__ void moving_steps(Packet1D &p, int budget, const uint8_t *__restrict__ tb,
+                                             const DevCloud *__restrict__ clouds, const WalkArgs &a,
+                                             unsigned long long *__restrict__ tally)
+{
+    const int lim = 2 * a.chunk;
+    for (int k = 0; k < lim; ++k) {
+        const bool en = p.active && k < budget;
+        if (!__any(en)) break;
+        // disabled lanes read the first words of the table buffer (always mapped; unused)
+        const uint4 rec = (en ? p.hot : reinterpret_cast<const uint4 *>(tb))[en ? p.i * p.nb + p.j : 0];
+        const float4 cm = (en ? p.cmap : reinterpret_cast<const float4 *>(tb))[en ? p.i : 0];
+        const u32x4 r = philox4x32_10((uint32_t)p.steps, (uint32_t)(p.steps >> 32), p.pid, p.key, a.key0, a.key1);
+        const StepWords w{r.x, r.y, r.z, r.w};
+        const bool slow = select_step_moving(p, en, w, rec, cm, clouds, tb);
+        if (__any(slow)) {
+            if (slow) slow_step<true>(p, w, rec, cm, tb, clouds, a, tally);
         }
     }
 }
@@ -692,7 +754,12 @@ __global__ __launch_bounds__(256) void walk1d(const uint8_t *__restrict__ tb, Wa
                 if (!p.active) break;
             }
         }
-        if (MOVING && p.moving) {
+        if (!SURR && MOVING && p.moving) {
+            const uint64_t lim = 2ull * (uint64_t)a.chunk;
+            const int budget = left < lim ? (int)left : (int)lim;
+            moving_steps(p, budget, tb, clouds, a, tally);
+        }
+        if (SURR && MOVING && p.moving) {
             const uint64_t lim = 2ull * (uint64_t)a.chunk;
             const int budget = left < lim ? (int)left : (int)lim;
             for (int k = 0; k < budget; ++k) {
