@@ -835,6 +835,50 @@ __device__ __forceinline__ void scan_from(uint32_t &st, int &vst, uint32_t tlo, 
     }
 }
 
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xf, 0xf, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+__device__ __forceinline__ double rl_f64(double v, int lane)
+{
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    return __longlong_as_double((long long)(((uint64_t)rl((uint32_t)(b >> 32), lane) << 32) | rl((uint32_t)b, lane)));
+}
+
+// Clock of a block without the sequential chain, where that gives the same bits.  With
+// t0 in [2^e, 2^(e+1)), ulp = 2^(e-52), and every partial sum below 2^(e+1), each
+// addition t + d (d >= 0) rounds to t + ulp * rint(d / ulp), unless d / ulp lies exactly
+// halfway between integers (then the rounding depends on the running sum).  Without such
+// a tie the block's result is t0 + ulp * (sum of the rint values): an exact integer sum,
+// reduced across the wave in any order.  Returns false (t unchanged) where the premises
+// fail; the caller then adds in order.
+__device__ __forceinline__ bool clock_parallel(double &t, double dd)
+{
+    const uint64_t tbits = (uint64_t)__double_as_longlong(t);
+    const int be = (int)((tbits >> 52) & 0x7ffu);
+    if (be == 0 || be >= 0x7fe) return false;        // zero, subnormal or near the top
+    const int e = be - 1023;
+    const double qv = ldexp(dd, 52 - e);               // exact: a power-of-two scaling
+    const double n = rint(qv);
+    const bool tie = (qv - floor(qv)) == 0.5;
+    if (__any(tie)) return false;
+    double s = n;                                      // integers below 2^53: exact sums
+    s += dpp_f64<0xb1>(s);                             // quad_perm [1,0,3,2]
+    s += dpp_f64<0x4e>(s);                             // quad_perm [2,3,0,1]
+    s += dpp_f64<0x124>(s);                            // row_ror:4
+    s += dpp_f64<0x128>(s);                            // row_ror:8
+    const double S = (rl_f64(s, 0) + rl_f64(s, 16)) + (rl_f64(s, 32) + rl_f64(s, 48));
+    const double tf = t + ldexp(S, e - 52);
+    if (!(tf < ldexp(1.0, e + 1))) return false;       // left the binade: add in order
+    t = tf;
+    return true;
+}
+
 // Clock of a block: t += the FP64 path lengths of lanes 0, 1, ... in order (lanes at or
 // beyond `done` hold +0, which leaves t unchanged).
 template <int G>
@@ -961,8 +1005,8 @@ __device__ void coop_walk(Packet1D &q, const uint8_t *__restrict__ tb, const Dev
         const double dd = (double)dl;
         const uint32_t dlo = (uint32_t)__double_as_longlong(dd);
         const uint32_t dhi = (uint32_t)((uint64_t)__double_as_longlong(dd) >> 32);
-        double t = q.t;                    // the lane walk's order of FP64 additions
-        if (done > 0) clock_from<0>(t, dlo, dhi, done);
+        double t = q.t;                    // the lane walk's FP64 additions, same bits
+        if (done > 0 && !clock_parallel(t, dd)) clock_from<0>(t, dlo, dhi, done);
         q.t = t;
         q.steps += (uint64_t)done;
         const int jj = jw + pos;
