@@ -454,12 +454,12 @@ __device__ __forceinline__ bool select_step_moving(Packet1D &p, bool en, StepWor
     return slow;
 }
 
-// Moving-medium steps (one Philox block each) with wave-uniform control flow.
-__device__ __forceinline__ void moving_steps(Packet1D &p, int budget, const uint8_t *__restrict__ tb,
+// Moving-medium steps (one Philox block each) with wave-uniform control flow: at most
+// `lim` iterations, lanes past their own `budget` disabled.
+__device__ __forceinline__ void moving_steps(Packet1D &p, int budget, int lim, const uint8_t *__restrict__ tb,
                                              const DevCloud *__restrict__ clouds, const WalkArgs &a,
                                              unsigned long long *__restrict__ tally)
 {
-    const int lim = 2 * a.chunk;
     for (int k = 0; k < lim; ++k) {
         const bool en = p.active && k < budget;
         if (!__any(en)) break;
@@ -757,7 +757,7 @@ __global__ __launch_bounds__(256) void walk1d(const uint8_t *__restrict__ tb, Wa
         if (!SURR && MOVING && p.moving) {
             const uint64_t lim = 2ull * (uint64_t)a.chunk;
             const int budget = left < lim ? (int)left : (int)lim;
-            moving_steps(p, budget, tb, clouds, a, tally);
+            moving_steps(p, budget, (int)lim, tb, clouds, a, tally);
         }
         if (SURR && MOVING && p.moving) {
             const uint64_t lim = 2ull * (uint64_t)a.chunk;
@@ -1015,7 +1015,7 @@ __device__ void coop_walk(Packet1D &q, const uint8_t *__restrict__ tb, const Dev
         if (special) {
             // the step at `done` in lane 0 with the lane walk's arithmetic; then, if several
             // blocks in a row stopped early (spatial leaks dominate here), a run of single
-            // steps in lane 0
+            // steps in lane 0, twice as long (up to 1024) for every further such block
             const int b = (jj - jb) & 63;
             const StepWords ws = {rl(wl.t, done), rl(ew, done), rl(wl.z, done), rl(wl.w, done)};
             const uint4 rec = make_uint4(rl(v_lk, b), rl(v_dhi, b), rl(v_shi, b), rl(v_fhi, b));
@@ -1023,7 +1023,16 @@ __device__ void coop_walk(Packet1D &q, const uint8_t *__restrict__ tb, const Dev
             if (lane == 0) {
                 const float4 cm = (MOVING && s1.moving) ? s1.cmap[s1.i] : make_float4(1.f, 0.f, 1.f, 0.f);
                 one_step<MOVING>(s1, ws, rec, cm, tb, clouds, a, tally);
-                if (short_run >= 3) single_steps<MOVING>(s1, 64, tb, clouds, a, tally);
+                if (short_run >= 3) {
+                    const int n = 64 << (short_run - 3 < 4 ? short_run - 3 : 4);
+                    if (MOVING && s1.moving) {
+                        const uint64_t left = s1.active ? a.max_steps - s1.steps : 0ull;
+                        const int budget = left < (uint64_t)n ? (int)left : n;
+                        moving_steps(s1, budget, budget, tb, clouds, a, tally);
+                    } else {
+                        single_steps<MOVING>(s1, n, tb, clouds, a, tally);
+                    }
+                }
             }
             q.i = (int)rl((uint32_t)s1.i, 0);
             q.j = (int)rl((uint32_t)s1.j, 0);
