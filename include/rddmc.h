@@ -130,8 +130,9 @@ typedef struct {
  *                bit-identical either way.
  *   surrogate    1D clouds: learned escape surrogate (rddmc_surrogate_attach) or NULL for
  *                plain rDDMC; with it, a packet in a state of its cloud's surrogate window
- *                leaves the cell by one exit drawn from the learned law (no cooperative
- *                tail walk).
+ *                leaves the cell by one exit drawn from the learned law (checked before
+ *                every step in moving clouds, at even step counts in static ones, in the
+ *                lane walk and the cooperative tail walk alike).
  */
 typedef struct {
     uint64_t seed;

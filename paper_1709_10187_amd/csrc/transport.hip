@@ -57,7 +57,7 @@ struct TailPacket {        // 48 bytes
     int32_t i, j;
     uint64_t steps;
     double t;
-    uint32_t flag, pad0;
+    uint32_t flag, surr_calls;   // slot state; surrogate exits the packet took before
     uint64_t pad1;
 };
 constexpr uint32_t kSlotEmpty = 0u, kSlotReady = 1u, kSlotTaken = 2u, kSlotAbandoned = 3u;
@@ -344,14 +344,35 @@ __device__ __forceinline__ StepWords words_of_step(const Packet1D &p, uint64_t s
     return (step & 1) ? StepWords{r.z, r.w, 0u, 0u} : StepWords{r.x, r.y, 0u, 0u};
 }
 
-// A few single steps of one packet (lane-walk arithmetic), used by the cooperative walk
-// where spatial leaks dominate.
+// A few single steps of one packet (lane-walk arithmetic), used by the cooperative walk on
+// static media where spatial leaks dominate (moving media use moving_steps).
 template <bool MOVING>
 __device__ void single_steps(Packet1D &p, int n, const uint8_t *__restrict__ tb,
                              const DevCloud *__restrict__ clouds, const WalkArgs &a,
                              unsigned long long *__restrict__ tally)
 {
     for (int k = 0; k < n && p.active && p.steps < a.max_steps; ++k) {
+        const StepWords w = words_of_step<MOVING>(p, p.steps, a);
+        const uint4 rec = p.hot[p.i * p.nb + p.j];
+        const float4 cm = (MOVING && p.moving) ? p.cmap[p.i] : make_float4(1.f, 0.f, 1.f, 0.f);
+        one_step<MOVING>(p, w, rec, cm, tb, clouds, a, tally);
+    }
+}
+
+// Single steps of one packet with the lane walk's surrogate exits (a step that starts in the
+// window is replaced by one exit, at the lane walk's check points), used by the cooperative
+// walk where spatial leaks dominate.
+template <bool MOVING>
+__device__ void surr_single_steps(Packet1D &p, int n, const SurrWin &sw, const float *__restrict__ recs,
+                                  const uint8_t *__restrict__ tb, const DevCloud *__restrict__ clouds,
+                                  const WalkArgs &a, unsigned long long *__restrict__ tally)
+{
+    for (int k = 0; k < n && p.active && p.steps < a.max_steps; ++k) {
+        const bool chk = (MOVING && p.moving) || !(p.steps & 1ull);
+        if (chk && p.steps + 3ull <= a.max_steps && in_window(p, sw)) {
+            surrogate_exit<MOVING>(p, sw, recs, tb, clouds[p.cl], a);
+            continue;
+        }
         const StepWords w = words_of_step<MOVING>(p, p.steps, a);
         const uint4 rec = p.hot[p.i * p.nb + p.j];
         const float4 cm = (MOVING && p.moving) ? p.cmap[p.i] : make_float4(1.f, 0.f, 1.f, 0.f);
@@ -479,7 +500,7 @@ __device__ __forceinline__ void moving_steps(Packet1D &p, int budget, int lim, c
 // escape frequencies.  Static media take one Philox block per pair of steps ((x, y) for the
 // even step and (z, w) for the odd one; all active lanes of a wave are at even step counts
 // between pairs); moving media take one block per step.
-template <bool MOVING>
+template <bool MOVING, bool SURR>
 __device__ void coop_walk(Packet1D &q, const uint8_t *__restrict__ tb, const DevCloud *__restrict__ clouds,
                           const WalkArgs &a, unsigned long long *__restrict__ tally, int lane);
 
@@ -520,7 +541,7 @@ __device__ Packet1D load_slot(const TailPacket *ts, const uint8_t *__restrict__ 
     q.uniform = c.uniform_bins != 0;
     q.moving = c.moving != 0;
     q.active = true;
-    q.surr_calls = 0u;
+    q.surr_calls = rl(tk.surr_calls, 0);
     return q;
 }
 
@@ -530,7 +551,7 @@ __device__ Packet1D load_slot(const TailPacket *ts, const uint8_t *__restrict__ 
 // so the retries end); a claimed slot whose packet is not yet published is marked abandoned
 // (its exporter walks it).  With nothing to claim it exits once every producer wave has
 // finished, or after kConsumerIdlePolls polls; what it leaves, the closing kernel walks.
-template <bool MOVING>
+template <bool MOVING, bool SURR>
 __device__ void consume_exported(const uint8_t *__restrict__ tb, const DevCloud *__restrict__ clouds,
                                  const WalkArgs &a, unsigned long long *__restrict__ tally,
                                  unsigned long long *__restrict__ work, int lane)
@@ -588,7 +609,7 @@ __device__ void consume_exported(const uint8_t *__restrict__ tb, const DevCloud 
         }
         if (rl(got, 0) == 0u) continue;
         Packet1D q = load_slot(slots + idx, tb, clouds);
-        coop_walk<MOVING>(q, tb, clouds, a, tally, lane);
+        coop_walk<MOVING, SURR>(q, tb, clouds, a, tally, lane);
     }
 }
 
@@ -605,7 +626,7 @@ __global__ __launch_bounds__(256) void walk1d(const uint8_t *__restrict__ tb, Wa
     const uint64_t *prefix = reinterpret_cast<const uint64_t *>(tb + H->off_prefix);
     const int lane = threadIdx.x & 63;
     if (blockIdx.x >= a.producer_blocks) {   // a consumer block
-        consume_exported<MOVING>(tb, clouds, a, tally, work, lane);
+        consume_exported<MOVING, SURR>(tb, clouds, a, tally, work, lane);
         return;
     }
 
@@ -698,6 +719,7 @@ __global__ __launch_bounds__(256) void walk1d(const uint8_t *__restrict__ tb, Wa
                     tp->j = p.j;
                     tp->steps = p.steps;
                     tp->t = p.t;
+                    tp->surr_calls = p.surr_calls;
                     __threadfence();
                     uint32_t expect = kSlotEmpty;
                     keep = !__hip_atomic_compare_exchange_strong(&tp->flag, &expect, kSlotReady, __ATOMIC_RELEASE,
@@ -711,7 +733,7 @@ __global__ __launch_bounds__(256) void walk1d(const uint8_t *__restrict__ tb, Wa
                     mine &= mine - 1ull;
                     const uint64_t slot = base + __popcll(live & ((1ull << l) - 1ull));
                     Packet1D q = load_slot(slots_of(work) + slot, tb, clouds);
-                    coop_walk<MOVING>(q, tb, clouds, a, tally, lane);
+                    coop_walk<MOVING, SURR>(q, tb, clouds, a, tally, lane);
                 }
                 break;
             }
@@ -895,10 +917,21 @@ __device__ __forceinline__ void clock_from(double &t, uint32_t dlo, uint32_t dhi
     }
 }
 
-template <bool MOVING>
+template <bool MOVING, bool SURR>
 __device__ void coop_walk(Packet1D &q, const uint8_t *__restrict__ tb, const DevCloud *__restrict__ clouds,
                           const WalkArgs &a, unsigned long long *__restrict__ tally, int lane)
 {
+    // the cloud's surrogate window: a step that starts in it is replaced by one exit, at the
+    // same points as in the lane walk (every step in moving media, even step counts in
+    // static media, and only with room for three more steps)
+    SurrWin sw{0, -1, 0, -1, 0ull};
+    const float *recs = nullptr;
+    if (SURR) {
+        const SurrHeader *SH = reinterpret_cast<const SurrHeader *>(a.surr);
+        recs = reinterpret_cast<const float *>(a.surr + SH->off_records);
+        const SurrCloud *scl = reinterpret_cast<const SurrCloud *>(a.surr + SH->off_clouds) + q.cl;
+        sw = SurrWin{scl->i_lo, scl->i_hi, scl->j_lo, scl->j_hi, scl->rec_off};
+    }
     int wi = -1, jb = 0;
     int short_run = 0;   // consecutive blocks stopped by a slow-path step within 16 steps
     uint32_t v_lk = 0u, v_dhi = 0u, v_shi = 0u, v_fhi = 0u;
@@ -936,6 +969,17 @@ __device__ void coop_walk(Packet1D &q, const uint8_t *__restrict__ tb, const Dev
         const int wb = jw - jb;   // band lane of window position 0
         const StepWords wl = words_of_step<MOVING>(q, q.steps + (uint64_t)lane, a);
         const uint32_t ew = wl.e;
+        // surrogate stops: window positions inside the surrogate window, for the steps that
+        // check it
+        uint32_t smask = 0u;
+        bool chk = false;
+        if (SURR && (unsigned)(q.i - sw.i_lo) <= (unsigned)(sw.i_hi - sw.i_lo)) {
+#pragma unroll
+            for (int b = 0; b < kCoopWin; ++b)
+                smask |= ((unsigned)(jw + b - sw.j_lo) <= (unsigned)(sw.j_hi - sw.j_lo) ? 1u : 0u) << b;
+            const uint64_t st_l = q.steps + (uint64_t)lane;
+            chk = ((MOVING && q.moving) || !(st_l & 1ull)) && st_l + 3ull <= a.max_steps;
+        }
         // the window's thresholds rotated into lanes 0..14
         const uint32_t wdh = (uint32_t)__shfl((int)v_dhi, (wb + lane) & 63);
         const uint32_t wsh = (uint32_t)__shfl((int)v_shi, (wb + lane) & 63);
@@ -945,7 +989,7 @@ __device__ void coop_walk(Packet1D &q, const uint8_t *__restrict__ tb, const Dev
         for (int b = 0; b < kCoopWin; ++b) {
             const uint32_t dh = rl(wdh, b), sh = rl(wsh, b);
             const bool dn = ew < dh;
-            const bool slow = (ew >= sh) || (ew == dh);
+            const bool slow = (ew >= sh) || (ew == dh) || (SURR && chk && ((smask >> b) & 1u));
             const uint32_t mv = dn ? (b == 0 ? 15u : (uint32_t)(b - 1)) : (b == kCoopWin - 1 ? 15u : (uint32_t)(b + 1));
             const uint32_t nx = slow ? 15u : mv;
             if (b < 8) tlo |= nx << (4 * b);
@@ -985,12 +1029,14 @@ __device__ void coop_walk(Packet1D &q, const uint8_t *__restrict__ tb, const Dev
         const uint32_t dhl = (uint32_t)__shfl((int)v_dhi, src);
         const uint32_t shl = (uint32_t)__shfl((int)v_shi, src);
         int done, pos;
-        bool special = false;
+        bool special = false, surr_stop = false;
         if (ls >= m) {                         // m steps, no stop
             done = m;
             pos = ls < 64 ? (int)rl((uint32_t)pl, ls) : (int)((st & 63u) >> 2);
         } else {
-            const uint32_t slow = ((ew >= shl) || (ew == dhl)) ? 1u : 0u;
+            const bool sstop = SURR && chk && pl < 15 && ((smask >> pl) & 1u);
+            surr_stop = SURR && rl(sstop ? 1u : 0u, ls) != 0u;
+            const uint32_t slow = (sstop || (ew >= shl) || (ew == dhl)) ? 1u : 0u;
             const int p = (int)rl((uint32_t)pl, ls);
             if (rl(slow, ls)) {                // step ls takes the slow path
                 special = true;
@@ -1020,10 +1066,15 @@ __device__ void coop_walk(Packet1D &q, const uint8_t *__restrict__ tb, const Dev
             const StepWords ws = {rl(wl.t, done), rl(ew, done), rl(wl.z, done), rl(wl.w, done)};
             const uint4 rec = make_uint4(rl(v_lk, b), rl(v_dhi, b), rl(v_shi, b), rl(v_fhi, b));
             Packet1D s1 = q;
-            if (lane == 0) {
+            if (lane == 0 && SURR && surr_stop) {
+                surrogate_exit<MOVING>(s1, sw, recs, tb, clouds[s1.cl], a);
+            } else if (lane == 0) {
                 const float4 cm = (MOVING && s1.moving) ? s1.cmap[s1.i] : make_float4(1.f, 0.f, 1.f, 0.f);
                 one_step<MOVING>(s1, ws, rec, cm, tb, clouds, a, tally);
-                if (short_run >= 3) {
+                if (SURR && short_run >= 3) {
+                    surr_single_steps<MOVING>(s1, 64 << (short_run - 3 < 4 ? short_run - 3 : 4), sw, recs, tb,
+                                              clouds, a, tally);
+                } else if (short_run >= 3) {
                     const int n = 64 << (short_run - 3 < 4 ? short_run - 3 : 4);
                     if (MOVING && s1.moving) {
                         const uint64_t left = s1.active ? a.max_steps - s1.steps : 0ull;
@@ -1041,11 +1092,14 @@ __device__ void coop_walk(Packet1D &q, const uint8_t *__restrict__ tb, const Dev
             q.t = __longlong_as_double((long long)(((uint64_t)rl((uint32_t)(tbits >> 32), 0) << 32) |
                                                    rl((uint32_t)tbits, 0)));
             q.active = rl(s1.active ? 1u : 0u, 0) != 0u;
+            if (SURR) q.surr_calls = rl(s1.surr_calls, 0);
         }
     }
+    if (SURR && lane == 0 && q.surr_calls)
+        atomicAdd(&tally[clouds[q.cl].tally_off + TW_SURR_CALLS], (unsigned long long)q.surr_calls);
 }
 
-template <bool MOVING>
+template <bool MOVING, bool SURR>
 __global__ __launch_bounds__(64) void walk1d_coop(const uint8_t *__restrict__ tb, WalkArgs a,
                                                   unsigned long long *__restrict__ tally,
                                                   unsigned long long *__restrict__ work)
@@ -1070,7 +1124,7 @@ __global__ __launch_bounds__(64) void walk1d_coop(const uint8_t *__restrict__ tb
         }
         if (rl(got, 0) == 0u) continue;
         Packet1D q = load_slot(slots + idx, tb, clouds);
-        coop_walk<MOVING>(q, tb, clouds, a, tally, lane);
+        coop_walk<MOVING, SURR>(q, tb, clouds, a, tally, lane);
     }
 }
 
@@ -1204,7 +1258,6 @@ hipError_t launch_walk(const uint8_t *d_tables, const DevHeader &h, const DevClo
     bool moving = false;
     for (int c = 0; c < h.n_clouds; ++c) moving |= host_clouds[c].moving != 0;
     a.surr = static_cast<const uint8_t *>(run.surrogate);
-    if (a.surr) a.tail_lanes = 0;   // the cooperative tail walk has no surrogate exits
     a.producer_blocks = (uint32_t)grid;
     a.producer_waves = (uint32_t)(grid * (uint64_t)(block / 64));
     // consumer blocks after the producers: 16 waves per CU walk handed-over packets as soon
@@ -1226,10 +1279,14 @@ hipError_t launch_walk(const uint8_t *d_tables, const DevHeader &h, const DevClo
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || a.tail_lanes == 0) return e;
     const unsigned cgrid = (unsigned)device_cu_count() * 16;   // one wave per block
-    if (moving)
-        walk1d_coop<true><<<cgrid, 64, 0, s>>>(d_tables, a, d_tally, d_work);
+    if (moving && a.surr)
+        walk1d_coop<true, true><<<cgrid, 64, 0, s>>>(d_tables, a, d_tally, d_work);
+    else if (moving)
+        walk1d_coop<true, false><<<cgrid, 64, 0, s>>>(d_tables, a, d_tally, d_work);
+    else if (a.surr)
+        walk1d_coop<false, true><<<cgrid, 64, 0, s>>>(d_tables, a, d_tally, d_work);
     else
-        walk1d_coop<false><<<cgrid, 64, 0, s>>>(d_tables, a, d_tally, d_work);
+        walk1d_coop<false, false><<<cgrid, 64, 0, s>>>(d_tables, a, d_tally, d_work);
     return hipGetLastError();
 }
 

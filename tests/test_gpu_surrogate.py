@@ -6,6 +6,7 @@
 * Surrogate-accelerated transport of sweep clouds against the exact chain O2 (spectrum,
   mean escape time) and against plain GPU rDDMC in packets/s.
 """
+import dataclasses
 import math
 import time
 
@@ -180,3 +181,28 @@ def test_surrogate_transport_matches_exact_chain_and_beats_plain(trained, idx):
     print(f"    plain {npl / tp:.0f} pk/s (steps/pk {prob.results()[0].steps_mean:.3g}); speedup {(n / ts) / (npl / tp):.1f}x",
           flush=True)
     assert n / ts > 3.0 * npl / tp
+
+
+@pytest.mark.parametrize("moving", [True, False])
+def test_surrogate_runs_bit_identical_across_tail_modes(trained, moving):
+    """Surrogate exits taken inside the cooperative tail walk land exactly where the lane
+    walk takes them: every tally is the same with the tail walk off, at its default
+    threshold, and handing everything over at once."""
+    net, _ = trained
+    c = media.sweep_parameters()[TARGETS[0]]
+    if not moving:
+        c = dataclasses.replace(c, v_max=0.0)
+    m = media.sweep_cloud_medium(c)
+    prob = rddmc.Problem(m)
+    att = sg.Attached(prob, net, DOM)
+    out = []
+    for tl in (-1, 0, 64):
+        print(f"[surrogate] moving={moving} tail_lanes={tl}: 4096 packets", flush=True)
+        prob.reset()
+        prob.run(seed=5, count=4096, surrogate=att.buffer, tail_lanes=tl)
+        r = prob.results()[0]
+        out.append((r.spectrum.copy(), r.t_mean, r.steps_total, r.surrogate_calls, r.escaped))
+        assert r.surrogate_calls > 0 and r.escaped == 4096
+    for o in out[1:]:
+        assert np.array_equal(o[0], out[0][0])
+        assert o[1:] == out[0][1:]
