@@ -41,7 +41,7 @@ PEAK_OPS = 256 * 4 * 16 * 2.4e9
 # FETCH_SIZE and WRITE_SIZE counters scaled by a plain copy of known size
 # (profiles/walk1d_sphere_tau1e7_block65536_pmc.md), taken on the kernel as it is now;
 # None for any other block, and None while the kernel has changed since the counters ran.
-TRAFFIC_DEFAULT_BLOCK = 5.29e7
+TRAFFIC_DEFAULT_BLOCK = 5.27e7
 
 
 def parse():
