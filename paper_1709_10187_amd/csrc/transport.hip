@@ -406,15 +406,23 @@ __device__ __forceinline__ bool select_step(Packet1D &p, bool en, uint32_t tw, u
 // steps of a pair with selects, lanes that are done or past their budget are disabled, and
 // the slow path and record reloads run under masks only when some lane needs them.  Same
 // records, random words and arithmetic as one_step, so the same bits.
-template <bool MOVING>
+template <bool MOVING, bool SURR = false>
 __device__ __forceinline__ void static_pairs(Packet1D &p, int budget, int last_state,
                                              const uint8_t *__restrict__ tb, const DevCloud *__restrict__ clouds,
-                                             const WalkArgs &a, unsigned long long *__restrict__ tally)
+                                             const WalkArgs &a, unsigned long long *__restrict__ tally,
+                                             const SurrWin *sw = nullptr, const float *__restrict__ recs = nullptr)
 {
     const float4 nomap = make_float4(1.f, 0.f, 1.f, 0.f);
     for (int k = 0; k < a.chunk; ++k) {
-        const bool en = p.active && k < budget;
+        bool en = p.active && k < budget && (!SURR || p.steps < a.max_steps);
         if (!__any(en)) break;
+        if (SURR) {   // a pair that starts in the surrogate window is replaced by one exit
+            const bool sx = en && p.steps + 3ull <= a.max_steps && in_window(p, *sw);
+            if (__any(sx)) {
+                if (sx) surrogate_exit<MOVING>(p, *sw, recs, tb, clouds[p.cl], a);
+            }
+            en = en && !sx;
+        }
         // disabled lanes read the first records of the table buffer (always mapped; unused)
         const uint4 *h = en ? p.hot : reinterpret_cast<const uint4 *>(tb);
         const int s = en ? p.i * p.nb + p.j : 0;
@@ -476,14 +484,24 @@ __device__ __forceinline__ bool select_step_moving(Packet1D &p, bool en, StepWor
 }
 
 // Moving-medium steps (one Philox block each) with wave-uniform control flow: at most
-// `lim` iterations, lanes past their own `budget` disabled.
+// `lim` iterations, lanes past their own `budget` disabled; with the surrogate, a step that
+// starts in the window is replaced by one exit.
+template <bool SURR = false>
 __device__ __forceinline__ void moving_steps(Packet1D &p, int budget, int lim, const uint8_t *__restrict__ tb,
                                              const DevCloud *__restrict__ clouds, const WalkArgs &a,
-                                             unsigned long long *__restrict__ tally)
+                                             unsigned long long *__restrict__ tally, const SurrWin *sw = nullptr,
+                                             const float *__restrict__ recs = nullptr)
 {
     for (int k = 0; k < lim; ++k) {
-        const bool en = p.active && k < budget;
+        bool en = p.active && k < budget && (!SURR || p.steps < a.max_steps);
         if (!__any(en)) break;
+        if (SURR) {
+            const bool sx = en && p.steps + 3ull <= a.max_steps && in_window(p, *sw);
+            if (__any(sx)) {
+                if (sx) surrogate_exit<true>(p, *sw, recs, tb, clouds[p.cl], a);
+            }
+            en = en && !sx;
+        }
         // disabled lanes read the first words of the table buffer (always mapped; unused)
         const uint4 rec = (en ? p.hot : reinterpret_cast<const uint4 *>(tb))[en ? p.i * p.nb + p.j : 0];
         const float4 cm = (en ? p.cmap : reinterpret_cast<const float4 *>(tb))[en ? p.i : 0];
@@ -742,63 +760,15 @@ __global__ __launch_bounds__(256) void walk1d(const uint8_t *__restrict__ tb, Wa
         // ---- walk up to `chunk` pairs of steps ---------------------------------------
         const bool was_active = p.active;
         const uint64_t left = p.active ? (a.max_steps - p.steps) : 0ull;
-        if (!SURR && !(MOVING && p.moving)) {
+        if (!(MOVING && p.moving)) {
             const uint64_t pairs = (left + 1) >> 1;
             const int budget = pairs < (uint64_t)a.chunk ? (int)pairs : a.chunk;
-            static_pairs<MOVING>(p, budget, last_state, tb, clouds, a, tally);
+            static_pairs<MOVING, SURR>(p, budget, last_state, tb, clouds, a, tally, &sw, recs);
         }
-        if (SURR && !(MOVING && p.moving)) {
-            const uint64_t pairs = (left + 1) >> 1;
-            const int budget = pairs < (uint64_t)a.chunk ? (int)pairs : a.chunk;
-            for (int k = 0; k < budget; ++k) {
-                if (SURR) {
-                    if (p.steps >= a.max_steps) break;
-                    if (p.steps + 3ull <= a.max_steps && in_window(p, sw)) {
-                        surrogate_exit<MOVING>(p, sw, recs, tb, clouds[p.cl], a);
-                        continue;
-                    }
-                }
-                const int s = p.i * p.nb + p.j;
-                const uint4 rm = p.hot[s > 0 ? s - 1 : 0];
-                const uint4 r0 = p.hot[s];
-                const uint4 rp = p.hot[s < last_state ? s + 1 : last_state];
-                const uint64_t pair = p.steps >> 1;
-                const u32x4 r = philox4x32_10((uint32_t)pair, (uint32_t)(pair >> 32), p.pid, p.key,
-                                              a.key0, a.key1);
-                const float4 nomap = make_float4(1.f, 0.f, 1.f, 0.f);
-                const int d = one_step<MOVING>(p, StepWords{r.x, r.y, 0u, 0u}, r0, nomap, tb, clouds, a, tally);
-                if (!p.active || p.steps >= a.max_steps) break;
-                uint4 rb;
-                if (d == -1) rb = rm;
-                else if (d == 1) rb = rp;
-                else rb = p.hot[p.i * p.nb + p.j];   // spatial move or slow step: new record
-                one_step<MOVING>(p, StepWords{r.z, r.w, 0u, 0u}, rb, nomap, tb, clouds, a, tally);
-                if (!p.active) break;
-            }
-        }
-        if (!SURR && MOVING && p.moving) {
+        if (MOVING && p.moving) {
             const uint64_t lim = 2ull * (uint64_t)a.chunk;
             const int budget = left < lim ? (int)left : (int)lim;
-            moving_steps(p, budget, (int)lim, tb, clouds, a, tally);
-        }
-        if (SURR && MOVING && p.moving) {
-            const uint64_t lim = 2ull * (uint64_t)a.chunk;
-            const int budget = left < lim ? (int)left : (int)lim;
-            for (int k = 0; k < budget; ++k) {
-                if (SURR) {
-                    if (p.steps >= a.max_steps) break;
-                    if (p.steps + 3ull <= a.max_steps && in_window(p, sw)) {
-                        surrogate_exit<MOVING>(p, sw, recs, tb, clouds[p.cl], a);
-                        continue;
-                    }
-                }
-                const uint4 rec = p.hot[p.i * p.nb + p.j];
-                const float4 cm = p.cmap[p.i];
-                const u32x4 r = philox4x32_10((uint32_t)p.steps, (uint32_t)(p.steps >> 32), p.pid, p.key,
-                                              a.key0, a.key1);
-                one_step<true>(p, StepWords{r.x, r.y, r.z, r.w}, rec, cm, tb, clouds, a, tally);
-                if (!p.active) break;
-            }
+            moving_steps<SURR>(p, budget, (int)lim, tb, clouds, a, tally, &sw, recs);
         }
         if (p.active && p.steps >= a.max_steps) {
             tally_finish(tally, clouds[p.cl], false, 0, 0, p.t, p.steps);
