@@ -786,16 +786,17 @@ __global__ __launch_bounds__(256) void walk1d(const uint8_t *__restrict__ tb, Wa
 //     packet's bin.
 //   * Lane l draws the Philox words of step steps+l and builds the step's transition table
 //     over the window: 4 bits per window position giving the next position, or 15 ("stop")
-//     for a slow-path step (a tie with a threshold, a spatial leak) or a move out of the
-//     window; position 15 maps to itself.
+//     for a slow-path step (a tie with a threshold, a spatial leak), a move out of the
+//     window, or (with the surrogate) a step that starts in the surrogate window at one of
+//     the lane walk's check points; position 15 maps to itself.
 //   * Each even lane composes its table with the next lane's (two steps per table); the
 //     sequential part is a scalar chain of two instructions per pair of steps (a 4-bit
 //     field extract addressed by the position, a shift-add back to an address); even
 //     lanes receive the position their step starts from, odd lanes take one step from it.
-//   * The lane whose step stops classifies it: a move out of the window completes, a
-//     slow-path step runs in lane 0 with the lane walk's arithmetic.
-// The clock adds the same f32 path lengths in the same order as the lane walk, so every
-// tally is bit-identical to walking the packet in a single lane.
+//   * The lane whose step stops classifies it: a move out of the window completes; a
+//     surrogate exit or a slow-path step runs in lane 0 with the lane walk's arithmetic.
+// The clock gives the bits of the lane walk's ordered FP64 additions (clock_parallel, else
+// in order), so every tally is bit-identical to walking the packet in a single lane.
 constexpr int kCoopWin = 15;
 // scan state: 4 x window position in bits 0..5, field width 4 in bits 16..22 (the operand
 // layout of s_bfe_u64); kScanStop is the state of the stop position
