@@ -341,7 +341,7 @@ def cpu_baseline_cube(args):
     from oracle import tables as otb
     from oracle import walk3d as ow3
     threads = _threads(args)
-    n = args.cpu_packets or (1 << 17)
+    n = args.cpu_packets or (1 << 20)
     m = media.cube(n=32)
     log(f"cpu baseline: oracle 3D walker, {n} packets of the 32^3 cube, {threads} threads")
     t = otb.build(m)
