@@ -10,7 +10,9 @@
   route with cos((n + 1/2) pi z) modes reproduces eq. (33), which checks it.
   Normalised numerically.
 * Grey symmetric birth-death chain with N interior cells: expected steps from
-  cell m is m (N + 1 - m); exit probability to the right is m / (N + 1).
+  cell m is m (N + 1 - m); exit probability to the right is m / (N + 1); the variance
+  of the number of steps (the duration of the symmetric gambler's ruin on {0..L},
+  L = N + 1, started at m) is m (L - m) (m^2 + (L - m)^2 - 2) / 3.
 """
 from __future__ import annotations
 
@@ -80,3 +82,10 @@ def grey_steps(N, m):
 
 def grey_right_exit(N, m):
     return m / (N + 1.0)
+
+
+def grey_steps_var(N, m):
+    """Variance of the duration of the symmetric gambler's ruin absorbed at 0 and N + 1
+    (textbook result; it vanishes for N = 1 and gives 2 for N = 2, m = 1)."""
+    L = N + 1
+    return m * (L - m) * (m * m + (L - m) ** 2 - 2) / 3.0

@@ -193,6 +193,21 @@ static void hemi_dir(rng_t *r, int ax, double sg, double n[3])
     n[(ax + 2) % 3] = t2;
 }
 
+/* One scattering (the hybrid section's MC step, eq. 41 with g = 0): the atom's velocity
+ * along the incoming direction n from o3_sample_upar, one perpendicular component from
+ * N(0, 1/2), an isotropic new direction written back into n; returns the new comoving x. */
+static double scatter(double a, double x, double n[3], rng_t *r)
+{
+    double upar = o3_sample_upar(a, x, r);
+    double uperp = gauss(r) * sqrt(0.5);
+    double n2[3];
+    iso_dir(r, n2);
+    double mu = n[0] * n2[0] + n[1] * n2[1] + n[2] * n2[2];
+    double xo = x + upar * (mu - 1.0) + uperp * sqrt(fmax(0.0, 1.0 - mu * mu));
+    n[0] = n2[0]; n[1] = n2[1]; n[2] = n2[2];
+    return xo;
+}
+
 static int locate(const double *e, int nb, double x)
 {
     if (x < e[0]) return -1;
@@ -235,13 +250,6 @@ static int64_t nbr_of(const o3_problem *p, int64_t c, int f)
     return idx[d] > 0 ? c - st[d] : -1;
 }
 static const double *axis_faces(const o3_problem *p, int d) { return d == 0 ? p->fx : (d == 1 ? p->fy : p->fz); }
-static double width_min(const o3_problem *p, int64_t c)
-{
-    int i[3]; cell_ijk(p, c, &i[0], &i[1], &i[2]);
-    double w = 1e300;
-    for (int d = 0; d < 3; ++d) { const double *f = axis_faces(p, d); double ww = f[i[d] + 1] - f[i[d]]; if (ww < w) w = ww; }
-    return w;
-}
 static int64_t pixel_of(const o3_problem *p, int64_t c, int f)
 {   /* escape pixel index: per face, the boundary cell's two other coordinates */
     int i[3]; cell_ijk(p, c, &i[0], &i[1], &i[2]);
@@ -380,14 +388,7 @@ static void walk_packet(const o3_problem *p, uint64_t id, uint64_t seed, uint64_
         if (ds < dface) {
             for (int d = 0; d < 3; ++d) pos[d] += ds * n[d];
             t += ds;
-            double a = p->a[c];
-            double upar = o3_sample_upar(a, x, &r);
-            double uperp = gauss(&r) * sqrt(0.5);
-            double n2[3];
-            iso_dir(&r, n2);
-            double mu = n[0] * n2[0] + n[1] * n2[1] + n[2] * n2[2];
-            x = x + upar * (mu - 1.0) + uperp * sqrt(fmax(0.0, 1.0 - mu * mu));
-            n[0] = n2[0]; n[1] = n2[1]; n[2] = n2[2];
+            x = scatter(p->a[c], x, n, &r);
             int jj = locate(p->edges, nb, x);
             if (jj >= 0 && jj < nb && p->thick[c * nb + jj]) { j = jj; mc = 0; R->to_ddmc++; }
             continue;
@@ -403,7 +404,11 @@ static void walk_packet(const o3_problem *p, uint64_t id, uint64_t seed, uint64_
         double xn = (x + nu) * sqrt(p->T[c] / p->T[nc]) - nu2;
         int jn = locate(p->edges, nb, xn);
         if (jn >= 0 && jn < nb && p->thick[nc * nb + jn]) {
-            double wn = width_min(p, nc);
+            /* eq. 39 with the neighbour's optical width across the interface (its width
+             * along the crossing axis, as in the DDMC -> MC rate of the same face) */
+            int in3[3]; cell_ijk(p, nc, &in3[0], &in3[1], &in3[2]);
+            const double *fn = axis_faces(p, f >> 1);
+            double wn = fn[in3[f >> 1] + 1] - fn[in3[f >> 1]];
             double mu = fabs(n[f >> 1]);
             double P = 2.0 / (p->k[nc * nb + jn] * wn + 2.0 * p->lambda) * (2.0 / 3.0 + mu);
             if (ru(&r) < P) { c = nc; j = jn; mc = 0; R->to_ddmc++; continue; }
@@ -479,4 +484,17 @@ void o3_upar_samples(double a, double x, uint64_t seed, int64_t n, double *out)
     uint64_t xs = seed;
     for (int i = 0; i < 4; ++i) r.s[i] = sm64(&xs);
     for (int64_t i = 0; i < n; ++i) out[i] = o3_sample_upar(a, x, &r);
+}
+
+/* test hook: outgoing frequencies of n scatterings of a photon absorbed at x, each from a
+ * fresh incoming direction along +z, through the walk's own scattering routine */
+void o3_redistribution_samples(double a, double x, uint64_t seed, int64_t n, double *out)
+{
+    rng_t r;
+    uint64_t xs = seed;
+    for (int i = 0; i < 4; ++i) r.s[i] = sm64(&xs);
+    for (int64_t i = 0; i < n; ++i) {
+        double dir[3] = {0.0, 0.0, 1.0};
+        out[i] = scatter(a, x, dir, &r);
+    }
 }

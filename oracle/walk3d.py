@@ -61,6 +61,8 @@ def _load():
         _lib.o3_voigt.argtypes = [C.c_double, C.c_double]
         _lib.o3_upar_samples.restype = None
         _lib.o3_upar_samples.argtypes = [C.c_double, C.c_double, C.c_uint64, C.c_int64, C.c_void_p]
+        _lib.o3_redistribution_samples.restype = None
+        _lib.o3_redistribution_samples.argtypes = [C.c_double, C.c_double, C.c_uint64, C.c_int64, C.c_void_p]
     return _lib
 
 
@@ -75,6 +77,13 @@ def voigt(a, x):
 def upar_samples(a, x, n, seed=1):
     out = np.zeros(int(n))
     _load().o3_upar_samples(float(a), float(x), int(seed), int(n), out.ctypes.data)
+    return out
+
+
+def redistribution_samples(a, x, n, seed=1):
+    """Outgoing comoving frequencies of n scatterings of a photon absorbed at x."""
+    out = np.zeros(int(n))
+    _load().o3_redistribution_samples(float(a), float(x), int(seed), int(n), out.ctypes.data)
     return out
 
 

@@ -1,6 +1,8 @@
 """Pins of O2 (the exact pure-DDMC chain) against analytic solutions, closed forms and
 brute force on tiny inputs."""
+import json
 import math
+import os
 
 import numpy as np
 import pytest
@@ -40,7 +42,10 @@ def test_validation_sphere_matches_derived_spectrum():
 
 
 def test_config_slab_regression_values():
-    """Conservation, static symmetry and the expected work of the 64x128 slab."""
+    """Conservation and static symmetry of the 64x128 slab (exact properties), and its
+    expected work against the stored regression values (tests/golden/chain_regression.json,
+    written by make_chain_regression.py from this oracle: a guard against unintended changes,
+    not a pin)."""
     m = media.config_slab()
     r = chain.solve(m)
     p = r.spectrum_total()
@@ -48,8 +53,10 @@ def test_config_slab_regression_values():
     assert p[0] == 0 and p[-1] == 0
     np.testing.assert_allclose(p[1:-1], p[1:-1][::-1], atol=1e-12)
     np.testing.assert_allclose(r.spectrum[0], r.spectrum[1], atol=1e-12)   # equal face fractions
-    assert r.steps == pytest.approx(1.748e6, rel=1e-3)
-    assert r.t_mean == pytest.approx(12.01, rel=1e-3)
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "chain_regression.json")))
+    ref = g["slab_tau1e5_64x128"]
+    for k in ("steps", "steps2", "t_mean", "t2"):
+        assert getattr(r, k) == pytest.approx(ref[k], rel=1e-9), k
 
 
 def _grey(N, k=50.0):
@@ -69,6 +76,7 @@ def test_grey_gamblers_ruin(N, start):
     m = m.replace(src_pos=np.array([[zc, 0, 0]]))
     r = chain.solve(m)
     assert r.steps == pytest.approx(an.grey_steps(N, start), rel=1e-10)
+    assert r.steps_var == pytest.approx(an.grey_steps_var(N, start), rel=1e-8)
     assert r.spectrum[1].sum() == pytest.approx(an.grey_right_exit(N, start), rel=1e-10)
     K = 2 / (3 * kbin * dz * dz)
     assert r.t_mean == pytest.approx(an.grey_steps(N, start) / K, rel=1e-10)
@@ -122,19 +130,36 @@ def test_brute_force_tiny_chain():
     assert r.steps == pytest.approx(acc.sum(), rel=1e-9)
     np.testing.assert_allclose(r.spectrum[:, 1:-1].ravel(), spec, rtol=1e-9, atol=1e-15)
     assert r.t_mean == pytest.approx(acc @ (1 / K), rel=1e-9)
-    # Monte Carlo of the jump chain for E[T^2]
+    # the law of the step count N, enumerated: P(N = n) = pi0 P^(n-1) (1 - P 1)
+    leave = 1.0 - P.sum(axis=1)
+    v = pi0.copy()
+    en1 = en2 = mass = 0.0
+    for n_ in range(1, 40000):
+        pn = float(v @ leave)
+        mass += pn
+        en1 += n_ * pn
+        en2 += n_ * n_ * pn
+        v = v @ P
+    assert mass == pytest.approx(1.0, abs=1e-12)
+    assert r.steps == pytest.approx(en1, rel=1e-9)
+    assert r.steps2 == pytest.approx(en2, rel=1e-9)
+    # Monte Carlo of the jump chain for E[T^2] and E[N^2]
     rng = np.random.default_rng(7)
     cum = np.cumsum(np.hstack([P, E]), axis=1)
     n = 40000
     T = np.zeros(n)
+    N = np.zeros(n)
     for i in range(n):
         s = rng.choice(ns, p=pi0)
         while True:
             T[i] += rng.exponential(1 / K[s])
+            N[i] += 1
             nxt = int(np.searchsorted(cum[s], rng.random(), side="right"))
             if nxt >= ns:
                 break
             s = nxt
+    seN = (N ** 2).std() / math.sqrt(n)
+    assert abs((N ** 2).mean() - r.steps2) < 4 * seN
     se = T.std() / math.sqrt(n)
     assert abs(T.mean() - r.t_mean) < 4 * se
     se2 = (T ** 2).std() / math.sqrt(n)

@@ -1,15 +1,17 @@
 """Pins of the 3D hybrid oracle walker (O1-3D): its own Dawson/Voigt, the atom-velocity
 sampler, the interface conversion probability, continuous-MC geometry and opacity against
-independent quadratures, and pure-DDMC runs against the exact chain."""
+independent quadratures, the whole scattering against the textbook redistribution function,
+brute-force MCRT of the slab against eq. 33, and pure-DDMC runs against the exact chain."""
 import math
 
 import numpy as np
 import pytest
 from scipy import integrate, special
 
+from oracle import analytic as an
 from oracle import chain, linemath, walk3d
 from paper_1709_10187_amd import media
-from tests._stats import assert_spectrum_matches, compare_exact
+from tests._stats import assert_spectrum_matches, compare_exact, compare_two_samples
 
 
 def test_own_dawson_and_voigt():
@@ -117,3 +119,82 @@ def test_lab_escape_law_quadrature_against_sampling():
     assert p.sum() == pytest.approx(1.0, abs=1e-12)
     assert np.all(p >= 0.0)
     assert np.all(np.abs(cnt - p) < 5 * np.sqrt(p * (1 - p) / n) + 1e-6)
+
+
+def _hummer_r2a(a, x, xp):
+    """Hummer's (1962) angle-averaged redistribution function for natural plus Doppler
+    broadening and an isotropic phase function (R_II-A): the joint density of absorption at
+    x and re-emission at x' in the observer's frame; its integral over x' is H(a,x)/sqrt(pi)."""
+    lo, hi = min(x, xp), max(x, xp)
+    f = lambda u: math.exp(-u * u) * (math.atan((lo + u) / a) - math.atan((hi - u) / a))
+    v, _ = integrate.quad(f, 0.5 * (hi - lo), np.inf, limit=400, epsabs=0, epsrel=1e-10)
+    return v / math.pi ** 1.5
+
+
+@pytest.mark.parametrize("a,x", [(1.4869e-2, 0.5), (1.4869e-2, 3.0), (4.702e-4, 8.0), (0.1487, 5.0)])
+def test_scattering_redistribution_matches_hummer_r2a(a, x):
+    """The walker's whole scattering (atom velocity along the photon from its rejection
+    sampler, one perpendicular component from N(0, 1/2), an isotropic new direction and the
+    eq. 41 frequency with no recoil) against the textbook redistribution law:
+    p(x' | x) = sqrt(pi) R_II-A(x, x') / H(a, x), with H the exact Voigt function.  A dropped
+    perpendicular term, a wrong sign of u_par or of (mu - 1), or an anisotropic direction
+    each change this law."""
+    n = 200000
+    smp = walk3d.redistribution_samples(a, x, n, seed=5)
+    lo, hi = np.percentile(smp, [0.5, 99.5])
+    edges = np.linspace(lo, hi, 31)
+    cnt, _ = np.histogram(smp, edges)
+    H = special.wofz(x + 1j * a).real
+    g = lambda xp: _hummer_r2a(a, x, xp)
+    p = np.array([integrate.quad(g, edges[i], edges[i + 1], limit=100,
+                                 points=[x] if edges[i] < x < edges[i + 1] else None)[0]
+                  for i in range(30)]) * math.sqrt(math.pi) / H
+    assert 0.0 < 1.0 - p.sum() < 0.02          # the law is normalised; ~1 % lies outside
+    res = compare_exact(np.r_[cnt, n - cnt.sum()], np.r_[p, 1.0 - p.sum()])
+    assert_spectrum_matches(res)
+
+
+def _all_mc_slab(atau0, T, n_bins, x_max, packets, width=1.0e3):
+    """The slab |z| <= 1 as one 3D cell of lateral extent 2 width (packets leave through the
+    z faces), with every state a continuous-MC state (tau_th above every state's depth): the
+    walker is then brute-force Monte Carlo transfer, scattering by scattering."""
+    a = float(linemath.damping(np.array([T]))[0])
+    tau0 = atau0 / a
+    fz = np.array([-1.0, 1.0])
+    fx = np.array([-width, width])
+    m = media.Medium(geometry=2, n_cells=(1, 1, 1), faces=[fx, fx.copy(), fz],
+                     bin_edges=media.uniform_edges(x_max, n_bins), k0=np.array([tau0]), temp=np.array([T]),
+                     vel=None, src_pos=np.array([[0.0, 0.0, 0.0]]), src_x=np.array([0.0]), n_packets=packets,
+                     tau_threshold=1.0e30, name="all_mc_slab")
+    return m, tau0
+
+
+def test_all_mc_slab_escape_spectrum_matches_neufeld():
+    """Brute-force MCRT of the Neufeld problem (Sec. 3.2.1, eq. 33) at a tau0 = 1e3 (T = 0.1 K,
+    a = 0.149, tau0 = 6725: ~1.2e4 scatterings per packet).  Eq. 33 is the large-a tau0 limit,
+    so at this depth the exact solution differs from it; the bar is the exact chain's own
+    distance to eq. 33 at the same a tau0 (201 cells x 240 bins, folded onto the tally grid)
+    plus twice the expected Monte Carlo noise L1.  Exact properties of the static problem are
+    checked as well: both faces equally likely, the spectrum symmetric in x."""
+    atau0, T, nb = 1.0e3, 0.1, 48
+    s = atau0 ** (1.0 / 3.0)
+    n = 1 << 14
+    m, tau0 = _all_mc_slab(atau0, T, nb, 4.0 * s, n)
+    r = walk3d.run(m, n_packets=n, seed=1)
+    assert r.escaped == n and r.to_ddmc == 0 and r.to_mc == 0
+    faces = r.spectrum.sum(axis=1)
+    assert faces[:4].sum() == 0
+    assert abs(faces[4] - faces[5]) < 4.0 * math.sqrt(n)            # Binomial(n, 1/2)
+    cnt = r.spectrum.sum(axis=0)
+    assert cnt[0] == 0 and cnt[-1] == 0
+    cnt = cnt[1:-1]
+    p = cnt / n
+    ref = an.binned(an.slab_pdf, m.bin_edges, atau0)
+    mo = media.slab(tau0, T, 201, nb * 5, x_max=4.0 * s)
+    po = chain.solve(mo).spectrum_total()[1:-1].reshape(nb, 5).sum(axis=1)
+    noise = float(np.sum(np.sqrt(2.0 / np.pi * po * (1.0 - po) / n)))
+    l1_mc, l1_chain = float(np.abs(p - ref).sum()), float(np.abs(po - ref).sum())
+    assert l1_mc <= l1_chain + 2.0 * noise, (l1_mc, l1_chain, noise)
+    # mirror symmetry x -> -x: the two halves are two samples of the same law
+    half = compare_two_samples(cnt[:nb // 2], cnt[nb // 2:][::-1])
+    assert_spectrum_matches(half)
