@@ -16,6 +16,8 @@
  *   - Host pointers are read only during the call; nothing is retained.
  *   - Device pointers are caller-owned (e.g. torch tensors); the library never
  *     allocates or frees device memory.  Buffers are sized with the *_bytes queries.
+ *     (rddmc_transport_static's work area is a device array of the library itself,
+ *     created with the library's code on each device, not allocated by a call.)
  *   - Every device operation is enqueued on the caller's stream; results are valid
  *     after that stream is synchronised.  rddmc_build_leakage and rddmc_tally also
  *     synchronise the stream themselves (they stage small host data).
@@ -264,6 +266,28 @@ rddmc_status rddmc_build_leakage(const rddmc_batch *batch, void *d_tables, size_
 rddmc_status rddmc_transport(const rddmc_batch *batch, const void *d_tables, const rddmc_run *run,
                              void *d_tally, size_t tally_bytes, void *d_work, size_t work_bytes,
                              void *stream);
+
+/*
+ * rddmc_transport_static -- rddmc_transport for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.  The
+ * same walk with the same results, bit for bit; the only difference is the work area (queue
+ * counters and the cooperative tail walk's export slots), which lives in a device array of
+ * RDDMC_STATIC_WORK_BYTES that the library holds on every device it runs on until the process
+ * ends.  The call allocates nothing: no hipMalloc, no hipFree, no allocating library routine.
+ *   batch, d_tables, run, d_tally, tally_bytes, stream  as for rddmc_transport; the device is
+ *                the calling thread's current device (its first call there looks up the
+ *                array's device address once).
+ * Every call on one device shares that device's array; each call clears the counters and
+ * slot flags it uses with a kernel on its stream before walking.  Calls that overlap on one
+ * device (two streams, or two threads) race on the array: serialise them.
+ * Errors: as rddmc_transport, plus ESIZE when an explicit run->grid x run->block exceeds
+ * RDDMC_STATIC_WORK_LANES resident lanes (automatic grids fit by construction on devices of
+ * up to 256 compute units; larger devices get a smaller automatic grid).
+ */
+#define RDDMC_STATIC_WORK_LANES (1ull << 19)
+#define RDDMC_STATIC_WORK_BYTES (256ull + 48ull * RDDMC_STATIC_WORK_LANES)   /* 24 MiB + 256 B */
+rddmc_status rddmc_transport_static(const rddmc_batch *batch, const void *d_tables, const rddmc_run *run,
+                                    void *d_tally, size_t tally_bytes, void *stream);
 
 /* Zero a tally buffer with a kernel on the stream (safe under stream capture). */
 rddmc_status rddmc_tally_reset(const rddmc_batch *batch, void *d_tally, size_t tally_bytes,

@@ -8,6 +8,7 @@
 #include <climits>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -278,6 +279,39 @@ rddmc_status make_layout(const rddmc_batch *b, Layout &L)
 void put(std::vector<uint8_t> &buf, uint64_t off, const void *src, size_t bytes)
 {
     if (bytes) std::memcpy(buf.data() + off, src, bytes);
+}
+
+}  // namespace
+
+// Work area of rddmc_transport_static: queue counters and the cooperative tail walk's export
+// slots, in device memory the library owns (one copy per device, held until the process
+// ends).  Host code never passes this name to a kernel: it is a host-side stand-in, and the
+// device address comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) unsigned long long scratch[RDDMC_STATIC_WORK_BYTES / 8];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the calling thread's current device.
+rddmc_status static_work_of_current_device(void **ptr)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(RDDMC_EUNSUPPORTED, "device index %d >= %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!p) return fail(RDDMC_EHIP, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return RDDMC_OK;
 }
 
 }  // namespace
@@ -799,6 +833,25 @@ rddmc_status rddmc_philox_fill(uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c
     if (!d_out && n) return fail(RDDMC_EINVAL, "d_out is NULL");
     hipError_t e = launch_philox_fill(k0, k1, c0, c1, c2, c3, n, d_out, reinterpret_cast<hipStream_t>(stream));
     return e == hipSuccess ? RDDMC_OK : hip_fail(e, "philox kernel");
+}
+
+rddmc_status rddmc_transport_static(const rddmc_batch *batch, const void *d_tables, const rddmc_run *run,
+                                    void *d_tally, size_t tally_bytes, void *stream)
+{
+    if (!run) return fail(RDDMC_EINVAL, "NULL argument");
+    if (run->grid > 0 && run->block >= 0) {
+        const uint64_t block = run->block > 0 ? (uint64_t)run->block : 256;
+        const uint64_t lanes = (uint64_t)run->grid * block;
+        if (lanes > RDDMC_STATIC_WORK_LANES)
+            return fail(RDDMC_ESIZE,
+                        "grid x block = %llu resident lanes; the static work area holds export slots for at most "
+                        "%llu (RDDMC_STATIC_WORK_LANES)",
+                        (unsigned long long)lanes, (unsigned long long)RDDMC_STATIC_WORK_LANES);
+    }
+    void *work = nullptr;
+    rddmc_status st = static_work_of_current_device(&work);
+    if (st != RDDMC_OK) return st;
+    return rddmc_transport(batch, d_tables, run, d_tally, tally_bytes, work, RDDMC_STATIC_WORK_BYTES, stream);
 }
 
 }  // extern "C"

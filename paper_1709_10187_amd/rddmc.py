@@ -76,7 +76,7 @@ ABI_VERSION = 3
 
 
 EXPORTS = ["rddmc_abi_version", "rddmc_last_error", "rddmc_table_bytes", "rddmc_tally_bytes",
-           "rddmc_work_bytes", "rddmc_build_leakage", "rddmc_transport", "rddmc_tally_reset",
+           "rddmc_work_bytes", "rddmc_build_leakage", "rddmc_transport", "rddmc_transport_static", "rddmc_tally_reset",
            "rddmc_tally", "rddmc_read_tables", "rddmc_philox_fill", "rddmc_mdn_bytes", "rddmc_mdn_init",
            "rddmc_mdn_set", "rddmc_mdn_get", "rddmc_mdn_forward", "rddmc_mdn_loss_grad", "rddmc_mdn_adam",
            "rddmc_surrogate_samples", "rddmc_surrogate_bytes", "rddmc_surrogate_window", "rddmc_surrogate_attach"]
@@ -102,6 +102,7 @@ def load(path: str = LIB_PATH):
         getattr(lib, name).restype = C.c_int
     lib.rddmc_build_leakage.argtypes = [C.POINTER(Batch_t), vp, sz, vp]
     lib.rddmc_transport.argtypes = [C.POINTER(Batch_t), vp, C.POINTER(Run_t), vp, sz, vp, sz, vp]
+    lib.rddmc_transport_static.argtypes = [C.POINTER(Batch_t), vp, C.POINTER(Run_t), vp, sz, vp]
     lib.rddmc_tally_reset.argtypes = [C.POINTER(Batch_t), vp, sz, vp]
     lib.rddmc_tally.argtypes = [C.POINTER(Batch_t), vp, sz, C.POINTER(TallyOut_t), vp]
     lib.rddmc_read_tables.argtypes = [C.POINTER(Batch_t), vp, C.c_int32, vp, vp, vp, vp, vp]
@@ -120,7 +121,7 @@ def load(path: str = LIB_PATH):
                                           C.POINTER(C.c_uint64)]
     lib.rddmc_surrogate_window.argtypes = [C.POINTER(Batch_t), cfgp, C.c_int32, vp]
     lib.rddmc_surrogate_attach.argtypes = [C.POINTER(Batch_t), vp, vp, vp, C.c_int64, cfgp, vp, sz, vp]
-    for name in ("rddmc_build_leakage", "rddmc_transport", "rddmc_tally_reset", "rddmc_tally",
+    for name in ("rddmc_build_leakage", "rddmc_transport", "rddmc_transport_static", "rddmc_tally_reset", "rddmc_tally",
                  "rddmc_read_tables", "rddmc_philox_fill", "rddmc_mdn_bytes", "rddmc_mdn_init",
                  "rddmc_mdn_set", "rddmc_mdn_get", "rddmc_mdn_forward", "rddmc_mdn_loss_grad",
                  "rddmc_mdn_adam", "rddmc_surrogate_samples", "rddmc_surrogate_bytes",
@@ -231,6 +232,18 @@ def transport(b: Batch, d_tables, d_tally, d_work, seed=0, first=0, count=0, max
                                C.c_void_p(d_tally.data_ptr()), d_tally.numel() * d_tally.element_size(),
                                C.c_void_p(d_work.data_ptr()), d_work.numel() * d_work.element_size(),
                                _stream(stream)))
+
+
+def transport_static(b: Batch, d_tables, d_tally, seed=0, first=0, count=0, max_steps=(1 << 62), block=0,
+                     grid=0, chunk=0, tail_lanes=0, stream=None, surrogate=None):
+    """rddmc_transport_static: the same walk with the library's own device work area (no
+    caller work buffer, no allocation in the call)."""
+    lib = load()
+    run = Run_t(int(seed), int(first), int(count), int(max_steps), int(block), int(grid), int(chunk),
+                int(tail_lanes), C.c_void_p(surrogate.data_ptr()) if surrogate is not None else None)
+    _check(lib.rddmc_transport_static(b.ref(), C.c_void_p(d_tables.data_ptr()), C.byref(run),
+                                      C.c_void_p(d_tally.data_ptr()), d_tally.numel() * d_tally.element_size(),
+                                      _stream(stream)))
 
 
 @dataclasses.dataclass
