@@ -495,7 +495,12 @@ __device__ void mc_step(Pk &p, const DevCloud &c, const uint8_t *__restrict__ tb
         (reinterpret_cast<const uint4 *>(tb + c.off_hot)[ncell * c.nb + jn].w & kFlagThick)) {
         const float kn = (float)reinterpret_cast<const double *>(tb + c.off_k)[ncell * c.nb + jn];
         const float mu = fabsf(comp(p.n, d));
-        const float P = 2.0f / fmaf(kn, m1.w, 2.0f * lambda) * (0.666666667f + mu);   // eq. 39
+        // the neighbour's width across the interface (along the crossing axis), as in the
+        // DDMC -> MC rate of the same face
+        const double *fd = faces_of(c, tb, d);
+        const int ind = compi(nix, niy, niz, d);
+        const float wn = (float)(fd[ind + 1] - fd[ind]);
+        const float P = 2.0f / fmaf(kn, wn, 2.0f * lambda) * (0.666666667f + mu);   // eq. 39
         if (uf(draw(p.r, a)) < P) {
             enter(p, nix, niy, niz, ncell);
             p.j = jn;
