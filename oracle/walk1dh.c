@@ -1,0 +1,394 @@
+/* O1-1DH: literal FP64 hybrid DDMC / continuous-MC walker on 1D grids (slab cells along z,
+ * or spherical shells) -- ORACLE, TEST INFRASTRUCTURE ONLY.  Plain C; shares nothing with
+ * the GPU library.
+ *
+ * Packets carry a full 3D position and direction; the geometry enters through the cells'
+ * boundaries (planes z = z_f, or spheres r = r_f), their outward normals (+-z, or +-r^), and
+ * the bulk velocity field (slab: u_c along +z; shell: u_c along r^, u_c = v_c / v_th(T_c)).
+ *
+ *  - DDMC states (tau_ij = k_ij w_i >= tau_th): every step draws dl_X = -ln(xi_X) / k_X for
+ *    EVERY leak X (two faces: eq. 10 or the thin/vacuum interface rate; two bins: eq. 11) and
+ *    takes the smallest (eqs. 15-16);
+ *      * through a face whose neighbour is thick at the shifted bin: move there, re-binned by
+ *        the f_mu-averaged shift of eq. 20;
+ *      * through a face into a thin state or vacuum: an MC packet at a uniform point of that
+ *        face with an isotropic outward direction (mu uniform in (0, 1] about the face's
+ *        outward normal), x uniform in the bin, moved to the neighbour's frame exactly,
+ *        x' = (x + n.u) sqrt(T/T') - n.u' (both velocities at that point); through vacuum it
+ *        escapes with the lab frequency x + n.u;
+ *      * into a thin bin: an MC packet at a uniform point of the cell (uniform in volume),
+ *        isotropic, x uniform in the new bin;
+ *      * re-binned into a thin state after a spatial move: MC in the new cell at a uniform
+ *        point, isotropic, with the shifted x.
+ *  - MC packets: distance to the cell boundary along n against an exponential optical depth
+ *    with opacity k0 H(a, x) (eq. 12) at the packet's comoving x;
+ *      * scattering: the shared MC physics (atom velocity by rejection, eq. 41 without recoil,
+ *        isotropic phase function, optional core-skipping above x_crit); if the state
+ *        (cell, bin(x')) is thick the packet becomes DDMC there;
+ *      * a boundary: vacuum -> escape at x + n.u; a neighbour at
+ *        x' = (x + n.u) sqrt(T/T') - n.u'; if that state is thick the packet converts with
+ *        P = 2/(k' w' + 2 lambda) (2/3 + mu) (eq. 39; mu the direction cosine to the face
+ *        normal, w' the neighbour's width), else it is reflected from a uniform point of the
+ *        interface with an isotropic direction back into its cell and x unchanged; if thin it
+ *        flies on in the neighbour.
+ *    In a shell the bulk velocity changes direction with position: the packet's comoving x
+ *    is kept for the point where it is (the lab frequency x + n.u is constant along a flight,
+ *    so x changes by n.(u(p0) - u(p1)) between its start p0 and end p1), and the opacity of
+ *    a flight is that of its starting x (exact for slabs, where u is uniform in a cell).
+ *  - Escapes are tallied by face (slab: 2 rows; sphere: 1), lab bin and time (c = 1).
+ *
+ * Random numbers: xoshiro256** per packet seeded by splitmix64(seed ^ id*golden).
+ */
+#include <math.h>
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "mcphys.h"
+
+#define OH_TIME_BINS 128
+#define OH_STEP_BINS 64
+
+typedef struct {
+    int32_t geometry;              /* 0 slab, 1 spherical shells */
+    int32_t nc, nb;
+    const double *faces;           /* nc+1 face coordinates (z, or r) */
+    const double *edges;           /* nb+1 */
+    const double *k;               /* [nc*nb] bin-averaged opacity (eq. 14) */
+    const uint8_t *thick;          /* [nc*nb] */
+    const double *rate_face;       /* [nc*nb*2] */
+    const uint8_t *face_mc;        /* [nc*nb*2] the leak through this face uses the interface rate */
+    const double *rate_dn, *rate_up;  /* [nc*nb] */
+    const int64_t *nbr;            /* [nc*2]: >= 0 cell, -1 vacuum, -2 no face */
+    const double *rho, *shift;     /* [nc*2] DDMC re-binning map into the neighbour */
+    const double *k0, *a, *T;      /* [nc] */
+    const double *u;               /* [nc] bulk speed along +z (slab) or +r^ (shell) / v_th(T_c) */
+    double lambda, x_crit;
+    int32_t n_src;
+    const int64_t *src_state;      /* [n_src] */
+    const double *src_pos;         /* [n_src] z, or r (a source at r > 0 is placed on the +z axis) */
+    const double *src_x;           /* [n_src] */
+    const double *src_cdf;         /* [n_src] */
+} oh_problem;
+
+typedef struct {
+    int64_t *spectrum;     /* [rows*(nb+2)], rows = 2 (slab) or 1 (sphere) */
+    int64_t *time_hist;    /* [OH_TIME_BINS+2] */
+    int64_t *step_hist;    /* [OH_STEP_BINS] */
+    double t_sum, t2_sum, steps_sum, mc_steps_sum, steps2_sum;
+    int64_t escaped, capped, to_mc, to_ddmc, reflected;
+} oh_result;
+
+static int locate(const double *e, int nb, double x)
+{
+    if (x < e[0]) return -1;
+    if (x >= e[nb]) return nb;
+    int lo = 0, hi = nb;
+    while (hi - lo > 1) { int m = (lo + hi) >> 1; if (x >= e[m]) lo = m; else hi = m; }
+    return lo;
+}
+
+static int time_bin(double t)
+{
+    if (!(t >= 1e-3)) return 0;
+    double u = (log10(t) + 3.0) / 9.0 * OH_TIME_BINS;
+    if (u >= OH_TIME_BINS) return OH_TIME_BINS + 1;
+    return 1 + (int)u;
+}
+
+static int step_bin(uint64_t n) { int b = 0; while (n > 1) { n >>= 1; ++b; } return b; }
+
+static double dot(const double a[3], const double b[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+/* unit vector along p (the +z axis at the origin) */
+static void radial(const double p[3], double e[3])
+{
+    double r = sqrt(dot(p, p));
+    if (r > 0.0) { e[0] = p[0] / r; e[1] = p[1] / r; e[2] = p[2] / r; }
+    else { e[0] = 0.0; e[1] = 0.0; e[2] = 1.0; }
+}
+
+/* outward normal of a cell at face f (0 lower / inner, 1 upper / outer) at point p */
+static void face_normal(const oh_problem *P, int f, const double p[3], double nrm[3])
+{
+    double s = f ? 1.0 : -1.0;
+    if (P->geometry == 0) { nrm[0] = 0.0; nrm[1] = 0.0; nrm[2] = s; return; }
+    radial(p, nrm);
+    nrm[0] *= s; nrm[1] *= s; nrm[2] *= s;
+}
+
+/* n . u of cell c at point p */
+static double n_dot_u(const oh_problem *P, int64_t c, const double p[3], const double n[3])
+{
+    if (P->geometry == 0) return n[2] * P->u[c];
+    double e[3];
+    radial(p, e);
+    return P->u[c] * dot(n, e);
+}
+
+/* direction with cosine mu ~ U(0, 1] about the unit vector N, uniform azimuth */
+static void hemi_about(rng_t *r, const double N[3], double n[3])
+{
+    double mu = ru(r), ph = 2.0 * M_PI * ru(r), s = sqrt(fmax(0.0, 1.0 - mu * mu));
+    double t1[3], t2[3];
+    /* an orthonormal pair perpendicular to N */
+    if (fabs(N[2]) < 0.9) { t1[0] = -N[1]; t1[1] = N[0]; t1[2] = 0.0; }
+    else { t1[0] = 0.0; t1[1] = -N[2]; t1[2] = N[1]; }
+    double l = sqrt(dot(t1, t1));
+    t1[0] /= l; t1[1] /= l; t1[2] /= l;
+    t2[0] = N[1] * t1[2] - N[2] * t1[1];
+    t2[1] = N[2] * t1[0] - N[0] * t1[2];
+    t2[2] = N[0] * t1[1] - N[1] * t1[0];
+    double c1 = s * cos(ph), c2 = s * sin(ph);
+    for (int d = 0; d < 3; ++d) n[d] = mu * N[d] + c1 * t1[d] + c2 * t2[d];
+}
+
+/* uniform point of face f of cell c */
+static void face_point(const oh_problem *P, int64_t c, int f, rng_t *r, double p[3])
+{
+    double rf = P->faces[c + f];
+    if (P->geometry == 0) { p[0] = 0.0; p[1] = 0.0; p[2] = rf; return; }
+    double w[3];
+    iso_dir(r, w);
+    p[0] = rf * w[0]; p[1] = rf * w[1]; p[2] = rf * w[2];
+}
+
+/* uniform point of cell c (uniform in volume) */
+static void cell_point(const oh_problem *P, int64_t c, rng_t *r, double p[3])
+{
+    double lo = P->faces[c], hi = P->faces[c + 1];
+    if (P->geometry == 0) { p[0] = 0.0; p[1] = 0.0; p[2] = lo + (hi - lo) * ru(r); return; }
+    double rr = cbrt(lo * lo * lo + ru(r) * (hi * hi * hi - lo * lo * lo));
+    double w[3];
+    iso_dir(r, w);
+    p[0] = rr * w[0]; p[1] = rr * w[1]; p[2] = rr * w[2];
+}
+
+/* distance along n to the boundary of cell c from p, and the face it reaches */
+static double wall_distance(const oh_problem *P, int64_t c, const double p[3], const double n[3], int *face)
+{
+    double lo = P->faces[c], hi = P->faces[c + 1];
+    if (P->geometry == 0) {
+        if (n[2] > 0.0) { *face = 1; return fmax(0.0, (hi - p[2]) / n[2]); }
+        if (n[2] < 0.0) { *face = 0; return fmax(0.0, (lo - p[2]) / n[2]); }
+        *face = 1;
+        return INFINITY;
+    }
+    double b = dot(p, n), pp = dot(p, p);
+    double s_out = -b + sqrt(fmax(0.0, b * b - pp + hi * hi));
+    *face = 1;
+    if (lo > 0.0 && b < 0.0) {
+        double disc = b * b - pp + lo * lo;
+        if (disc > 0.0) {
+            double s_in = -b - sqrt(disc);
+            if (s_in < 0.0) s_in = 0.0;
+            if (s_in < s_out) { *face = 0; return s_in; }
+        }
+    }
+    return fmax(0.0, s_out);
+}
+
+static void tally_escape(oh_result *R, const oh_problem *P, int f, double xlab, double t)
+{
+    int nb = P->nb;
+    int row = P->geometry == 0 ? f : 0;
+    int slot = locate(P->edges, nb, xlab) + 1;
+    R->spectrum[(int64_t)row * (nb + 2) + slot]++;
+    R->escaped++;
+    R->t_sum += t;
+    R->t2_sum += t * t;
+    R->time_hist[time_bin(t)]++;
+}
+
+typedef struct {
+    const oh_problem *p;
+    uint64_t first, n, seed, max_steps;
+    volatile uint64_t *next;
+    pthread_mutex_t *lock;
+    oh_result *out;
+} job_t;
+
+static void walk_packet(const oh_problem *P, uint64_t id, uint64_t seed, uint64_t max_steps, oh_result *R)
+{
+    rng_t r;
+    uint64_t xs = seed ^ (id * 0x9E3779B97F4A7C15ull);
+    for (int i = 0; i < 4; ++i) r.s[i] = sm64(&xs);
+    const int nb = P->nb;
+    double uu = ru(&r);
+    int k = 0;
+    while (k < P->n_src - 1 && uu >= P->src_cdf[k]) ++k;
+    int64_t s = P->src_state[k];
+    int64_t c = s / nb;
+    int j = (int)(s % nb);
+    int mc = !P->thick[s];
+    double pos[3] = {0.0, 0.0, P->src_pos[k]};
+    double n[3] = {0.0, 0.0, 1.0};
+    double x = P->src_x[k];
+    if (mc) iso_dir(&r, n);
+    double t = 0.0;
+    uint64_t steps = 0, mcsteps = 0;
+    for (;;) {
+        if (steps >= max_steps) { R->capped++; break; }
+        ++steps;
+        if (!mc) {
+            s = c * nb + j;
+            double best = INFINITY;
+            int ev = -1;
+            for (int f = 0; f < 2; ++f) {
+                double rt = P->rate_face[s * 2 + f];
+                if (rt > 0.0) { double l = -log(ru(&r)) / rt; if (l < best) { best = l; ev = f; } }
+            }
+            if (P->rate_dn[s] > 0.0) { double l = -log(ru(&r)) / P->rate_dn[s]; if (l < best) { best = l; ev = 2; } }
+            if (P->rate_up[s] > 0.0) { double l = -log(ru(&r)) / P->rate_up[s]; if (l < best) { best = l; ev = 3; } }
+            t += best;
+            if (ev >= 2) {
+                j += (ev == 2) ? -1 : 1;
+                if (!P->thick[c * nb + j]) {   /* frequency leak into a thin bin */
+                    cell_point(P, c, &r, pos);
+                    iso_dir(&r, n);
+                    x = P->edges[j] + (P->edges[j + 1] - P->edges[j]) * ru(&r);
+                    mc = 1;
+                    R->to_mc++;
+                }
+                continue;
+            }
+            int f = ev;
+            int64_t nc = P->nbr[c * 2 + f];
+            double xin = P->edges[j] + (P->edges[j + 1] - P->edges[j]) * ru(&r);
+            if (P->face_mc[s * 2 + f] || nc < 0) {
+                /* interface leak: MC at a uniform point of the face, isotropic outward */
+                double N[3];
+                face_point(P, c, f, &r, pos);
+                face_normal(P, f, pos, N);
+                hemi_about(&r, N, n);
+                double nu = n_dot_u(P, c, pos, n);
+                if (nc < 0) { tally_escape(R, P, f, xin + nu, t); break; }
+                x = (xin + nu) * sqrt(P->T[c] / P->T[nc]) - n_dot_u(P, nc, pos, n);
+                c = nc;
+                mc = 1;
+                R->to_mc++;
+                continue;
+            }
+            double rho = P->rho[c * 2 + f], sh = P->shift[c * 2 + f];
+            double xsh = rho * xin + sh;
+            if (rho != 1.0 || sh != 0.0) {
+                int jn = locate(P->edges, nb, xsh);
+                j = jn < 0 ? 0 : (jn > nb - 1 ? nb - 1 : jn);
+            }
+            c = nc;
+            if (!P->thick[c * nb + j]) {   /* re-binned into a thin state */
+                cell_point(P, c, &r, pos);
+                iso_dir(&r, n);
+                x = xsh;
+                mc = 1;
+                R->to_mc++;
+            }
+            continue;
+        }
+        /* ---- continuous MC ---- */
+        ++mcsteps;
+        int fexit;
+        double dwall = wall_distance(P, c, pos, n, &fexit);
+        double kx = P->k0[c] * mc_voigt(P->a[c], x);
+        double ds = -log(ru(&r)) / kx;
+        double p0[3] = {pos[0], pos[1], pos[2]};
+        double u0 = n_dot_u(P, c, p0, n);
+        if (ds < dwall) {
+            for (int d = 0; d < 3; ++d) pos[d] += ds * n[d];
+            t += ds;
+            x += u0 - n_dot_u(P, c, pos, n);
+            x = scatter(P->a[c], x, n, &r, P->x_crit);
+            int jj = locate(P->edges, nb, x);
+            if (jj >= 0 && jj < nb && P->thick[c * nb + jj]) { j = jj; mc = 0; R->to_ddmc++; }
+            continue;
+        }
+        for (int d = 0; d < 3; ++d) pos[d] += dwall * n[d];
+        t += dwall;
+        int f = fexit;
+        if (P->geometry == 0) {
+            pos[2] = P->faces[c + f];
+        } else {   /* put the point exactly on its sphere */
+            double e[3];
+            radial(pos, e);
+            for (int d = 0; d < 3; ++d) pos[d] = P->faces[c + f] * e[d];
+        }
+        double nu = n_dot_u(P, c, pos, n);
+        x += u0 - nu;                                   /* comoving x at the wall */
+        int64_t nc = P->nbr[c * 2 + f];
+        if (nc == -2) continue;                         /* no face (r = 0): cannot occur */
+        if (nc < 0) { tally_escape(R, P, f, x + nu, t); break; }
+        double xn = (x + nu) * sqrt(P->T[c] / P->T[nc]) - n_dot_u(P, nc, pos, n);
+        int jn = locate(P->edges, nb, xn);
+        if (jn >= 0 && jn < nb && P->thick[nc * nb + jn]) {
+            double N[3];
+            face_normal(P, f, pos, N);
+            double wn = P->faces[nc + 1] - P->faces[nc];
+            double mu = fabs(dot(n, N));
+            double Pacc = 2.0 / (P->k[nc * nb + jn] * wn + 2.0 * P->lambda) * (2.0 / 3.0 + mu);
+            if (ru(&r) < Pacc) { c = nc; j = jn; mc = 0; R->to_ddmc++; continue; }
+            /* reflected into c: uniform point of the interface, isotropic inward direction;
+             * x unchanged at the new point */
+            double Nin[3];
+            face_point(P, c, f, &r, pos);
+            face_normal(P, f, pos, N);
+            Nin[0] = -N[0]; Nin[1] = -N[1]; Nin[2] = -N[2];
+            hemi_about(&r, Nin, n);
+            R->reflected++;
+            continue;
+        }
+        c = nc;
+        x = xn;
+    }
+    R->steps_sum += (double)steps;
+    R->mc_steps_sum += (double)mcsteps;
+    R->steps2_sum += (double)steps * (double)steps;
+    R->step_hist[step_bin(steps ? steps : 1)]++;
+}
+
+static void *worker(void *arg)
+{
+    job_t *jb = (job_t *)arg;
+    const oh_problem *P = jb->p;
+    oh_result L;
+    memset(&L, 0, sizeof L);
+    size_t rows = P->geometry == 0 ? 2 : 1;
+    size_t ns = rows * (size_t)(P->nb + 2);
+    L.spectrum = calloc(ns, 8);
+    L.time_hist = calloc(OH_TIME_BINS + 2, 8);
+    L.step_hist = calloc(OH_STEP_BINS, 8);
+    for (;;) {
+        uint64_t b = __sync_fetch_and_add(jb->next, 8);
+        if (b >= jb->n) break;
+        uint64_t e = b + 8 < jb->n ? b + 8 : jb->n;
+        for (uint64_t i = b; i < e; ++i) walk_packet(P, jb->first + i, jb->seed, jb->max_steps, &L);
+    }
+    pthread_mutex_lock(jb->lock);
+    oh_result *R = jb->out;
+    for (size_t i = 0; i < ns; ++i) R->spectrum[i] += L.spectrum[i];
+    for (int i = 0; i < OH_TIME_BINS + 2; ++i) R->time_hist[i] += L.time_hist[i];
+    for (int i = 0; i < OH_STEP_BINS; ++i) R->step_hist[i] += L.step_hist[i];
+    R->t_sum += L.t_sum; R->t2_sum += L.t2_sum; R->steps_sum += L.steps_sum; R->mc_steps_sum += L.mc_steps_sum;
+    R->steps2_sum += L.steps2_sum;
+    R->escaped += L.escaped; R->capped += L.capped; R->to_mc += L.to_mc; R->to_ddmc += L.to_ddmc;
+    R->reflected += L.reflected;
+    pthread_mutex_unlock(jb->lock);
+    free(L.spectrum); free(L.time_hist); free(L.step_hist);
+    return NULL;
+}
+
+int oh_run(const oh_problem *p, uint64_t first, uint64_t n, uint64_t seed, uint64_t max_steps, int threads,
+           oh_result *out)
+{
+    if (!p || !out || threads < 1) return -1;
+    volatile uint64_t next = 0;
+    pthread_mutex_t lock;
+    pthread_mutex_init(&lock, NULL);
+    job_t jb = {p, first, n, seed, max_steps, &next, &lock, out};
+    pthread_t *th = malloc(sizeof(pthread_t) * threads);
+    for (int i = 0; i < threads; ++i) pthread_create(&th[i], NULL, worker, &jb);
+    for (int i = 0; i < threads; ++i) pthread_join(th[i], NULL);
+    free(th);
+    pthread_mutex_destroy(&lock);
+    return 0;
+}

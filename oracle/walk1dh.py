@@ -1,0 +1,136 @@
+"""O1-1DH wrapper: the literal FP64 hybrid DDMC / continuous-MC walker on slabs and spherical
+shells (oracle/walk1dh.c) -- test infrastructure only."""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import os
+import subprocess
+
+import numpy as np
+
+from . import linemath
+from . import tables as tb
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(HERE, "libo1walk1dh.so")
+TIME_BINS = 128
+STEP_BINS = 64
+
+
+def build_lib():
+    src = os.path.join(HERE, "walk1dh.c")
+    subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-Wall", "-o", LIB, src, "-lm", "-lpthread"])
+    return LIB
+
+
+class _Problem(C.Structure):
+    _fields_ = [("geometry", C.c_int32), ("nc", C.c_int32), ("nb", C.c_int32), ("faces", C.c_void_p),
+                ("edges", C.c_void_p), ("k", C.c_void_p), ("thick", C.c_void_p), ("rate_face", C.c_void_p),
+                ("face_mc", C.c_void_p), ("rate_dn", C.c_void_p), ("rate_up", C.c_void_p), ("nbr", C.c_void_p),
+                ("rho", C.c_void_p), ("shift", C.c_void_p), ("k0", C.c_void_p), ("a", C.c_void_p),
+                ("T", C.c_void_p), ("u", C.c_void_p), ("lambda_", C.c_double), ("x_crit", C.c_double),
+                ("n_src", C.c_int32), ("src_state", C.c_void_p), ("src_pos", C.c_void_p), ("src_x", C.c_void_p),
+                ("src_cdf", C.c_void_p)]
+
+
+class _Result(C.Structure):
+    _fields_ = [("spectrum", C.c_void_p), ("time_hist", C.c_void_p), ("step_hist", C.c_void_p),
+                ("t_sum", C.c_double), ("t2_sum", C.c_double), ("steps_sum", C.c_double),
+                ("mc_steps_sum", C.c_double), ("steps2_sum", C.c_double), ("escaped", C.c_int64),
+                ("capped", C.c_int64), ("to_mc", C.c_int64), ("to_ddmc", C.c_int64), ("reflected", C.c_int64)]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build_lib()
+        _lib = C.CDLL(LIB)
+        _lib.oh_run.restype = C.c_int
+        _lib.oh_run.argtypes = [C.POINTER(_Problem), C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint64,
+                                C.c_int, C.POINTER(_Result)]
+    return _lib
+
+
+@dataclasses.dataclass
+class Walk1DHResult:
+    spectrum: np.ndarray     # (rows, nb+2): slab rows = faces 0/1, sphere one row
+    time_hist: np.ndarray
+    step_hist: np.ndarray
+    t_sum: float
+    t2_sum: float
+    steps_sum: float
+    mc_steps_sum: float
+    steps2_sum: float
+    escaped: int
+    capped: int
+    to_mc: int
+    to_ddmc: int
+    reflected: int
+    n_packets: int
+
+    @property
+    def t_mean(self):
+        return self.t_sum / max(self.escaped, 1)
+
+    @property
+    def t_var(self):
+        return self.t2_sum / max(self.escaped, 1) - self.t_mean ** 2
+
+    @property
+    def steps_mean(self):
+        return self.steps_sum / max(self.n_packets, 1)
+
+    @property
+    def steps_var(self):
+        return self.steps2_sum / max(self.n_packets, 1) - self.steps_mean ** 2
+
+
+def run(m, n_packets=None, seed=0, first_id=0, max_steps=(1 << 62), n_threads=None, tabs=None, x_crit=0.0):
+    """Walk ``n_packets`` packets of the 1D medium ``m`` (slab or sphere, pure or hybrid)."""
+    lib = _load()
+    assert m.geometry in (tb.SLAB, tb.SPHERE)
+    t = tabs if tabs is not None else tb.build(m)
+    n = int(m.n_packets if n_packets is None else n_packets)
+    keep = []
+
+    def arr(a, dt):
+        a = np.ascontiguousarray(a, dtype=dt)
+        keep.append(a)
+        return a.ctypes.data
+
+    T = np.asarray(m.temp, dtype=np.float64)
+    vth = linemath.v_thermal(T)
+    vel = np.zeros(t.nc) if m.vel is None else np.asarray(m.vel, dtype=np.float64).reshape(t.nc)
+    st, pos, xs, pr = [], [], [], []
+    nsrc = len(m.src_x)
+    for s in range(nsrc):
+        one = m.replace(src_pos=np.asarray(m.src_pos)[s:s + 1], src_x=np.asarray(m.src_x)[s:s + 1])
+        for state, p in tb.locate_sources(one):
+            st.append(state)
+            pos.append(float(np.asarray(m.src_pos)[s][0]))
+            xs.append(float(np.asarray(m.src_x)[s]))
+            pr.append(p / nsrc)
+    cdf = np.cumsum(pr)
+    cdf[-1] = 1.0
+    P = _Problem(int(m.geometry), t.nc, t.nb, arr(m.faces[0], np.float64), arr(t.bin_edges, np.float64),
+                 arr(t.k, np.float64), arr(t.thick, np.uint8), arr(t.rate_face, np.float64),
+                 arr(t.face_is_mc, np.uint8), arr(t.rate_dn, np.float64), arr(t.rate_up, np.float64),
+                 arr(t.nbr, np.int64), arr(t.rho, np.float64), arr(t.shift, np.float64), arr(m.k0, np.float64),
+                 arr(linemath.damping(T), np.float64), arr(T, np.float64), arr(vel / vth, np.float64),
+                 float(m.lam), float(x_crit), len(st), arr(st, np.int64), arr(pos, np.float64),
+                 arr(xs, np.float64), arr(cdf, np.float64))
+    rows = 2 if m.geometry == tb.SLAB else 1
+    spec = np.zeros((rows, t.nb + 2), dtype=np.int64)
+    th = np.zeros(TIME_BINS + 2, dtype=np.int64)
+    sh = np.zeros(STEP_BINS, dtype=np.int64)
+    R = _Result(spec.ctypes.data, th.ctypes.data, sh.ctypes.data, 0.0, 0.0, 0.0, 0.0, 0.0, 0, 0, 0, 0, 0)
+    rc = lib.oh_run(C.byref(P), first_id, n, seed, max_steps, n_threads or os.cpu_count() or 1, C.byref(R))
+    if rc != 0:
+        raise RuntimeError("oh_run failed")
+    return Walk1DHResult(spec, th, sh, R.t_sum, R.t2_sum, R.steps_sum, R.mc_steps_sum, R.steps2_sum, R.escaped,
+                         R.capped, R.to_mc, R.to_ddmc, R.reflected, n)

@@ -62,7 +62,8 @@ def _load():
         _lib.o3_upar_samples.restype = None
         _lib.o3_upar_samples.argtypes = [C.c_double, C.c_double, C.c_uint64, C.c_int64, C.c_void_p]
         _lib.o3_redistribution_samples.restype = None
-        _lib.o3_redistribution_samples.argtypes = [C.c_double, C.c_double, C.c_uint64, C.c_int64, C.c_void_p]
+        _lib.o3_redistribution_samples.argtypes = [C.c_double, C.c_double, C.c_double, C.c_uint64, C.c_int64,
+                                                   C.c_void_p]
     return _lib
 
 
@@ -80,10 +81,11 @@ def upar_samples(a, x, n, seed=1):
     return out
 
 
-def redistribution_samples(a, x, n, seed=1):
-    """Outgoing comoving frequencies of n scatterings of a photon absorbed at x."""
+def redistribution_samples(a, x, n, seed=1, x_crit=0.0):
+    """Outgoing comoving frequencies of n scatterings of a photon absorbed at x (optional
+    core-skipping above x_crit)."""
     out = np.zeros(int(n))
-    _load().o3_redistribution_samples(float(a), float(x), int(seed), int(n), out.ctypes.data)
+    _load().o3_redistribution_samples(float(a), float(x), float(x_crit), int(seed), int(n), out.ctypes.data)
     return out
 
 
