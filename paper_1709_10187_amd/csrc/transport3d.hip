@@ -607,18 +607,25 @@ __global__ __launch_bounds__(256) void walk3d(const uint8_t *__restrict__ tb, Wa
         }
         if (!__any(p.active)) break;
 
-        if (p.active) {
-            const DevCloud &c = clouds[SINGLE ? 0 : p.cl];
-            const float lambda = (float)c.lambda;
-            for (int k = 0; k < a.chunk; ++k) {
-                if (p.steps >= a.max_steps) {
-                    finish(p, c, tally, false, 0, 0);
-                    break;
-                }
+        // Mode-batched passes: a pass advances either the wave's DDMC lanes by one step or its
+        // continuous-MC lanes by one event, never both, so a wave with a few MC lanes does not
+        // issue the long MC path on every step.  The MC lanes wait for a pass of their own
+        // until they are at least a quarter as many as the DDMC lanes, or every eighth pass.
+        // Every packet still takes its own steps in its own order from its own stream, so the
+        // results do not depend on this schedule.
+        const DevCloud &c = clouds[SINGLE ? 0 : p.cl];
+        const float lambda = (float)c.lambda;
+        for (int k = 0; k < a.chunk; ++k) {
+            if (p.active && p.steps >= a.max_steps) finish(p, c, tally, false, 0, 0);
+            const uint64_t bm = __ballot(p.active && p.mc);
+            const uint64_t bd = __ballot(p.active && !p.mc);
+            if (!(bm | bd)) break;
+            const int nm = __popcll(bm), nd = __popcll(bd);
+            const bool mc_pass = nm > 0 && (4 * nm >= nd || (k & 7) == 7);
+            if (p.active && p.mc == mc_pass) {
                 ++p.steps;
-                if (p.mc) mc_step(p, c, tb, a, tally, vtab, u0tab, lambda);
+                if (mc_pass) mc_step(p, c, tb, a, tally, vtab, u0tab, lambda);
                 else ddmc_step(p, c, tb, a, tally);
-                if (!p.active) break;
             }
         }
     }
