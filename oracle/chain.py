@@ -12,6 +12,18 @@ moments of the escape time are solutions of sparse linear systems:
   E[steps] = sum_s v_s,  E[T] = sum_s v_s / K_s  (c = 1),
   (I - P) m1 = tau, E[T^2] = 2 sum_s v_s tau_s m1_s, with tau_s = 1 / K_s.
 
+Dust (Sec. 2.4): the leakage coefficients use the total scattering coefficient (the tables add
+the dust scattering k_s), and absorption is one more exponential channel of rate k_a, so
+K_s = sum of leakage rates + k_a and the chain is absorbed with probability
+sum_s v_s k_a / K_s.  Escape-time moments are then conditioned on escape: with h the
+escape probability from each state ((I - P) h = the one-step escape probability),
+(I - P) u = tau h gives E[T 1_esc] = v . (tau h) and E[T^2 1_esc] = 2 v . (tau u).
+
+The transient law (time-dependent estimators of eq. 17): the occupation probabilities
+p(t) = p0 exp(Q t) of the generator Q = rates - diag(K), at census times and averaged over
+the intervals between them; with an emission window [t_s, t_e] the law is the flash law
+averaged over emission times.
+
 With bulk velocity a spatial move draws x uniformly in the bin, maps it to the
 neighbour's frame (Sec. 2.5) and re-bins it; the exact transition weights are
 the overlaps of the shifted bin with the neighbour's bins (parts outside the
@@ -34,12 +46,13 @@ from . import tables as tb
 class ChainResult:
     spectrum: np.ndarray      # (n_escape_faces, nb + 2) escape probability per face and lab bin
     faces: list               # face ids of the rows of spectrum
-    steps: float              # E[number of leakage events]
+    steps: float              # E[number of leakage events] (an absorption counts as one)
     steps2: float             # E[steps^2]
-    t_mean: float             # E[escape time] (length / c)
-    t2: float                 # E[escape time^2]
+    t_mean: float             # E[escape time | escaped] (length / c)
+    t2: float                 # E[escape time^2 | escaped]
     visits: np.ndarray        # expected visits per state (nc, nb)
-    total: float              # sum of all escape probabilities (should be 1)
+    total: float              # sum of all escape probabilities (1 without dust)
+    absorbed: float = 0.0     # probability of absorption by dust (Sec. 2.4)
 
     @property
     def t_var(self):
@@ -151,14 +164,16 @@ def lab_bin_probs_3d(edges, lo, hi, u_n, u_t, n_mu=64, n_phi=64):
     return (wts @ slots) / wts.sum()
 
 
-def solve(m, tabs=None) -> ChainResult:
-    """Exact expected results of pure DDMC on medium ``m``."""
+def _chain(m, tabs=None):
+    """The sparse chain of pure DDMC on medium ``m``: transient-to-transient rates, total
+    rates K (leakage plus dust absorption), escape channels and the emission law."""
     t = tabs if tabs is not None else tb.build(m)
     if not np.all(t.thick):
         raise ValueError("the exact chain covers pure DDMC only (every state thick)")
     nc, nb, nf = t.nc, t.nb, t.nf
     ns = nc * nb
-    K = t.K.reshape(ns)
+    k_abs = np.zeros(nc) if t.k_abs is None else t.k_abs
+    K = (t.K + k_abs[:, None]).reshape(ns)
     edges = t.bin_edges
     rows, cols, vals = [], [], []
     sidx = np.arange(ns).reshape(nc, nb)
@@ -220,23 +235,95 @@ def solve(m, tabs=None) -> ChainResult:
             vals.append(r[src_j[keep]] * wts[keep])
     rows = np.concatenate(rows)
     cols = np.concatenate(cols)
-    vals = np.concatenate(vals) / K[rows]
-    P = sp.csr_matrix((vals, (rows, cols)), shape=(ns, ns))
-    A = (sp.identity(ns, format="csr") - P).tocsc()
-    lu = spla.splu(A)
+    R = sp.csr_matrix((np.concatenate(vals), (rows, cols)), shape=(ns, ns))
     pi0 = np.zeros(ns)
     for st, pr in tb.locate_sources(m):
         pi0[st] += pr
+    es, ef, eb, er = (np.concatenate(z) for z in (es, ef, eb, er))
+    return dict(t=t, ns=ns, nb=nb, K=K, R=R, pi0=pi0, esc=(es, ef, eb, er), faces=esc_faces,
+                k_abs=np.repeat(k_abs, nb))
+
+
+def solve(m, tabs=None) -> ChainResult:
+    """Exact expected results of pure DDMC on medium ``m``."""
+    ch = _chain(m, tabs)
+    ns, nb, K, R, pi0 = ch["ns"], ch["nb"], ch["K"], ch["R"], ch["pi0"]
+    es, ef, eb, er = ch["esc"]
+    nc = ns // nb
+    P = sp.diags(1.0 / K) @ R
+    A = (sp.identity(ns, format="csr") - P).tocsc()
+    lu = spla.splu(A)
     v = lu.solve(pi0, trans="T")
     tau = 1.0 / K
-    m1 = lu.solve(tau)
     n1 = lu.solve(np.ones(ns))
-    es, ef, eb, er = (np.concatenate(z) for z in (es, ef, eb, er))
+    nrow = len(ch["faces"])
     spec = np.bincount(ef * (nb + 2) + eb, weights=(v / K)[es] * er,
-                       minlength=len(esc_faces) * (nb + 2)).reshape(len(esc_faces), nb + 2)
+                       minlength=nrow * (nb + 2)).reshape(nrow, nb + 2)
+    # escape probability from each state (1 without dust)
+    esc1 = np.bincount(es, weights=er, minlength=ns) / K
+    h = lu.solve(esc1)
+    u = lu.solve(tau * h)
+    p_esc = float(pi0 @ h)
     steps = float(v.sum())
     steps2 = float(v @ (2.0 * n1 - 1.0))
-    t_mean = float(v @ tau)
-    t2 = float(2.0 * v @ (tau * m1))
-    return ChainResult(spectrum=spec, faces=esc_faces, steps=steps, steps2=steps2, t_mean=t_mean,
-                       t2=t2, visits=v.reshape(nc, nb), total=float(spec.sum()))
+    t_mean = float(v @ (tau * h)) / p_esc
+    t2 = float(2.0 * v @ (tau * u)) / p_esc
+    absorbed = float(v @ (ch["k_abs"] / K))
+    return ChainResult(spectrum=spec, faces=ch["faces"], steps=steps, steps2=steps2, t_mean=t_mean,
+                       t2=t2, visits=v.reshape(nc, nb), total=float(spec.sum()), absorbed=absorbed)
+
+
+@dataclasses.dataclass
+class TransientResult:
+    edges: np.ndarray         # census times t_0 < ... < t_n
+    at_edges: np.ndarray      # (n+1, nc, nb): P(the packet is in state s at t_e)
+    mean_in: np.ndarray       # (n, nc, nb): the occupation averaged over [t_e, t_e+1)
+    escaped_by: np.ndarray    # (n+1,): P(escaped by t_e)
+
+
+def transient(m, edges, tabs=None, emit=None) -> TransientResult:
+    """Transient law of pure DDMC on a small medium (dense matrices): the expectations, per
+    emitted packet, of the 'bin' estimator at each census time and of the 'path' estimator
+    over each census interval (eq. 17, without the energy and volume factors).  ``emit`` =
+    (t_s, t_e) emits packets uniformly in time over that window (t_e > t_s), else a flash at
+    t = 0."""
+    from scipy import linalg as la
+    ch = _chain(m, tabs)
+    ns, nb, K, R, pi0 = ch["ns"], ch["nb"], ch["K"], ch["R"], ch["pi0"]
+    if ns > 4000:
+        raise ValueError("the dense transient solve is for small media")
+    es, ef, eb, er = ch["esc"]
+    Q = R.toarray() - np.diag(K)
+    esc_rate = np.bincount(es, weights=er, minlength=ns)
+    Qi = la.inv(Q)
+    edges = np.asarray(edges, dtype=np.float64)
+
+    def E(t):     # exp(Q t), t >= 0
+        return la.expm(Q * t)
+
+    def F(t):     # int_0^t exp(Q s) ds
+        return Qi @ (E(t) - np.eye(ns)) if t > 0 else np.zeros((ns, ns))
+
+    def G(t):     # int_0^t F(s) ds
+        return Qi @ (F(t) - t * np.eye(ns)) if t > 0 else np.zeros((ns, ns))
+
+    def occ(t):   # P(in state s at time t)
+        if emit is None:
+            return pi0 @ E(t)
+        ts, te = emit
+        return pi0 @ (F(max(t - ts, 0.0)) - F(max(t - te, 0.0))) / (te - ts)
+
+    def occ_int(t):   # int_0^t occ
+        if emit is None:
+            return pi0 @ F(t)
+        ts, te = emit
+        return pi0 @ (G(max(t - ts, 0.0)) - G(max(t - te, 0.0))) / (te - ts)
+
+    at = np.array([occ(t) for t in edges])
+    cum = np.array([occ_int(t) for t in edges])
+    mean = (cum[1:] - cum[:-1]) / np.diff(edges)[:, None]
+    # escaped by t: the escape flux integrated, int_0^t occ . esc_rate
+    escaped = cum @ esc_rate
+    nc = ns // nb
+    return TransientResult(edges=edges, at_edges=at.reshape(len(edges), nc, nb),
+                           mean_in=mean.reshape(len(edges) - 1, nc, nb), escaped_by=escaped)

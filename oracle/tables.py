@@ -2,7 +2,10 @@
 
 For every state s = (cell c, bin j) this computes, in plain numpy FP64:
 
-* k[s]        bin-averaged opacity k0_c [calH(hi) - calH(lo)] / dx_j      (eq. 14)
+* k[s]        bin-averaged opacity k0_c [calH(hi) - calH(lo)] / dx_j      (eq. 14),
+              plus the cell's dust scattering coefficient k_s when the medium has dust
+              (the leakage coefficients use the total scattering coefficient, Sec. 2.4)
+* k_abs[c]    the cell's dust absorption coefficient k_a (zero without dust)
 * tau[s]      k[s] * w_c, w_c the cell width across a face                 (hybrid section)
 * thick[s]    tau[s] >= tau_threshold (every state when tau_threshold = 0: pure DDMC)
 * rate_face   spatial leakage through each face of the cell:
@@ -60,6 +63,7 @@ class Tables:
     u_t: np.ndarray          # (nc, nf) tangential speed / v_th(T_c) (3D; zero in 1D)
     width: np.ndarray        # (nc, nf) width of the cell across each face
     moving: bool
+    k_abs: np.ndarray = None  # (nc,) dust absorption coefficient (zeros without dust)
 
     @property
     def K(self) -> np.ndarray:
@@ -137,13 +141,16 @@ def build(m, f_mu: Optional[float] = None) -> Tables:
     fmu = m.f_mu if f_mu is None else f_mu
     lam = m.lam
 
-    # eq. (14), one cell at a time (cells may differ in temperature)
+    # eq. (14), one cell at a time (cells may differ in temperature), plus dust scattering
     k = np.empty((nc, nb))
     uniq_T, inv = np.unique(T, return_inverse=True)
     for t_idx, Tv in enumerate(uniq_T):
         prof = linemath.hcal_diff(float(linemath.damping(Tv)), lo_e, hi_e) / dx
         cells = np.nonzero(inv == t_idx)[0]
         k[cells, :] = k0[cells, None] * prof[None, :]
+    k_sca = np.zeros(nc) if getattr(m, "dust_sca", None) is None else np.asarray(m.dust_sca, dtype=np.float64)
+    k_abs = np.zeros(nc) if getattr(m, "dust_abs", None) is None else np.asarray(m.dust_abs, dtype=np.float64)
+    k = k + k_sca[:, None]
 
     wmin = width.min(axis=1)
     tau = k * wmin[:, None]
@@ -192,7 +199,7 @@ def build(m, f_mu: Optional[float] = None) -> Tables:
                     continue
                 aa = float(linemath.damping(Tv))
                 kn[cells[sel], :] = (k0[nbc[sel], None] * linemath.hcal_diff(aa, lo_s[sel], hi_s[sel])
-                                     / (hi_s[sel] - lo_s[sel]))
+                                     / (hi_s[sel] - lo_s[sel]) + k_sca[nbc[sel], None])
         wn = np.zeros(nc)
         wn[has] = width[nb_c[has], f]
         tau_n = kn * np.where(has, wmin[np.where(has, nb_c, 0)], 0.0)[:, None]
@@ -224,7 +231,7 @@ def build(m, f_mu: Optional[float] = None) -> Tables:
     return Tables(geometry=m.geometry, nc=nc, nb=nb, nf=nf, bin_edges=edges, k=k, tau=tau,
                   thick=thick, rate_face=rate_face, face_is_mc=face_is_mc, rate_dn=rate_dn,
                   rate_up=rate_up, nbr=nbr, rho=rho, shift=shift, u_n=u_n, u_t=u_t, width=width,
-                  moving=bool(moving))
+                  moving=bool(moving), k_abs=k_abs)
 
 
 def locate_sources(m):

@@ -36,6 +36,14 @@
  *    so x changes by n.(u(p0) - u(p1)) between its start p0 and end p1), and the opacity of
  *    a flight is that of its starting x (exact for slabs, where u is uniform in a cell).
  *  - Escapes are tallied by face (slab: 2 rows; sphere: 1), lab bin and time (c = 1).
+ *  - Dust (Sec. 2.4): the tables' rates already use the total scattering coefficient; DDMC
+ *    states have one more exponential distance, to absorption at rate k_a, and an absorbed
+ *    packet is removed after that residence; MC flights meet Lya, dust scattering (k_s:
+ *    isotropic, coherent in the comoving frame) and dust absorption (k_a) in proportion.
+ *  - Time-dependent estimators (eq. 17), unnormalised: at every census time t_e the packet's
+ *    state is counted ('bin'), and its residence time in each state is summed per census
+ *    interval ('path'); an MC packet's state is (cell, bin of its comoving x at the start of
+ *    the flight).  Packets are emitted at t = 0, or uniformly over their source's window.
  *
  * Random numbers: xoshiro256** per packet seeded by splitmix64(seed ^ id*golden).
  */
@@ -70,6 +78,10 @@ typedef struct {
     const double *src_pos;         /* [n_src] z, or r (a source at r > 0 is placed on the +z axis) */
     const double *src_x;           /* [n_src] */
     const double *src_cdf;         /* [n_src] */
+    const double *k_abs, *k_sca;   /* [nc] dust absorption / scattering coefficients, or NULL */
+    const double *src_t;           /* [n_src*2] emission windows, or NULL (flash at t = 0) */
+    int32_t n_census;              /* census intervals (0 = none) */
+    const double *census;          /* [n_census+1] increasing census times */
 } oh_problem;
 
 typedef struct {
@@ -77,7 +89,9 @@ typedef struct {
     int64_t *time_hist;    /* [OH_TIME_BINS+2] */
     int64_t *step_hist;    /* [OH_STEP_BINS] */
     double t_sum, t2_sum, steps_sum, mc_steps_sum, steps2_sum;
-    int64_t escaped, capped, to_mc, to_ddmc, reflected;
+    int64_t escaped, capped, to_mc, to_ddmc, reflected, absorbed;
+    double *e_bin;         /* [(n_census+1)*nc*nb] counts of packets in each state at each census time */
+    double *e_path;        /* [n_census*nc*nb] residence time in each state per census interval */
 } oh_result;
 
 static int locate(const double *e, int nb, double x)
@@ -189,6 +203,26 @@ static double wall_distance(const oh_problem *P, int64_t c, const double p[3], c
     return fmax(0.0, s_out);
 }
 
+/* the packet stays in state s over [t0, t1): census counts and residence times */
+static void census_add(const oh_problem *P, oh_result *R, int64_t s, double t0, double t1)
+{
+    if (P->n_census <= 0) return;
+    const int64_t ns = (int64_t)P->nc * P->nb;
+    for (int e = 0; e <= P->n_census; ++e)
+        if (P->census[e] >= t0 && P->census[e] < t1) R->e_bin[(int64_t)e * ns + s] += 1.0;
+    for (int n = 0; n < P->n_census; ++n) {
+        double a = fmax(t0, P->census[n]), b = fmin(t1, P->census[n + 1]);
+        if (b > a) R->e_path[(int64_t)n * ns + s] += b - a;
+    }
+}
+
+static int64_t mc_state(const oh_problem *P, int64_t c, double x)
+{
+    int j = locate(P->edges, P->nb, x);
+    j = j < 0 ? 0 : (j > P->nb - 1 ? P->nb - 1 : j);
+    return c * P->nb + j;
+}
+
 static void tally_escape(oh_result *R, const oh_problem *P, int f, double xlab, double t)
 {
     int nb = P->nb;
@@ -225,8 +259,9 @@ static void walk_packet(const oh_problem *P, uint64_t id, uint64_t seed, uint64_
     double pos[3] = {0.0, 0.0, P->src_pos[k]};
     double n[3] = {0.0, 0.0, 1.0};
     double x = P->src_x[k];
-    if (mc) iso_dir(&r, n);
     double t = 0.0;
+    if (P->src_t) t = P->src_t[2 * k] + (P->src_t[2 * k + 1] - P->src_t[2 * k]) * ru(&r);
+    if (mc) iso_dir(&r, n);
     uint64_t steps = 0, mcsteps = 0;
     for (;;) {
         if (steps >= max_steps) { R->capped++; break; }
@@ -241,7 +276,13 @@ static void walk_packet(const oh_problem *P, uint64_t id, uint64_t seed, uint64_
             }
             if (P->rate_dn[s] > 0.0) { double l = -log(ru(&r)) / P->rate_dn[s]; if (l < best) { best = l; ev = 2; } }
             if (P->rate_up[s] > 0.0) { double l = -log(ru(&r)) / P->rate_up[s]; if (l < best) { best = l; ev = 3; } }
+            if (P->k_abs && P->k_abs[c] > 0.0) {
+                double l = -log(ru(&r)) / P->k_abs[c];
+                if (l < best) { best = l; ev = 4; }
+            }
+            census_add(P, R, s, t, t + best);
             t += best;
+            if (ev == 4) { R->absorbed++; break; }   /* removed by dust after that residence */
             if (ev >= 2) {
                 j += (ev == 2) ? -1 : 1;
                 if (!P->thick[c * nb + j]) {   /* frequency leak into a thin bin */
@@ -290,14 +331,22 @@ static void walk_packet(const oh_problem *P, uint64_t id, uint64_t seed, uint64_
         ++mcsteps;
         int fexit;
         double dwall = wall_distance(P, c, pos, n, &fexit);
-        double kx = P->k0[c] * mc_voigt(P->a[c], x);
+        double kl = P->k0[c] * mc_voigt(P->a[c], x);
+        double ka = P->k_abs ? P->k_abs[c] : 0.0, ks = P->k_sca ? P->k_sca[c] : 0.0;
+        double kx = kl + ks + ka;
         double ds = -log(ru(&r)) / kx;
         double p0[3] = {pos[0], pos[1], pos[2]};
         double u0 = n_dot_u(P, c, p0, n);
+        census_add(P, R, mc_state(P, c, x), t, t + fmin(ds, dwall));
         if (ds < dwall) {
             for (int d = 0; d < 3; ++d) pos[d] += ds * n[d];
             t += ds;
             x += u0 - n_dot_u(P, c, pos, n);
+            if (ka > 0.0 || ks > 0.0) {   /* which opacity interacted */
+                double uu2 = ru(&r) * kx;
+                if (uu2 < ka) { R->absorbed++; break; }
+                if (uu2 < ka + ks) { iso_dir(&r, n); continue; }   /* dust: coherent, isotropic */
+            }
             x = scatter(P->a[c], x, n, &r, P->x_crit);
             int jj = locate(P->edges, nb, x);
             if (jj >= 0 && jj < nb && P->thick[c * nb + jj]) { j = jj; mc = 0; R->to_ddmc++; }
@@ -357,6 +406,11 @@ static void *worker(void *arg)
     L.spectrum = calloc(ns, 8);
     L.time_hist = calloc(OH_TIME_BINS + 2, 8);
     L.step_hist = calloc(OH_STEP_BINS, 8);
+    size_t nst = (size_t)P->nc * P->nb;
+    size_t nbin = P->n_census > 0 ? (size_t)(P->n_census + 1) * nst : 0;
+    size_t npath = P->n_census > 0 ? (size_t)P->n_census * nst : 0;
+    L.e_bin = nbin ? calloc(nbin, 8) : NULL;
+    L.e_path = npath ? calloc(npath, 8) : NULL;
     for (;;) {
         uint64_t b = __sync_fetch_and_add(jb->next, 8);
         if (b >= jb->n) break;
@@ -372,8 +426,11 @@ static void *worker(void *arg)
     R->steps2_sum += L.steps2_sum;
     R->escaped += L.escaped; R->capped += L.capped; R->to_mc += L.to_mc; R->to_ddmc += L.to_ddmc;
     R->reflected += L.reflected;
+    R->absorbed += L.absorbed;
+    for (size_t i = 0; i < nbin; ++i) R->e_bin[i] += L.e_bin[i];
+    for (size_t i = 0; i < npath; ++i) R->e_path[i] += L.e_path[i];
     pthread_mutex_unlock(jb->lock);
-    free(L.spectrum); free(L.time_hist); free(L.step_hist);
+    free(L.spectrum); free(L.time_hist); free(L.step_hist); free(L.e_bin); free(L.e_path);
     return NULL;
 }
 

@@ -31,14 +31,16 @@ class _Problem(C.Structure):
                 ("rho", C.c_void_p), ("shift", C.c_void_p), ("k0", C.c_void_p), ("a", C.c_void_p),
                 ("T", C.c_void_p), ("u", C.c_void_p), ("lambda_", C.c_double), ("x_crit", C.c_double),
                 ("n_src", C.c_int32), ("src_state", C.c_void_p), ("src_pos", C.c_void_p), ("src_x", C.c_void_p),
-                ("src_cdf", C.c_void_p)]
+                ("src_cdf", C.c_void_p), ("k_abs", C.c_void_p), ("k_sca", C.c_void_p), ("src_t", C.c_void_p),
+                ("n_census", C.c_int32), ("census", C.c_void_p)]
 
 
 class _Result(C.Structure):
     _fields_ = [("spectrum", C.c_void_p), ("time_hist", C.c_void_p), ("step_hist", C.c_void_p),
                 ("t_sum", C.c_double), ("t2_sum", C.c_double), ("steps_sum", C.c_double),
                 ("mc_steps_sum", C.c_double), ("steps2_sum", C.c_double), ("escaped", C.c_int64),
-                ("capped", C.c_int64), ("to_mc", C.c_int64), ("to_ddmc", C.c_int64), ("reflected", C.c_int64)]
+                ("capped", C.c_int64), ("to_mc", C.c_int64), ("to_ddmc", C.c_int64), ("reflected", C.c_int64),
+                ("absorbed", C.c_int64), ("e_bin", C.c_void_p), ("e_path", C.c_void_p)]
 
 
 _lib = None
@@ -72,6 +74,9 @@ class Walk1DHResult:
     to_ddmc: int
     reflected: int
     n_packets: int
+    absorbed: int = 0
+    e_bin: np.ndarray = None   # (n_census+1, nc, nb) packets in each state at each census time
+    e_path: np.ndarray = None  # (n_census, nc, nb) residence time per census interval
 
     @property
     def t_mean(self):
@@ -90,9 +95,12 @@ class Walk1DHResult:
         return self.steps2_sum / max(self.n_packets, 1) - self.steps_mean ** 2
 
 
-def run(m, n_packets=None, seed=0, first_id=0, max_steps=(1 << 62), n_threads=None, tabs=None, x_crit=0.0):
-    """Walk ``n_packets`` packets of the 1D medium ``m`` (slab or sphere, pure or hybrid)."""
+def run(m, n_packets=None, seed=0, first_id=0, max_steps=(1 << 62), n_threads=None, tabs=None, x_crit=None):
+    """Walk ``n_packets`` packets of the 1D medium ``m`` (slab or sphere, pure or hybrid); the
+    core-skipping threshold is the medium's unless ``x_crit`` is given."""
     lib = _load()
+    if x_crit is None:
+        x_crit = getattr(m, "x_crit", 0.0)
     assert m.geometry in (tb.SLAB, tb.SPHERE)
     t = tabs if tabs is not None else tb.build(m)
     n = int(m.n_packets if n_packets is None else n_packets)
@@ -106,7 +114,7 @@ def run(m, n_packets=None, seed=0, first_id=0, max_steps=(1 << 62), n_threads=No
     T = np.asarray(m.temp, dtype=np.float64)
     vth = linemath.v_thermal(T)
     vel = np.zeros(t.nc) if m.vel is None else np.asarray(m.vel, dtype=np.float64).reshape(t.nc)
-    st, pos, xs, pr = [], [], [], []
+    st, pos, xs, pr, tw = [], [], [], [], []
     nsrc = len(m.src_x)
     for s in range(nsrc):
         one = m.replace(src_pos=np.asarray(m.src_pos)[s:s + 1], src_x=np.asarray(m.src_x)[s:s + 1])
@@ -115,6 +123,8 @@ def run(m, n_packets=None, seed=0, first_id=0, max_steps=(1 << 62), n_threads=No
             pos.append(float(np.asarray(m.src_pos)[s][0]))
             xs.append(float(np.asarray(m.src_x)[s]))
             pr.append(p / nsrc)
+            if m.src_t is not None:
+                tw.extend(float(v) for v in np.asarray(m.src_t, dtype=np.float64).reshape(nsrc, 2)[s])
     cdf = np.cumsum(pr)
     cdf[-1] = 1.0
     P = _Problem(int(m.geometry), t.nc, t.nb, arr(m.faces[0], np.float64), arr(t.bin_edges, np.float64),
@@ -123,14 +133,23 @@ def run(m, n_packets=None, seed=0, first_id=0, max_steps=(1 << 62), n_threads=No
                  arr(t.nbr, np.int64), arr(t.rho, np.float64), arr(t.shift, np.float64), arr(m.k0, np.float64),
                  arr(linemath.damping(T), np.float64), arr(T, np.float64), arr(vel / vth, np.float64),
                  float(m.lam), float(x_crit), len(st), arr(st, np.int64), arr(pos, np.float64),
-                 arr(xs, np.float64), arr(cdf, np.float64))
+                 arr(xs, np.float64), arr(cdf, np.float64),
+                 arr(m.dust_abs, np.float64) if m.dust_abs is not None else None,
+                 arr(m.dust_sca, np.float64) if m.dust_sca is not None else None,
+                 arr(tw, np.float64) if m.src_t is not None else None,
+                 0 if m.census is None else len(m.census) - 1,
+                 arr(m.census, np.float64) if m.census is not None else None)
     rows = 2 if m.geometry == tb.SLAB else 1
     spec = np.zeros((rows, t.nb + 2), dtype=np.int64)
     th = np.zeros(TIME_BINS + 2, dtype=np.int64)
     sh = np.zeros(STEP_BINS, dtype=np.int64)
-    R = _Result(spec.ctypes.data, th.ctypes.data, sh.ctypes.data, 0.0, 0.0, 0.0, 0.0, 0.0, 0, 0, 0, 0, 0)
+    nce = 0 if m.census is None else len(m.census) - 1
+    e_bin = np.zeros((nce + 1, t.nc, t.nb)) if nce else None
+    e_path = np.zeros((nce, t.nc, t.nb)) if nce else None
+    R = _Result(spec.ctypes.data, th.ctypes.data, sh.ctypes.data, 0.0, 0.0, 0.0, 0.0, 0.0, 0, 0, 0, 0, 0, 0,
+                e_bin.ctypes.data if nce else None, e_path.ctypes.data if nce else None)
     rc = lib.oh_run(C.byref(P), first_id, n, seed, max_steps, n_threads or os.cpu_count() or 1, C.byref(R))
     if rc != 0:
         raise RuntimeError("oh_run failed")
     return Walk1DHResult(spec, th, sh, R.t_sum, R.t2_sum, R.steps_sum, R.mc_steps_sum, R.steps2_sum, R.escaped,
-                         R.capped, R.to_mc, R.to_ddmc, R.reflected, n)
+                         R.capped, R.to_mc, R.to_ddmc, R.reflected, n, R.absorbed, e_bin, e_path)

@@ -62,6 +62,7 @@ typedef struct {
     const double *src_pos;         /* [n_src*3] */
     const double *src_x;           /* [n_src] */
     const double *src_cdf;         /* [n_src] */
+    double x_crit;                 /* core-skipping threshold of the scattering (0 = off) */
 } o3_problem;
 
 typedef struct {
@@ -270,7 +271,7 @@ static void walk_packet(const o3_problem *p, uint64_t id, uint64_t seed, uint64_
         if (ds < dface) {
             for (int d = 0; d < 3; ++d) pos[d] += ds * n[d];
             t += ds;
-            x = scatter(p->a[c], x, n, &r, 0.0);
+            x = scatter(p->a[c], x, n, &r, p->x_crit);
             int jj = locate(p->edges, nb, x);
             if (jj >= 0 && jj < nb && p->thick[c * nb + jj]) { j = jj; mc = 0; R->to_ddmc++; }
             continue;

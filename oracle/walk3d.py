@@ -32,7 +32,7 @@ class _Problem(C.Structure):
                 ("rho", C.c_void_p), ("shift", C.c_void_p), ("k0", C.c_void_p), ("a", C.c_void_p),
                 ("T", C.c_void_p), ("u", C.c_void_p), ("lambda_", C.c_double), ("n_src", C.c_int32),
                 ("src_state", C.c_void_p), ("src_pos", C.c_void_p), ("src_x", C.c_void_p),
-                ("src_cdf", C.c_void_p)]
+                ("src_cdf", C.c_void_p), ("x_crit", C.c_double)]
 
 
 class _Result(C.Structure):
@@ -169,7 +169,7 @@ def run(m, n_packets=None, seed=0, first_id=0, max_steps=(1 << 62), n_threads=No
                  arr(t.rate_dn, np.float64), arr(t.rate_up, np.float64), arr(t.rho, np.float64),
                  arr(t.shift, np.float64), arr(m.k0, np.float64), arr(linemath.damping(T), np.float64),
                  arr(T, np.float64), arr(u, np.float64), float(m.lam), len(st), arr(st, np.int64),
-                 arr(np.array(pos), np.float64), arr(xs, np.float64), arr(cdf, np.float64))
+                 arr(np.array(pos), np.float64), arr(xs, np.float64), arr(cdf, np.float64), float(m.x_crit))
     spec = np.zeros((6, t.nb + 2), dtype=np.int64)
     pix = np.zeros(2 * (ny * nz + nx * nz + nx * ny), dtype=np.int64)
     th = np.zeros(TIME_BINS + 2, dtype=np.int64)

@@ -65,6 +65,12 @@ class Medium:
     lam: float = 0.7104
     flags: int = 0
     name: str = ""
+    x_crit: float = 0.0            # continuous-MC core-skipping threshold (0 = off)
+    dust_abs: Optional[np.ndarray] = None   # per cell dust absorption coefficient [1/length]
+    dust_sca: Optional[np.ndarray] = None   # per cell dust scattering coefficient [1/length]
+    src_t: Optional[np.ndarray] = None      # (n_src, 2) emission windows [t_start, t_end]; None = flash at 0
+    census: Optional[np.ndarray] = None     # census times (n+1 increasing edges) of the energy-density
+                                            # estimators; None = no time-dependent tallies
 
     @property
     def n_bins(self) -> int:

@@ -1,13 +1,14 @@
 """Pins of the 1D hybrid oracle walker (O1-1DH, slabs and spherical shells): pure mode against
 the exact chain, slabs against the independently written 3D walker on slab-shaped boxes
 (all-MC, hybrid, moving, non-uniform), the shell geometry against free-streaming quadratures,
-all-MC spheres against the derived sphere spectrum, and the core-skipping draw against its
-moment identity."""
+all-MC spheres against the derived sphere spectrum, the core-skipping draw against its
+moment identity, the census estimators and emission windows against the exact transient law,
+and dust against the chain's absorption channel and exponential-integral transmission."""
 import math
 
 import numpy as np
 import pytest
-from scipy import integrate
+from scipy import integrate, special
 
 from oracle import analytic as an
 from oracle import chain, linemath, walk1dh, walk3d
@@ -134,3 +135,82 @@ def test_core_skipping_moment_identity(x_crit):
     want = 4.0 / 3.0 * eu2 + (x_crit * x_crit + 1.0) / 3.0
     se = (d ** 2).std() / math.sqrt(n)
     assert abs((d ** 2).mean() - want) < 4 * se, ((d ** 2).mean(), want, se)
+
+
+def _census_checks(m, edges, n, emit=None):
+    """The walker's census counts and residence times against the exact transient law: the bin
+    estimator is a binomial count; the path estimator averages a variable in [0, 1] whose
+    variance is at most its mean."""
+    r = walk1dh.run(m.replace(census=edges), n_packets=n, seed=13)
+    ex = chain.transient(m, edges, emit=emit)
+    p = ex.at_edges.ravel()
+    got = r.e_bin.ravel() / n
+    sig = np.sqrt(np.maximum(p * (1 - p), 1e-300) / n)
+    z = np.abs(got - p) / np.where(p > 0, sig, 1.0)
+    assert np.all(got[p == 0] == 0)
+    assert np.sum(z[p * n >= 10] > 3) <= 2 and z[p * n >= 10].max() < 5, z.max()
+    dt = np.diff(edges)[:, None, None]
+    mean = (r.e_path / (n * dt)).ravel()
+    want = ex.mean_in.ravel()
+    assert np.all(np.abs(mean - want) <= 5 * np.sqrt(np.maximum(want, 1e-30) / n) + 1e-12)
+    return r, ex
+
+
+@pytest.mark.parametrize("m", [media.slab(100.0, 1e4, 4, 6, x_max=4.0),
+                               media.sphere(300.0, 1e4, 5, 8, x_max=5.0, v_max=12.0)], ids=["slab", "sphere_outflow"])
+def test_census_estimators_match_exact_transient_law(m):
+    ref = chain.solve(m)
+    edges = np.array([0.0, 0.2, 0.5, 1.0, 2.0, 4.0]) * ref.t_mean
+    _census_checks(m, edges, 200000)
+
+
+def test_emission_window_census_matches_exact_transient_law():
+    m = media.slab(100.0, 1e4, 4, 6, x_max=4.0)
+    ref = chain.solve(m)
+    ts, te = 0.3 * ref.t_mean, 1.1 * ref.t_mean
+    edges = np.array([0.0, 0.25, 0.5, 1.0, 1.5, 3.0]) * ref.t_mean
+    r, _ = _census_checks(m.replace(src_t=np.array([[ts, te]])), edges, 200000, emit=(ts, te))
+    # escape times are emission time plus the flash law's: their mean shifts by (ts + te) / 2
+    se = math.sqrt(r.t_var / r.escaped)
+    assert abs(r.t_mean - (ref.t_mean + 0.5 * (ts + te))) < 4.5 * se
+
+
+def test_dust_in_ddmc_states_matches_exact_chain():
+    """Dust absorption as a competing exponential in every DDMC step, with dust scattering in
+    the leakage coefficients: escape and absorption fractions and the spectrum of the escaped
+    packets against the chain's absorption channel."""
+    m = media.sphere(400.0, 1e4, 6, 16, x_max=6.0, v_max=10.0)
+    m = m.replace(dust_abs=np.linspace(0.5, 2.0, 6), dust_sca=np.full(6, 3.0))
+    n = 200000
+    r = walk1dh.run(m, n_packets=n, seed=21)
+    ref = chain.solve(m)
+    assert r.escaped + r.absorbed == n
+    pa = ref.absorbed
+    assert abs(r.absorbed / n - pa) < 4 * math.sqrt(pa * (1 - pa) / n)
+    assert_spectrum_matches(compare_exact(r.spectrum.ravel(), ref.spectrum.ravel() / ref.total, r.escaped))
+    assert abs(r.t_mean - ref.t_mean) < 4 * math.sqrt(ref.t_var / r.escaped)
+
+
+@pytest.mark.parametrize("ka,ks", [(0.7, 0.0), (0.0, 0.7), (0.3, 0.4)])
+def test_dust_in_mc_states_against_transmission(ka, ks):
+    """A slab |z| <= 1 of dust only (negligible Lya opacity, every state MC), source at the
+    centre: a packet leaves with no interaction with probability E_2(k_a + k_s) (the
+    exponential integral: isotropic directions through an optical depth k / |mu|), and its
+    first interaction is an absorption with probability k_a / (k_a + k_s), so it takes one
+    event with probability E_2 + (1 - E_2) k_a / (k_a + k_s); with no scattering E_2 is the
+    escape fraction, with no absorption every packet escapes."""
+    m = media.slab(1e-9, 1e4, 1, 8, x_max=4.0, tau_threshold=1e30)
+    m = m.replace(dust_abs=np.array([ka]), dust_sca=np.array([ks]))
+    n = 400000
+    r = walk1dh.run(m, n_packets=n, seed=3)
+    e2 = float(special.expn(2, ka + ks))
+    p1 = e2 + (1.0 - e2) * ka / (ka + ks)
+    one_step = r.step_hist[0] / n
+    assert abs(one_step - p1) <= 4 * math.sqrt(p1 * (1 - p1) / n)
+    if ks == 0.0:
+        assert abs(r.escaped / n - e2) < 4 * math.sqrt(e2 * (1 - e2) / n)
+    if ka == 0.0:
+        assert r.escaped == n
+    assert r.escaped + r.absorbed == n
+    spec = r.spectrum.sum(axis=0)
+    assert spec[1 + 3] + spec[1 + 4] == r.escaped              # dust scattering keeps x = 0
