@@ -180,7 +180,11 @@ static void cell_point(const oh_problem *P, int64_t c, rng_t *r, double p[3])
 }
 
 /* distance along n to the boundary of cell c from p, and the face it reaches */
-static double wall_distance(const oh_problem *P, int64_t c, const double p[3], const double n[3], int *face)
+/* A flight that starts on the cell's inner sphere moving outward cannot meet that sphere again
+ * (a line leaves a ball once): left_inner says so, where the sign of p . n cannot for a grazing
+ * flight. */
+static double wall_distance(const oh_problem *P, int64_t c, const double p[3], const double n[3], int left_inner,
+                            int *face)
 {
     double lo = P->faces[c], hi = P->faces[c + 1];
     if (P->geometry == 0) {
@@ -189,10 +193,13 @@ static double wall_distance(const oh_problem *P, int64_t c, const double p[3], c
         *face = 1;
         return INFINITY;
     }
-    double b = dot(p, n), pp = dot(p, p);
+    double b = dot(p, n);
+    /* the packet is inside its shell: a point put on a face can sit a rounding error outside,
+     * which would turn the far root into a zero-length crossing back and forth */
+    double rr = fmin(fmax(sqrt(dot(p, p)), lo), hi), pp = rr * rr;
     double s_out = -b + sqrt(fmax(0.0, b * b - pp + hi * hi));
     *face = 1;
-    if (lo > 0.0 && b < 0.0) {
+    if (lo > 0.0 && b < 0.0 && !left_inner) {
         double disc = b * b - pp + lo * lo;
         if (disc > 0.0) {
             double s_in = -b - sqrt(disc);
@@ -261,6 +268,7 @@ static void walk_packet(const oh_problem *P, uint64_t id, uint64_t seed, uint64_
     double x = P->src_x[k];
     double t = 0.0;
     if (P->src_t) t = P->src_t[2 * k] + (P->src_t[2 * k + 1] - P->src_t[2 * k]) * ru(&r);
+    int left_inner = 0;
     if (mc) iso_dir(&r, n);
     uint64_t steps = 0, mcsteps = 0;
     for (;;) {
@@ -288,6 +296,7 @@ static void walk_packet(const oh_problem *P, uint64_t id, uint64_t seed, uint64_
                 if (!P->thick[c * nb + j]) {   /* frequency leak into a thin bin */
                     cell_point(P, c, &r, pos);
                     iso_dir(&r, n);
+                    left_inner = 0;
                     x = P->edges[j] + (P->edges[j + 1] - P->edges[j]) * ru(&r);
                     mc = 1;
                     R->to_mc++;
@@ -307,6 +316,7 @@ static void walk_packet(const oh_problem *P, uint64_t id, uint64_t seed, uint64_
                 if (nc < 0) { tally_escape(R, P, f, xin + nu, t); break; }
                 x = (xin + nu) * sqrt(P->T[c] / P->T[nc]) - n_dot_u(P, nc, pos, n);
                 c = nc;
+                left_inner = f == 1;
                 mc = 1;
                 R->to_mc++;
                 continue;
@@ -321,6 +331,7 @@ static void walk_packet(const oh_problem *P, uint64_t id, uint64_t seed, uint64_
             if (!P->thick[c * nb + j]) {   /* re-binned into a thin state */
                 cell_point(P, c, &r, pos);
                 iso_dir(&r, n);
+                left_inner = 0;
                 x = xsh;
                 mc = 1;
                 R->to_mc++;
@@ -330,7 +341,7 @@ static void walk_packet(const oh_problem *P, uint64_t id, uint64_t seed, uint64_
         /* ---- continuous MC ---- */
         ++mcsteps;
         int fexit;
-        double dwall = wall_distance(P, c, pos, n, &fexit);
+        double dwall = wall_distance(P, c, pos, n, left_inner, &fexit);
         double kl = P->k0[c] * mc_voigt(P->a[c], x);
         double ka = P->k_abs ? P->k_abs[c] : 0.0, ks = P->k_sca ? P->k_sca[c] : 0.0;
         double kx = kl + ks + ka;
@@ -345,9 +356,10 @@ static void walk_packet(const oh_problem *P, uint64_t id, uint64_t seed, uint64_
             if (ka > 0.0 || ks > 0.0) {   /* which opacity interacted */
                 double uu2 = ru(&r) * kx;
                 if (uu2 < ka) { R->absorbed++; break; }
-                if (uu2 < ka + ks) { iso_dir(&r, n); continue; }   /* dust: coherent, isotropic */
+                if (uu2 < ka + ks) { iso_dir(&r, n); left_inner = 0; continue; }   /* dust: coherent, isotropic */
             }
             x = scatter(P->a[c], x, n, &r, P->x_crit);
+            left_inner = 0;
             int jj = locate(P->edges, nb, x);
             if (jj >= 0 && jj < nb && P->thick[c * nb + jj]) { j = jj; mc = 0; R->to_ddmc++; }
             continue;
@@ -383,10 +395,12 @@ static void walk_packet(const oh_problem *P, uint64_t id, uint64_t seed, uint64_
             face_normal(P, f, pos, N);
             Nin[0] = -N[0]; Nin[1] = -N[1]; Nin[2] = -N[2];
             hemi_about(&r, Nin, n);
+            left_inner = f == 0;
             R->reflected++;
             continue;
         }
         c = nc;
+        left_inner = f == 1;
         x = xn;
     }
     R->steps_sum += (double)steps;
