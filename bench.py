@@ -50,7 +50,7 @@ PEAK_OPS = 256 * 4 * 16 * 2.4e9
 # Sources of each walk kernel: HBM traffic recorded in a profile counts only while they are
 # unchanged since the counters were taken.
 KERNEL_SOURCES = {
-    "walk3d": ["transport3d.hip", "philox.h", "rddmc_internal.h"],
+    "walk3d": ["transport3d.hip", "mc_dev.h", "philox.h", "rddmc_internal.h"],
     "walk1d": ["transport.hip", "philox.h", "rddmc_internal.h", "surrogate_dev.h", "linemath_dev.h"],
 }
 TRAFFIC_RE = re.compile(r"traffic_bytes_per_launch = ([0-9.eE+]+) \(sources sha256 ([0-9a-f]{64})\)")

@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define RDDMC_ABI_VERSION 3
+#define RDDMC_ABI_VERSION 5
 
 typedef enum {
     RDDMC_OK = 0,
@@ -75,9 +75,10 @@ enum { RDDMC_SLAB = 0, RDDMC_SPHERE = 1, RDDMC_CART3D = 2 };
  *   vel          NULL for a static medium; else per cell: slab v_z, sphere v_r (one value
  *                per cell), Cartesian (vx,vy,vz) (three values per cell) [km/s].
  *   tau_threshold  0 selects pure DDMC (every state diffusive); > 0 (must be >= 2, the
- *                hybrid section's validity bound) makes states with k_ij dz_i below it
- *                continuous Monte Carlo states (walked on RDDMC_CART3D grids; a 1D cloud
- *                with a thin state is refused with RDDMC_EUNSUPPORTED).
+ *                hybrid section's validity bound) makes states with k_ij w_i below it (w_i the
+ *                cell's smallest width) continuous Monte Carlo states.  A 1D batch in which a
+ *                cloud has tau_threshold > 0 or x_crit > 0 is walked by the hybrid 1D walk
+ *                (slab planes or spherical shells); a 1D batch without is the pure walk.
  *   f_mu         Doppler averaging factor of eq. 20 (1/2 for isotropic escape).
  *   lambda       extrapolation distance of the vacuum/thin-face rate (0.7104).
  *   n_src, src_pos, src_x  source positions (3 doubles each: slab z; sphere r; Cartesian
@@ -89,6 +90,27 @@ enum { RDDMC_SLAB = 0, RDDMC_SPHERE = 1, RDDMC_CART3D = 2 };
  *                only, not on its position in a batch.  Give clouds of one batch distinct
  *                keys (the Python binding uses the batch index).
  *   n_packets    packets emitted by this cloud (initial flash, equal weights, t = 0).
+ *   x_crit       core-skipping of the continuous-MC scattering (hybrid section): a photon
+ *                scattered at |x| < x_crit takes the atom's perpendicular speed from the
+ *                Maxwellian's tail above x_crit (its square is x_crit^2 + Exp(1)); 0 = off.
+ *                This biases the result; it is an option for comparisons, not for parity.
+ *   dust_abs, dust_sca  per cell dust absorption k_a and scattering k_s coefficients
+ *                [1/length] (>= 0), or NULL (Sec. 2.4): the leakage coefficients use the total
+ *                scattering coefficient k_ij + k_s, and absorption competes as one more
+ *                exponential distance (rate k_a) in DDMC states; in MC states dust scatters
+ *                isotropically and coherently in the comoving frame, or absorbs.  Absorbed
+ *                packets are counted, not tallied as escapes.  1D clouds only.
+ *   src_t        per source emission window {t_start, t_end} (0 <= t_start <= t_end): packets
+ *                are emitted uniformly in time over it (Sec. 2.3); NULL = a flash at t = 0.
+ *                1D clouds only.
+ *   n_census, census  time-dependent estimators (eq. 17): n_census intervals between
+ *                n_census + 1 increasing times (>= 0).  The tallies then hold, per state, the
+ *                number of packets in it at each census time ('bin' estimator) and the
+ *                residence time in it during each interval, in units of 2^-24 length/c
+ *                ('path' estimator); E_ij,n follows by the packet energy over dV dx (and dt).
+ *                1D clouds only; n_census = 0 and census = NULL for none.
+ * A 1D batch in which any cloud uses x_crit, dust, emission windows or a census is walked by
+ * the hybrid 1D walk.
  */
 typedef struct {
     int32_t geometry;
@@ -108,6 +130,13 @@ typedef struct {
     const double *src_pos;
     const double *src_x;
     uint64_t n_packets;
+    double x_crit;
+    const double *dust_abs;
+    const double *dust_sca;
+    const double *src_t;
+    int32_t n_census;
+    int32_t reserved1;
+    const double *census;
 } rddmc_medium;
 
 /* A batch of independent clouds transported together (one persistent launch). */
@@ -161,14 +190,15 @@ typedef struct {
     double   t_var;          /* variance of the escape time                              */
     int32_t  n_rows;         /* spectrum rows (escape faces): slab 2, sphere 1, 3D 6     */
     int32_t  n_slots;        /* n_bins + 2 (slot 0 below the grid, slot n_bins+1 above) */
-    uint64_t to_mc;          /* hybrid (3D): DDMC -> continuous-MC conversions            */
-    uint64_t to_ddmc;        /* hybrid (3D): continuous-MC -> DDMC conversions            */
-    uint64_t reflected;      /* hybrid (3D): MC packets reflected at a thick interface    */
-    uint64_t mc_steps;       /* hybrid (3D): MC events (scatterings and face crossings),  */
+    uint64_t to_mc;          /* hybrid: DDMC -> continuous-MC conversions                 */
+    uint64_t to_ddmc;        /* hybrid: continuous-MC -> DDMC conversions                 */
+    uint64_t reflected;      /* hybrid: MC packets reflected at a thick interface         */
+    uint64_t mc_steps;       /* hybrid: MC events (scatterings and face crossings),       */
                              /* included in steps_total                                  */
     uint64_t n_pix;          /* 3D: escape pixels 2 (ny nz + nx nz + nx ny); else 0       */
     uint64_t surrogate_calls;/* cell exits drawn from the learned surrogate (each counted  */
                              /* as two steps in steps_total)                             */
+    uint64_t absorbed;       /* packets absorbed by dust                                  */
 } rddmc_cloud_stats;
 
 /*
@@ -181,6 +211,10 @@ typedef struct {
  *                 1 = +x, 2 = -y, 3 = +y, 4 = -z, 5 = +z) a block of the face's cells, blocks
  *                 in face order; x faces index iz*ny + iy, y faces iz*nx + ix, z faces
  *                 iy*nx + ix.
+ *   census_bin[c] (with a census) int64 [(n_census + 1) * n_cells * n_bins]: packets in each
+ *                 state (cell * n_bins + bin) at each census time, time-major.
+ *   census_path[c] (with a census) int64 [n_census * n_cells * n_bins]: residence time in each
+ *                 state during each census interval, units of 2^-24 length/c, interval-major.
  * Any pointer array may be NULL to skip that output.
  */
 typedef struct {
@@ -189,7 +223,11 @@ typedef struct {
     int64_t **step_hist;
     rddmc_cloud_stats *stats;
     int64_t **pixels;
+    int64_t **census_bin;
+    int64_t **census_path;
 } rddmc_tally_out;
+
+#define RDDMC_CENSUS_PATH_FIX 16777216.0   /* residence-time units per length/c (2^24) */
 
 /* ---- queries ------------------------------------------------------------------------- */
 
@@ -225,16 +263,16 @@ rddmc_status rddmc_work_bytes(const rddmc_batch *batch, size_t *bytes);
  *            the first and last bin (reflecting frequency edges);
  * and stores, per state, a 16-byte hot record {ln2/K (f32), high words of the u64
  * categorical thresholds D = P(lower bin) 2^64 and S = (1 - P(spatial)) 2^64, w3} with
- * w3 = high word of F = S + P(face 0) 2^64 on 1D grids, and on 3D grids a flag word (bit 0
- * thick, bit 1+f face f leads into a thin state or vacuum, bits 7 / 8 bin j-1 / j+1 thin);
- * plus cold arrays (low words, the face split, k_ij, Doppler maps), and for 3D the per-cell
- * FP32 record of the continuous-MC step and the FP32 Voigt (H1 of eq. 12) and
- * atom-velocity sampler tables.
+ * w3 = high word of F = S + P(face 0) 2^64 on pure 1D grids, and on 3D grids and hybrid 1D
+ * batches a flag word (bit 0 thick, bit 1+f face f leads into a thin state or vacuum,
+ * bits 7 / 8 bin j-1 / j+1 thin); plus cold arrays (low words, the face split, k_ij, Doppler
+ * maps), and with continuous-MC states the per-cell FP32 record of the MC step and the FP32
+ * Voigt (H1 of eq. 12) and atom-velocity sampler tables.
  *   batch        host description, read during the call.
  *   d_tables     device buffer of >= rddmc_table_bytes bytes, 256-byte aligned.
  *   stream       hipStream_t (NULL = default stream); the call synchronises it.
  * Errors: EINVAL (bad grid or inputs), ESIZE (buffer), ENUMERIC (non-finite table entry),
- * EUNSUPPORTED (mixed geometries in one batch, thin states in a 1D cloud), EHIP.
+ * EUNSUPPORTED (mixed geometries in one batch), EHIP.
  */
 rddmc_status rddmc_build_leakage(const rddmc_batch *batch, void *d_tables, size_t table_bytes,
                                  void *stream);
@@ -242,10 +280,11 @@ rddmc_status rddmc_build_leakage(const rddmc_batch *batch, void *d_tables, size_
 /*
  * rddmc_transport -- the walk of Sec. 2.3 (eqs. 15-16), emission as an initial flash
  * (Sec. 2.3), Doppler re-binning across faces (Sec. 2.5) and removal at the boundary; on
- * 3D grids the hybrid scheme (conversions, eq. 39 acceptance, continuous MC with the
- * Voigt opacity of eq. 12 and the redistribution of eq. 41), one lane per packet drawing
- * its words in order from its own Philox stream; on 1D clouds optionally the learned
- * escape surrogate (run.surrogate).
+ * 3D grids and hybrid 1D batches (slab planes, spherical shells) the hybrid scheme
+ * (conversions, eq. 39 acceptance, continuous MC with the Voigt opacity of eq. 12 and the
+ * redistribution of eq. 41, optional core-skipping), one lane per packet drawing its words
+ * in order from its own Philox stream; on pure 1D clouds optionally the learned escape
+ * surrogate (run.surrogate; EUNSUPPORTED with a hybrid batch).
  * A persistent kernel: every lane carries one packet; every run.chunk steps finished
  * lanes take new packet ids from a work counter.  One Philox4x32-10 block serves two
  * steps; each step takes one 32-bit word for the exponential path length (time advances
@@ -261,7 +300,7 @@ rddmc_status rddmc_build_leakage(const rddmc_batch *batch, void *d_tables, size_
  *   d_work       >= rddmc_work_bytes bytes (a smaller buffer of >= 256 bytes disables the
  *                cooperative tail walk); its counters are cleared by the call (a kernel).
  *   stream       hipStream_t; asynchronous.
- * Errors: EINVAL (run parameters), ESIZE, EHIP.
+ * Errors: EINVAL (run parameters), ESIZE, EUNSUPPORTED (surrogate with a hybrid batch), EHIP.
  */
 rddmc_status rddmc_transport(const rddmc_batch *batch, const void *d_tables, const rddmc_run *run,
                              void *d_tally, size_t tally_bytes, void *d_work, size_t work_bytes,

@@ -7,8 +7,8 @@
 //   build_k    : per state the tophat bin-averaged opacity k_ij (eq. 14);
 //   build_rates: per state the face and frequency leakage rates, packed into the
 //                16-byte hot record and the face-split thresholds;
-//   build_mcell: (3D) per cell the FP32 record of the continuous-MC step;
-// and, once per buffer of a 3D batch, the FP32 Voigt and sampler tables of the MC step.
+//   build_mcell: (3D and 1D hybrid) per cell the FP32 record of the continuous-MC step;
+// and, once per buffer of a batch with MC states, the FP32 Voigt and sampler tables.
 #include <hip/hip_runtime.h>
 
 #include "linemath_dev.h"
@@ -133,7 +133,8 @@ __global__ void build_k(DevCloud c, uint8_t *tb, uint32_t *err)
     const double *e = f64p(tb, c.off_edges);
     const double lo = e[j], hi = e[j + 1];
     const double a = damping_dev(f64p(tb, c.off_T)[cell]);
-    const double k = f64p(tb, c.off_k0)[cell] * hcal_diff_dev(a, lo, hi) / (hi - lo);
+    double k = f64p(tb, c.off_k0)[cell] * hcal_diff_dev(a, lo, hi) / (hi - lo);
+    if (c.dusty) k += f64p(tb, c.off_dust)[2 * cell + 1];   // total scattering: Lya + dust (Sec. 2.4)
     reinterpret_cast<double *>(tb + c.off_k)[s] = k;
     if (!(k > 0.0) || !isfinite(k)) atomicOr(err, (uint32_t)BE_NONFINITE);
 }
@@ -168,10 +169,10 @@ __global__ void build_rates(DevCloud c, uint8_t *tb, uint32_t *err)
     const double lo = e[j], hi = e[j + 1], dx = hi - lo;
     const double ks = kk[s];
     const bool hybrid = c.tau_th > 0.0;
-    const bool cart = c.geometry == RDDMC_CART3D;
+    const bool flagged = c.flag_layout != 0;
     const bool thick = !hybrid || ks * min_width(c, tb, cell) >= c.tau_th;
     if (!thick) {
-        if (!cart) {   // the 1D walk is pure DDMC
+        if (!flagged) {   // the pure 1D walk has no continuous-MC states
             atomicOr(err, (uint32_t)BE_THIN);
             return;
         }
@@ -210,6 +211,7 @@ __global__ void build_rates(DevCloud c, uint8_t *tb, uint32_t *err)
                 const double a_n = damping_dev(T[g.nbr]);
                 const double l2 = rho * lo + sh, h2 = rho * hi + sh;
                 kn = k0[g.nbr] * hcal_diff_dev(a_n, l2, h2) / (h2 - l2);
+                if (c.dusty) kn += f64p(tb, c.off_dust)[2 * g.nbr + 1];
             }
             const FaceGeom gn = face_geom(c, tb, g.nbr, f ^ 1);
             const bool nb_thick = !hybrid || kn * min_width(c, tb, g.nbr) >= c.tau_th;
@@ -229,19 +231,23 @@ __global__ void build_rates(DevCloud c, uint8_t *tb, uint32_t *err)
         const double dxp = e[j + 2] - e[j + 1];
         ru = 1.0 / (dx * (dx / ks + dxp / kk[s + 1]));
     }
-    const double K = rs + rd + ru;
+    const double ka = c.dusty ? f64p(tb, c.off_dust)[2 * cell] : 0.0;   // dust absorption rate
+    const double K = rs + rd + ru + ka;
     if (!(K > 0.0) || !isfinite(K)) atomicOr(err, (uint32_t)BE_NONFINITE);
 
-    // categorical thresholds in units of 2^-64: D = P(lower), S = 1 - P(spatial),
-    // F = S + P(face 0) (the face-0 / face-1 boundary of 1D cells)
+    // categorical thresholds in units of 2^-64: D = P(lower), S = 1 - P(spatial) - P(absorb),
+    // F = S + P(face 0) (the face-0 / face-1 boundary of 1D cells); with dust the spatial
+    // leaks end at A = 1 - P(absorb) and absorption takes [A, 2^64)
     const uint64_t D = prob_to_u64(rd / K);
+    const uint64_t Tab = prob_to_u64(ka / K);
+    const uint64_t A = 0ull - Tab;                  // 2^64 - Tab (0 = no absorption)
     uint64_t Tsp = prob_to_u64(rs / K);
     uint64_t S;
-    if (rs >= K) {
-        S = 0ull;                                   // every leak is spatial (one bin)
+    if (rs + ka >= K) {
+        S = 0ull;                                   // every leak is spatial or an absorption (one bin)
     } else {
         if (Tsp == 0ull) Tsp = 1ull;                // keep the spatial leak reachable
-        S = 0ull - Tsp;                             // 2^64 - Tsp
+        S = 0ull - Tsp - Tab;                       // 2^64 - Tsp - Tab
         if (S < D || ru <= 0.0) S = D;              // no upper move from the last bin, even by rounding
     }
     // face 1 gets [F, 2^64); saturate if rounding leaves it less than nothing
@@ -252,18 +258,18 @@ __global__ void build_rates(DevCloud c, uint8_t *tb, uint32_t *err)
     h.d_hi = (uint32_t)(D >> 32);
     h.s_hi = (uint32_t)(S >> 32);
     uint32_t flags = kFlagThick | (iface << kFlagFaceShift);
-    if (cart && hybrid) {
+    if (flagged && hybrid) {
         const double wmin = min_width(c, tb, cell);
         if (j > 0 && kk[s - 1] * wmin < c.tau_th) flags |= kFlagDnThin;
         if (j < nb - 1 && kk[s + 1] * wmin < c.tau_th) flags |= kFlagUpThin;
     }
-    h.f_hi = cart ? flags : (uint32_t)(F >> 32);
+    h.f_hi = flagged ? flags : (uint32_t)(F >> 32);
     reinterpret_cast<HotRecord *>(tb + c.off_hot)[s] = h;
     uint32_t *lw = reinterpret_cast<uint32_t *>(tb + c.off_lo_words) + 4 * s;
     lw[0] = (uint32_t)D;
     lw[1] = (uint32_t)S;
-    lw[2] = cart ? 0u : (uint32_t)F;
-    lw[3] = 0u;
+    lw[2] = flagged ? (uint32_t)A : (uint32_t)F;
+    lw[3] = flagged ? (uint32_t)(A >> 32) : 0u;
 
     // cumulative face split: thresholds for faces 0 .. nf-2
     uint32_t *fsplit = reinterpret_cast<uint32_t *>(tb + c.off_face_split) + s * (nf - 1);
@@ -280,8 +286,8 @@ __global__ void build_rates(DevCloud c, uint8_t *tb, uint32_t *err)
     }
 }
 
-// Per-cell FP32 record of the continuous-MC step (3D): {k0, a, sqrt(T), w_min} and the bulk
-// velocity in units of the cell's own thermal speed.
+// Per-cell FP32 record of the continuous-MC step: {k0, a, sqrt(T), w_min} and the bulk
+// velocity in units of the cell's own thermal speed (1D: its component along +z or +r).
 __global__ void build_mcell(DevCloud c, uint8_t *tb)
 {
     const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -292,9 +298,15 @@ __global__ void build_mcell(DevCloud c, uint8_t *tb)
     mc[0] = make_float4((float)f64p(tb, c.off_k0)[cell], (float)damping_dev(T), (float)sqrt(T),
                         (float)min_width(c, tb, cell));
     float4 u = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (c.moving) {
+    if (c.moving && c.geometry == RDDMC_CART3D) {
         const double *v = f64p(tb, c.off_vel) + 3 * cell;
         u = make_float4((float)(v[0] / vth), (float)(v[1] / vth), (float)(v[2] / vth), 0.f);
+    } else if (c.moving) {
+        u.x = (float)(f64p(tb, c.off_vel)[cell] / vth);
+    }
+    if (c.dusty) {   // 1D: dust scattering and absorption coefficients of the MC flight
+        u.y = (float)f64p(tb, c.off_dust)[2 * cell + 1];
+        u.z = (float)f64p(tb, c.off_dust)[2 * cell];
     }
     mc[1] = u;
 }
@@ -358,7 +370,7 @@ hipError_t launch_build(const DevCloud &c, int cloud_index, uint8_t *d_tables, h
     const unsigned g = (unsigned)((ns + bs - 1) / bs);
     build_k<<<g, bs, 0, s>>>(c, d_tables, err);
     build_rates<<<g, bs, 0, s>>>(c, d_tables, err);
-    if (c.geometry == RDDMC_CART3D)
+    if (c.off_mcell)
         build_mcell<<<(unsigned)((c.nc + bs - 1) / bs), bs, 0, s>>>(c, d_tables);
     return hipGetLastError();
 }

@@ -87,6 +87,7 @@ struct Layout {
     std::vector<std::vector<int32_t>> src_state;
     std::vector<std::vector<double>> src_cdf;
     std::vector<std::vector<float>> src_pos;     // 3D: {x, y, z, frequency} per emission entry
+    std::vector<std::vector<double>> src_t;      // hybrid 1D: emission window per entry
     uint64_t table_bytes = 0;
     uint64_t tally_words = 0;
     bool any_moving = false;
@@ -128,6 +129,27 @@ rddmc_status validate_cloud(const rddmc_medium &m, int idx)
     if (!(m.lambda > 0.0) || !std::isfinite(m.lambda)) return fail(RDDMC_EINVAL, "cloud %d: lambda <= 0", idx);
     if (m.n_src < 1 || !m.src_pos || !m.src_x) return fail(RDDMC_EINVAL, "cloud %d: no sources", idx);
     if (m.n_packets >= (1ull << 32)) return fail(RDDMC_EINVAL, "cloud %d: n_packets >= 2^32", idx);
+    if (!(m.x_crit >= 0.0) || !std::isfinite(m.x_crit))
+        return fail(RDDMC_EINVAL, "cloud %d: x_crit must be finite and >= 0", idx);
+    for (const double *d : {m.dust_abs, m.dust_sca})
+        if (d)
+            for (int64_t c = 0; c < nc; ++c)
+                if (!(d[c] >= 0.0) || !std::isfinite(d[c]))
+                    return fail(RDDMC_EINVAL, "cloud %d: dust coefficients must be finite and >= 0", idx);
+    if (m.src_t)
+        for (int s = 0; s < m.n_src; ++s) {
+            const double a = m.src_t[2 * s], b = m.src_t[2 * s + 1];
+            if (!(a >= 0.0) || !(b >= a) || !std::isfinite(b))
+                return fail(RDDMC_EINVAL, "cloud %d: emission window %d must satisfy 0 <= t_start <= t_end", idx, s);
+        }
+    if (m.n_census < 0 || m.n_census > 4096 || (m.n_census > 0) != (m.census != nullptr))
+        return fail(RDDMC_EINVAL, "cloud %d: n_census in [0, 4096] with census given iff n_census > 0", idx);
+    if (m.n_census > 0 && (!finite_all(m.census, m.n_census + 1) || !increasing(m.census, m.n_census + 1) ||
+                           m.census[0] < 0.0))
+        return fail(RDDMC_EINVAL, "cloud %d: census times must be finite, >= 0 and increasing", idx);
+    const bool extras = m.dust_abs || m.dust_sca || m.src_t || m.n_census > 0;
+    if (extras && m.geometry == RDDMC_CART3D)
+        return fail(RDDMC_EUNSUPPORTED, "cloud %d: dust, emission windows and census tallies are for 1D clouds", idx);
     return RDDMC_OK;
 }
 
@@ -140,16 +162,28 @@ rddmc_status make_layout(const rddmc_batch *b, Layout &L)
     L.src_state.assign(n, {});
     L.src_cdf.assign(n, {});
     L.src_pos.assign(n, {});
+    L.src_t.assign(n, {});
     const int geom = b->clouds[0].geometry;
+    // a 1D batch with a continuous-MC option (tau_threshold > 0 or core-skipping) is walked by
+    // the hybrid 1D walk: flag layout, MC cell records and line tables for every cloud
+    bool hybrid1d = false;
+    if (geom != RDDMC_CART3D)
+        for (int ci = 0; ci < n; ++ci) {
+            const rddmc_medium &m = b->clouds[ci];
+            hybrid1d |= m.tau_threshold > 0.0 || m.x_crit > 0.0 || m.dust_abs || m.dust_sca || m.src_t ||
+                        m.n_census > 0;
+        }
+    const bool flagged = geom == RDDMC_CART3D || hybrid1d;
     uint64_t off = 0;
     L.h.n_clouds = n;
     L.h.geometry = geom;
+    L.h.hybrid1d = hybrid1d ? 1u : 0u;
     off = align_up(sizeof(DevHeader));
     L.h.off_clouds = off;
     off = align_up(off + sizeof(DevCloud) * n);
     L.h.off_prefix = off;
     off = align_up(off + sizeof(uint64_t) * (n + 1));
-    if (geom == RDDMC_CART3D) {   // FP32 line tables of the continuous-MC step
+    if (flagged) {   // FP32 line tables of the continuous-MC step
         L.h.off_voigt = off;
         off = align_up(off + 4ull * kVoigtN);
         L.h.off_u0 = off;
@@ -197,6 +231,10 @@ rddmc_status make_layout(const rddmc_batch *b, Layout &L)
         }
         c.f_mu = m.f_mu;
         c.lambda = m.lambda;
+        c.flag_layout = flagged ? 1 : 0;
+        c.x_crit = (float)m.x_crit;
+        c.dusty = (m.dust_abs || m.dust_sca) ? 1 : 0;
+        c.n_census = m.n_census;
         // sources -> (state, probability); 3D keeps one entry per (source, state) with the
         // source's position and frequency (a packet starting in a thin state needs them)
         std::map<int32_t, double> acc;
@@ -208,10 +246,25 @@ rddmc_status make_layout(const rddmc_batch *b, Layout &L)
             const double *p = m.src_pos + 3 * s;
             if (!split_coord(m.faces[0], m.n_cells[0], p[0], cx))
                 return fail(RDDMC_EINVAL, "cloud %d: source %d outside the grid", ci, s);
-            if (m.geometry != RDDMC_CART3D) {
+            if (m.geometry != RDDMC_CART3D && !hybrid1d) {
                 for (auto &a : cx)
                     for (auto &bb : bins)
                         acc[a.first * m.n_bins + bb.first] += a.second * bb.second / m.n_src;
+                continue;
+            }
+            if (m.geometry != RDDMC_CART3D) {   // hybrid 1D: one entry per (source, state)
+                for (auto &a : cx)
+                    for (auto &bb : bins) {
+                        cum3 += a.second * bb.second / m.n_src;
+                        L.src_state[ci].push_back((int32_t)(a.first * m.n_bins + bb.first));
+                        L.src_cdf[ci].push_back(cum3);
+                        L.src_pos[ci].push_back(0.0f);
+                        L.src_pos[ci].push_back(0.0f);
+                        L.src_pos[ci].push_back((float)p[0]);
+                        L.src_pos[ci].push_back((float)m.src_x[s]);
+                        L.src_t[ci].push_back(m.src_t ? m.src_t[2 * s] : 0.0);
+                        L.src_t[ci].push_back(m.src_t ? m.src_t[2 * s + 1] : 0.0);
+                    }
                 continue;
             }
             if (!split_coord(m.faces[1], m.n_cells[1], p[1], cy) || !split_coord(m.faces[2], m.n_cells[2], p[2], cz))
@@ -230,7 +283,7 @@ rddmc_status make_layout(const rddmc_batch *b, Layout &L)
                             L.src_pos[ci].push_back((float)m.src_x[s]);
                         }
         }
-        if (m.geometry != RDDMC_CART3D) {
+        if (m.geometry != RDDMC_CART3D && !hybrid1d) {
             double cum = 0.0;
             for (auto &kv : acc) {
                 cum += kv.second;
@@ -261,13 +314,21 @@ rddmc_status make_layout(const rddmc_batch *b, Layout &L)
         c.off_rates = c.keep_rates ? take(8ull * c.n_states * (c.nf + 2)) : 0;
         c.off_map = take(8ull * 3 * c.nc * c.nf);
         c.off_cmap = take(16ull * c.nc);
-        c.off_mcell = m.geometry == RDDMC_CART3D ? take(32ull * c.nc) : 0;
+        c.off_mcell = flagged ? take(32ull * c.nc) : 0;
+        c.off_dust = c.dusty ? take(16ull * c.nc) : 0;
+        c.off_src_t = hybrid1d ? take(16ull * c.n_src) : 0;
+        c.off_census = c.n_census > 0 ? take(8ull * (c.n_census + 1)) : 0;
         c.n_pix = m.geometry == RDDMC_CART3D
                       ? 2ull * ((uint64_t)c.n[1] * c.n[2] + (uint64_t)c.n[0] * c.n[2] + (uint64_t)c.n[0] * c.n[1])
                       : 0;
         c.tally_off = tally;
         c.tally_words = kTallyHeader + (uint64_t)c.n_rows * (c.nb + 2) + (RDDMC_TIME_BINS + 2) + RDDMC_STEP_BINS +
                         c.n_pix;
+        if (c.n_census > 0) {
+            c.census_bin_off = c.tally_words;
+            c.census_path_off = c.census_bin_off + (uint64_t)(c.n_census + 1) * c.n_states;
+            c.tally_words = c.census_path_off + (uint64_t)c.n_census * c.n_states;
+        }
         tally += c.tally_words;
     }
     L.h.total_packets = L.prefix[n];
@@ -383,6 +444,7 @@ rddmc_status rddmc_build_leakage(const rddmc_batch *batch, void *d_tables, size_
         const rddmc_medium &m = batch->clouds[ci];
         const DevCloud &c = L.clouds[ci];
         const uint64_t a = c.off_edges, z = c.off_src_pos + 16ull * c.n_src;
+        // regions after the input block, staged separately
         bufs.emplace_back(z - a, 0);
         auto &buf = bufs.back();
         put(buf, c.off_edges - a, m.bin_edges, 8ull * (c.nb + 1));
@@ -399,10 +461,37 @@ rddmc_status rddmc_build_leakage(const rddmc_batch *batch, void *d_tables, size_
         if (m.vel) put(buf, c.off_vel - a, m.vel, 8ull * c.nc * (c.geometry == RDDMC_CART3D ? 3 : 1));
         put(buf, c.off_src_state - a, L.src_state[ci].data(), 4ull * c.n_src);
         put(buf, c.off_src_cdf - a, L.src_cdf[ci].data(), 8ull * c.n_src);
-        if (c.geometry == RDDMC_CART3D) put(buf, c.off_src_pos - a, L.src_pos[ci].data(), 16ull * c.n_src);
+        if (c.flag_layout) put(buf, c.off_src_pos - a, L.src_pos[ci].data(), 16ull * c.n_src);
         if ((e = hipMemcpyAsync(static_cast<uint8_t *>(d_tables) + a, buf.data(), z - a, hipMemcpyHostToDevice,
                                 s)) != hipSuccess)
             return hip_fail(e, "hipMemcpyAsync(inputs)");
+        // dust coefficients, emission windows and census times (small per-cloud arrays)
+        if (c.off_dust) {
+            bufs.emplace_back(16ull * c.nc, 0);
+            auto &d = bufs.back();
+            for (int64_t i = 0; i < c.nc; ++i) {
+                const double ka = m.dust_abs ? m.dust_abs[i] : 0.0, ks = m.dust_sca ? m.dust_sca[i] : 0.0;
+                put(d, 16ull * i, &ka, 8);
+                put(d, 16ull * i + 8, &ks, 8);
+            }
+            if ((e = hipMemcpyAsync(static_cast<uint8_t *>(d_tables) + c.off_dust, d.data(), d.size(),
+                                    hipMemcpyHostToDevice, s)) != hipSuccess)
+                return hip_fail(e, "hipMemcpyAsync(dust)");
+        }
+        if (c.off_src_t) {
+            bufs.emplace_back(16ull * c.n_src, 0);
+            put(bufs.back(), 0, L.src_t[ci].data(), 16ull * c.n_src);
+            if ((e = hipMemcpyAsync(static_cast<uint8_t *>(d_tables) + c.off_src_t, bufs.back().data(),
+                                    16ull * c.n_src, hipMemcpyHostToDevice, s)) != hipSuccess)
+                return hip_fail(e, "hipMemcpyAsync(emission windows)");
+        }
+        if (c.off_census) {
+            bufs.emplace_back(8ull * (c.n_census + 1), 0);
+            put(bufs.back(), 0, m.census, 8ull * (c.n_census + 1));
+            if ((e = hipMemcpyAsync(static_cast<uint8_t *>(d_tables) + c.off_census, bufs.back().data(),
+                                    8ull * (c.n_census + 1), hipMemcpyHostToDevice, s)) != hipSuccess)
+                return hip_fail(e, "hipMemcpyAsync(census)");
+        }
     }
     for (int ci = 0; ci < L.h.n_clouds; ++ci)
         if ((e = launch_build(L.clouds[ci], ci, static_cast<uint8_t *>(d_tables), s)) != hipSuccess)
@@ -415,10 +504,7 @@ rddmc_status rddmc_build_leakage(const rddmc_batch *batch, void *d_tables, size_
         return hip_fail(e, "hipMemcpyAsync(flags)");
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
     if (flags & BE_NONFINITE) return fail(RDDMC_ENUMERIC, "a leakage table entry is non-finite or non-positive");
-    if (flags & BE_THIN)
-        return fail(RDDMC_EUNSUPPORTED,
-                    "thin (continuous Monte Carlo) states are walked on 3D Cartesian grids only; 1D geometries "
-                    "need tau_threshold = 0 or every state thick");
+    if (flags & BE_THIN) return fail(RDDMC_ENUMERIC, "a thin state in a cloud without continuous-MC states");
     return RDDMC_OK;
 }
 
@@ -457,6 +543,14 @@ rddmc_status rddmc_transport(const rddmc_batch *batch, const void *d_tables, con
                                      static_cast<unsigned long long *>(d_tally),
                                      static_cast<unsigned long long *>(d_work), reinterpret_cast<hipStream_t>(stream));
         return e == hipSuccess ? RDDMC_OK : hip_fail(e, "3D walk kernel");
+    }
+    if (L.h.hybrid1d) {
+        if (run->surrogate)
+            return fail(RDDMC_EUNSUPPORTED, "the escape surrogate runs with pure-DDMC 1D batches only");
+        hipError_t e = launch_walk1dh(static_cast<const uint8_t *>(d_tables), L.h, *run, run->first, count,
+                                      static_cast<unsigned long long *>(d_tally),
+                                      static_cast<unsigned long long *>(d_work), reinterpret_cast<hipStream_t>(stream));
+        return e == hipSuccess ? RDDMC_OK : hip_fail(e, "1D hybrid walk kernel");
     }
     hipError_t e = launch_walk(static_cast<const uint8_t *>(d_tables), L.h, L.clouds.data(), *run, run->first,
                                count, static_cast<unsigned long long *>(d_tally),
@@ -512,8 +606,13 @@ rddmc_status rddmc_tally(const rddmc_batch *batch, const void *d_tally, size_t t
             z.reflected = w[TW_REFLECTED];
             z.mc_steps = w[TW_MC_STEPS];
             z.surrogate_calls = w[TW_SURR_CALLS];
+            z.absorbed = w[TW_ABSORBED];
             z.n_pix = c.n_pix;
         }
+        if (c.n_census > 0 && out->census_bin && out->census_bin[ci])
+            std::memcpy(out->census_bin[ci], w + c.census_bin_off, 8ull * (c.n_census + 1) * c.n_states);
+        if (c.n_census > 0 && out->census_path && out->census_path[ci])
+            std::memcpy(out->census_path[ci], w + c.census_path_off, 8ull * c.n_census * c.n_states);
     }
     return RDDMC_OK;
 }
@@ -631,6 +730,7 @@ rddmc_status surrogate_layout(const rddmc_batch *b, const rddmc_surrogate_cfg *c
     Layout L;
     rddmc_status st = make_layout(b, L);
     if (st != RDDMC_OK) return st;
+    if (L.h.hybrid1d) return fail(RDDMC_EUNSUPPORTED, "the escape surrogate runs with pure-DDMC 1D batches only");
     const int n = b->n_clouds;
     S.clouds.resize(n);
     uint64_t rec = 0;
@@ -731,7 +831,8 @@ rddmc_status rddmc_surrogate_samples(const rddmc_batch *batch, const void *d_tab
     if (n < 1) return fail(RDDMC_EINVAL, "n < 1");
     if (scratch_bytes < 8ull * (uint64_t)n) return fail(RDDMC_ESIZE, "scratch needs 8 n bytes");
     if (max_steps < 1) return fail(RDDMC_EINVAL, "max_steps must be >= 1");
-    if (L.h.geometry == RDDMC_CART3D) return fail(RDDMC_EUNSUPPORTED, "sub-walk data is built for 1D clouds");
+    if (L.h.geometry == RDDMC_CART3D || L.h.hybrid1d)
+        return fail(RDDMC_EUNSUPPORTED, "sub-walk data is built for pure-DDMC 1D clouds");
     bool moving = false;
     for (int64_t q = 0; q < n; ++q) {
         const int c = h_cloud[q];

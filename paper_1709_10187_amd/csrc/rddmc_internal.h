@@ -27,6 +27,7 @@ enum TallyWord {
     TW_REFLECTED = 10,//         MC packets reflected at a thick interface
     TW_MC_STEPS = 11, //         MC events (scatterings and face crossings)
     TW_SURR_CALLS = 12, // exits drawn from the learned surrogate
+    TW_ABSORBED = 13,   // packets absorbed by dust
 };
 
 // 3D cells: the fourth word of the hot record holds flags instead of F.
@@ -83,15 +84,28 @@ struct alignas(16) DevCloud {
     uint64_t off_rates;          // f64 [n_states * (nf+2)]  (only with keep_rates)
     uint64_t off_map;            // f64 [nc * nf * 3]: rho, shift, u_n per (cell, face)
     uint64_t off_cmap;           // f32x4 [nc] (1D): rho and shift of face 0, then of face 1
-    uint64_t off_src_pos;        // f32x4 [n_src] (3D): source position and frequency
-    uint64_t off_mcell;          // f32x4 [2 nc] (3D): {k0, a, sqrt(T), w_min}, {u_x, u_y, u_z, 0}
+    uint64_t off_src_pos;        // f32x4 [n_src] (flag layout): source position (1D: {0, 0, z or r}) and frequency
+    uint64_t off_mcell;          // f32x4 [2 nc] (flag layout): {k0, a, sqrt(T), w_min}, {u_x, u_y, u_z, 0}
+                                 // (1D: u along +z or +r in the first component)
     uint64_t tally_off;          // int64 word offset of this cloud's tally block
     uint64_t tally_words;
     uint64_t n_pix;              // 3D: escape pixels 2 (ny nz + nx nz + nx ny), after the step histogram
     double tau_th, f_mu, lambda;
     float x0, dx, inv_dx;        // uniform bin grid: first edge, width, 1/width
     int32_t uniform_bins;        // 1 when every bin has the same width
+    int32_t flag_layout;         // hot records carry flags and the face split lives in its own
+                                 // array (3D grids and 1D hybrid batches); else w3 = F (1D pure)
+    float x_crit;                // MC core-skipping threshold (0 = off)
+    int32_t dusty;               // dust coefficients present (absorption threshold in lo_words[2..3])
+    int32_t n_census;            // census intervals of the time-dependent estimators (0 = none)
+    uint64_t off_dust;           // f64 [2 nc]: k_a, k_s per cell (dusty clouds)
+    uint64_t off_src_t;          // f64 [2 n_src]: emission window per source entry (0 = flash)
+    uint64_t off_census;         // f64 [n_census + 1] census times
+    uint64_t census_bin_off;     // int64 word offsets (in the cloud's tally block) of the 'bin'
+    uint64_t census_path_off;    //   counts [(n_census+1) n_states] and 'path' times [n_census n_states]
 };
+
+constexpr double kPathFix = RDDMC_CENSUS_PATH_FIX;   // residence-time fixed point (2^24 per length/c)
 
 struct alignas(16) DevHeader {
     int32_t n_clouds;
@@ -100,7 +114,7 @@ struct alignas(16) DevHeader {
     uint64_t off_clouds;         // DevCloud [n_clouds]
     uint64_t off_prefix;         // u64 [n_clouds+1] flattened packet prefix
     uint32_t error_flags;        // set by the build kernels (see BuildError)
-    uint32_t pad;
+    uint32_t hybrid1d;           // 1D batch walked by the hybrid 1D walk (flag layout, MC tables)
     uint64_t off_voigt;          // f32 [kVoigtN] (3D batches)
     uint64_t off_u0;             // f32 [kU0NA * kU0NX] (3D batches)
 };
@@ -138,6 +152,8 @@ const float *mdn_outputs(void *d_work, int64_t cap);
 hipError_t launch_build_line_tables(const DevHeader &h, uint8_t *d_tables, hipStream_t s);
 hipError_t launch_walk3d(const uint8_t *d_tables, const DevHeader &h, const rddmc_run &run, uint64_t first,
                          uint64_t count, unsigned long long *d_tally, unsigned long long *d_work, hipStream_t s);
+hipError_t launch_walk1dh(const uint8_t *d_tables, const DevHeader &h, const rddmc_run &run, uint64_t first,
+                          uint64_t count, unsigned long long *d_tally, unsigned long long *d_work, hipStream_t s);
 hipError_t launch_philox_fill(uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1, uint32_t c2,
                               uint32_t c3, uint64_t n, uint32_t *d_out, hipStream_t s);
 int device_cu_count();

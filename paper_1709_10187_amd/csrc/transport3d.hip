@@ -21,7 +21,8 @@
 //     opacity k0 H(a, x); a scattering draws the atom's parallel velocity from
 //     exp(-u^2) / (a^2 + (x - u)^2) by rejection from a Lorentzian split at u0 (the method of
 //     Zheng & Miralda-Escude 2002; any u0 >= 0 is exact, a table holds the one minimising
-//     the proposal mass), the perpendicular one from N(0, 1/2), an isotropic new direction
+//     the proposal mass), the perpendicular one from N(0, 1/2) (with core-skipping on, from
+//     its tail above x_crit for photons in the core), an isotropic new direction
 //     and x' = x + u_par (mu - 1) + u_perp sqrt(1 - mu^2) (eq. 41, no recoil); if (cell,
 //     bin(x')) is thick the packet becomes DDMC there.  At a wall: vacuum -> escape with the
 //     lab frequency x + n.u; a thick neighbour state accepts the packet with probability
@@ -30,6 +31,7 @@
 // Escapes add face, lab bin, boundary pixel and time to the exact int64 tallies.
 #include <hip/hip_runtime.h>
 
+#include "mc_dev.h"
 #include "philox.h"
 #include "rddmc_internal.h"
 
@@ -38,64 +40,9 @@ namespace rddmc {
 namespace {
 
 constexpr uint32_t kDom3D = 0x40000000u;        // counter domain of the 3D walk's streams
-constexpr float kPi = 3.14159265358979f;
-constexpr float kHalfPi = 1.57079632679490f;
-constexpr float kTwoPi = 6.28318530717959f;
-constexpr int kUparMaxTries = 1 << 20;          // the sampler's acceptance is >= ~1e-3
 
-struct Walk3Args {
-    uint64_t first, count, max_steps;
-    uint32_t key0, key1;
-    int32_t chunk, n_clouds;
-};
-
-// Per-packet stream: block b is Philox4x32-10 of counter (b_lo, kDom3D | b_hi, packet id,
-// cloud key) under the run's seed; its four words are used in order, each once.
-struct Rng {
-    uint32_t w0, w1, w2, w3;
-    uint32_t avail;
-    uint32_t ctr, ctr_hi;
-    uint32_t pid, key;
-};
-
-__device__ __forceinline__ uint32_t draw(Rng &r, const Walk3Args &a)
-{
-    if (r.avail == 0u) {
-        const u32x4 b = philox4x32_10(r.ctr, kDom3D | r.ctr_hi, r.pid, r.key, a.key0, a.key1);
-        r.w0 = b.x;
-        r.w1 = b.y;
-        r.w2 = b.z;
-        r.w3 = b.w;
-        r.avail = 4u;
-        if (++r.ctr == 0u) ++r.ctr_hi;
-    }
-    const uint32_t v = r.w0;
-    r.w0 = r.w1;
-    r.w1 = r.w2;
-    r.w2 = r.w3;
-    --r.avail;
-    return v;
-}
-
-// 24-bit uniform in (0, 1) (exactly representable, never 0 or 1)
-__device__ __forceinline__ float uf(uint32_t w) { return ((float)(w >> 8) + 0.5f) * 5.9604644775390625e-8f; }
-__device__ __forceinline__ double ud(uint32_t w) { return ((double)w + 0.5) * 2.3283064365386962890625e-10; }
-
-__device__ __forceinline__ float ddmc_path(uint32_t tw, float ln2_over_K)
-{   // -ln(xi) / K with xi = (tw + 1/2) 2^-32, as -log2(xi) ln2/K
-    const float xi = __fmul_rn(__fadd_rn((float)tw, 0.5f), 2.3283064365386963e-10f);
-    return __fmul_rn(-__log2f(xi), ln2_over_K);
-}
-
-__device__ __forceinline__ float comp(float3 v, int d) { return d == 0 ? v.x : (d == 1 ? v.y : v.z); }
-__device__ __forceinline__ int compi(int a, int b, int c, int d) { return d == 0 ? a : (d == 1 ? b : c); }
-__device__ __forceinline__ void setc(float3 &v, int d, float s)
-{
-    v.x = d == 0 ? s : v.x;
-    v.y = d == 1 ? s : v.y;
-    v.z = d == 2 ? s : v.z;
-}
-__device__ __forceinline__ float dot3(float3 a, float4 b) { return fmaf(a.x, b.x, fmaf(a.y, b.y, a.z * b.z)); }
+using namespace mc;
+using Walk3Args = McArgs;
 
 struct Pk {
     int cl;
@@ -110,121 +57,6 @@ struct Pk {
     uint32_t mcs, tomc, toddmc, refl;
     Rng r;
 };
-
-__device__ __forceinline__ const double *faces_of(const DevCloud &c, const uint8_t *tb, int d)
-{
-    const uint64_t o = d == 0 ? c.off_faces[0] : (d == 1 ? c.off_faces[1] : c.off_faces[2]);
-    return reinterpret_cast<const double *>(tb + o);
-}
-
-// lab-frame bin of frequency x: -1 below the grid, nb at or above its top edge
-__device__ __forceinline__ int bin_of(const DevCloud &c, const uint8_t *tb, float x)
-{
-    if (c.uniform_bins) {
-        const float f = (x - c.x0) * c.inv_dx;
-        if (!(f >= 0.0f)) return -1;
-        if (f >= (float)c.nb) return c.nb;
-        const int j = (int)f;
-        return j < c.nb - 1 ? j : c.nb - 1;
-    }
-    const double *e = reinterpret_cast<const double *>(tb + c.off_edges);
-    const double xd = (double)x;
-    if (xd < e[0]) return -1;
-    if (xd >= e[c.nb]) return c.nb;
-    int lo = 0, hi = c.nb;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (xd >= e[mid]) lo = mid; else hi = mid;
-    }
-    return lo;
-}
-
-// x uniform in bin j
-__device__ __forceinline__ float bin_x(const DevCloud &c, const uint8_t *tb, int j, float u)
-{
-    if (c.uniform_bins) return fmaf((float)j + u, c.dx, c.x0);
-    const double *e = reinterpret_cast<const double *>(tb + c.off_edges);
-    return (float)(e[j] + (e[j + 1] - e[j]) * (double)u);
-}
-
-// H(a, x) of eq. 12 in FP32: exp(-x^2)(1 + a^2 (1 - 2 x^2)) + a H1(|x|), H1 from the table
-// below |x| = 16 and from its asymptotic series (1/sqrt(pi)) (1/x^2 + 3/(2x^4) + 15/(4x^6)
-// + 105/(8x^8)) above.
-__device__ __forceinline__ float voigt_f32(float a, float x, const float *__restrict__ tab)
-{
-    const float ax = fabsf(x);
-    const float x2 = ax * ax;
-    float h1;
-    if (ax < 16.0f) {
-        const float f = ax * kVoigtScale;
-        int i = (int)f;
-        i = i < kVoigtN - 2 ? i : kVoigtN - 2;
-        const float fr = f - (float)i;
-        const float t0 = tab[i], t1 = tab[i + 1];
-        h1 = fmaf(fr, t1 - t0, t0);
-    } else {
-        const float q = 1.0f / x2;
-        h1 = 0.564189583547756f * q * fmaf(q, fmaf(q, fmaf(q, 13.125f, 3.75f), 1.5f), 1.0f);
-    }
-    const float e = __expf(-x2);
-    return fmaf(a, h1, e * fmaf(a * a, 1.0f - 2.0f * x2, 1.0f));
-}
-
-// bilinear split point u0(a, |x|) (clamped to the table; every u0 >= 0 is exact)
-__device__ __forceinline__ float u0_of(float a, float ax, const float *__restrict__ tab)
-{
-    float fa = (__log10f(a) + 6.0f) * kU0Scale;
-    fa = fminf(fmaxf(fa, 0.0f), (float)(kU0NA - 1));
-    const float fx = fminf(ax * kU0Scale, (float)(kU0NX - 1));
-    int ia = (int)fa, ix = (int)fx;
-    ia = ia < kU0NA - 2 ? ia : kU0NA - 2;
-    ix = ix < kU0NX - 2 ? ix : kU0NX - 2;
-    const float ta = fa - (float)ia, tx = fx - (float)ix;
-    const float *r0 = tab + ia * kU0NX + ix;
-    const float *r1 = r0 + kU0NX;
-    const float v0 = fmaf(tx, r0[1] - r0[0], r0[0]);
-    const float v1 = fmaf(tx, r1[1] - r1[0], r1[0]);
-    return fmaxf(fmaf(ta, v1 - v0, v0), 0.0f);
-}
-
-// Atom velocity along the photon direction, density ~ exp(-u^2) / (a^2 + (x - u)^2).
-// Lorentzian proposals centred on |x| written as u = |x| - a cot(phi), phi uniform: below
-// u0 (phi in (0, phi0)) accepted with exp(-u^2), above (phi in (phi0, pi)) with
-// exp(u0^2 - u^2); the branch is chosen by its proposal mass.  Returns false if no
-// proposal was accepted within the try limit.
-__device__ bool sample_upar(float a, float x, const float *__restrict__ u0tab, Rng &r, const Walk3Args &A,
-                            float &out)
-{
-    const float ax = fabsf(x);
-    const float u0 = u0_of(a, ax, u0tab);
-    const float phi0 = kHalfPi + atanf((u0 - ax) / a);
-    const float e0 = __expf(-u0 * u0);
-    const float pl = phi0 / fmaf(e0, kPi - phi0, phi0);
-    for (int it = 0; it < kUparMaxTries; ++it) {
-        const float r1 = uf(draw(r, A)), r2 = uf(draw(r, A)), r3 = uf(draw(r, A));
-        const bool below = r1 <= pl;
-        const float phi = below ? r2 * phi0 : fmaf(r2, kPi - phi0, phi0);
-        float sn, cs;
-        sincosf(phi, &sn, &cs);
-        const float uu = ax - a * (cs / sn);
-        const float acc = below ? __expf(-uu * uu) : __expf(u0 * u0 - uu * uu);
-        if (r3 <= acc) {
-            out = x < 0.0f ? -uu : uu;
-            return true;
-        }
-    }
-    return false;
-}
-
-__device__ __forceinline__ float3 iso_dir(Rng &r, const Walk3Args &a)
-{
-    const float mu = fmaf(2.0f, uf(draw(r, a)), -1.0f);
-    const float ph = kTwoPi * uf(draw(r, a));
-    const float s = sqrtf(fmaxf(0.0f, 1.0f - mu * mu));
-    float sn, cs;
-    sincosf(ph, &sn, &cs);
-    return make_float3(s * cs, s * sn, mu);
-}
 
 // isotropic over the hemisphere of axis d with sign sg (mu uniform in (0, 1])
 __device__ __forceinline__ float3 hemi_dir(Rng &r, const Walk3Args &a, int d, float sg)
@@ -459,7 +291,10 @@ __device__ void mc_step(Pk &p, const DevCloud &c, const uint8_t *__restrict__ tb
             finish(p, c, tally, false, 0, 0);   // counted with the step-capped packets
             return;
         }
-        const float uperp = sqrtf(-__logf(uf(draw(p.r, a)))) * cosf(kTwoPi * uf(draw(p.r, a)));
+        // perpendicular velocity in the scattering plane: sqrt(xc^2 - ln xi) cos(phi), a
+        // N(0, 1/2) component without core-skipping (xc = 0)
+        const float xc = (c.x_crit > 0.0f && fabsf(p.x) < c.x_crit) ? c.x_crit : 0.0f;
+        const float uperp = sqrtf(fmaf(xc, xc, -__logf(uf(draw(p.r, a))))) * cosf(kTwoPi * uf(draw(p.r, a)));
         const float3 n2 = iso_dir(p.r, a);
         const float mu = fmaf(p.n.x, n2.x, fmaf(p.n.y, n2.y, p.n.z * n2.z));
         p.x = p.x + upar * (mu - 1.0f) + uperp * sqrtf(fmaxf(0.0f, 1.0f - mu * mu));
@@ -545,7 +380,7 @@ __global__ __launch_bounds__(256) void walk3d(const uint8_t *__restrict__ tb, Wa
     p.n = make_float3(0.f, 0.f, 1.f);
     p.x = 0.f; p.t = 0.0; p.steps = 0;
     p.mcs = p.tomc = p.toddmc = p.refl = 0u;
-    p.r = Rng{0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+    p.r = Rng{0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 4u, false, 0u, 0u, 0u, 0u};
     bool exhausted = false;
 
     for (;;) {
@@ -573,7 +408,8 @@ __global__ __launch_bounds__(256) void walk3d(const uint8_t *__restrict__ tb, Wa
                         }
                         const DevCloud &c = clouds[cl];
                         p.cl = cl;
-                        p.r = Rng{0u, 0u, 0u, 0u, 0u, 0u, 0u, (uint32_t)(g - prefix[cl]), c.stream};
+                        p.r = Rng{0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 4u, false, 0u, 0u,
+                                  (uint32_t)(g - prefix[cl]), c.stream};
                         // emission (Sec. 2.3): a source entry drawn by its probability
                         const double u = ud(draw(p.r, a));
                         const double *cdf = reinterpret_cast<const double *>(tb + c.off_src_cdf);
@@ -607,12 +443,14 @@ __global__ __launch_bounds__(256) void walk3d(const uint8_t *__restrict__ tb, Wa
         }
         if (!__any(p.active)) break;
 
-        // Mode-batched passes: a pass advances either the wave's DDMC lanes by one step or its
-        // continuous-MC lanes by one event, never both, so a wave with a few MC lanes does not
-        // issue the long MC path on every step.  The MC lanes wait for a pass of their own
-        // until they are at least a quarter as many as the DDMC lanes, or every eighth pass.
-        // Every packet still takes its own steps in its own order from its own stream, so the
-        // results do not depend on this schedule.
+        // Mode-batched passes: a pass advances either the wave's DDMC lanes by up to two steps
+        // or its continuous-MC lanes by one event, never both, so a wave with a few MC lanes
+        // does not issue the long MC path on every step.  The MC lanes wait for a pass of
+        // their own until they are at least a quarter as many as the DDMC lanes, or every
+        // eighth pass.  Each pass starts by generating every taking part lane's next random
+        // block together (two frequency steps read one block).  Every packet still takes its
+        // own steps in its own order from its own stream, so the results do not depend on
+        // this schedule.
         const DevCloud &c = clouds[SINGLE ? 0 : p.cl];
         const float lambda = (float)c.lambda;
         for (int k = 0; k < a.chunk; ++k) {
@@ -623,9 +461,17 @@ __global__ __launch_bounds__(256) void walk3d(const uint8_t *__restrict__ tb, Wa
             const int nm = __popcll(bm), nd = __popcll(bd);
             const bool mc_pass = nm > 0 && (4 * nm >= nd || (k & 7) == 7);
             if (p.active && p.mc == mc_pass) {
+                prefetch(p.r, a);
                 ++p.steps;
-                if (mc_pass) mc_step(p, c, tb, a, tally, vtab, u0tab, lambda);
-                else ddmc_step(p, c, tb, a, tally);
+                if (mc_pass) {
+                    mc_step(p, c, tb, a, tally, vtab, u0tab, lambda);
+                } else {
+                    ddmc_step(p, c, tb, a, tally);
+                    if (p.active && !p.mc && p.steps < a.max_steps) {
+                        ++p.steps;
+                        ddmc_step(p, c, tb, a, tally);
+                    }
+                }
             }
         }
     }
@@ -649,6 +495,7 @@ hipError_t launch_walk3d(const uint8_t *d_tables, const DevHeader &h, const rddm
     a.key1 = (uint32_t)(run.seed >> 32);
     a.chunk = run.chunk > 0 ? run.chunk : 64;
     a.n_clouds = h.n_clouds;
+    a.dom = kDom3D;
     const int block = run.block > 0 ? run.block : 256;
     uint64_t grid = run.grid > 0 ? (uint64_t)run.grid : 0;
     if (grid == 0) {

@@ -38,7 +38,9 @@ class Medium_t(C.Structure):
                 ("k0", C.c_void_p), ("temp", C.c_void_p), ("vel", C.c_void_p),
                 ("tau_threshold", C.c_double), ("f_mu", C.c_double), ("lambda_", C.c_double),
                 ("n_src", C.c_int32), ("stream", C.c_uint32), ("src_pos", C.c_void_p),
-                ("src_x", C.c_void_p), ("n_packets", C.c_uint64)]
+                ("src_x", C.c_void_p), ("n_packets", C.c_uint64), ("x_crit", C.c_double),
+                ("dust_abs", C.c_void_p), ("dust_sca", C.c_void_p), ("src_t", C.c_void_p),
+                ("n_census", C.c_int32), ("reserved1", C.c_int32), ("census", C.c_void_p)]
 
 
 class Batch_t(C.Structure):
@@ -63,16 +65,18 @@ class CloudStats_t(C.Structure):
                 ("t_mean", C.c_double), ("t_var", C.c_double), ("n_rows", C.c_int32),
                 ("n_slots", C.c_int32), ("to_mc", C.c_uint64), ("to_ddmc", C.c_uint64),
                 ("reflected", C.c_uint64), ("mc_steps", C.c_uint64), ("n_pix", C.c_uint64),
-                ("surrogate_calls", C.c_uint64)]
+                ("surrogate_calls", C.c_uint64), ("absorbed", C.c_uint64)]
 
 
 class TallyOut_t(C.Structure):
     _fields_ = [("spectrum", C.POINTER(C.c_void_p)), ("time_hist", C.POINTER(C.c_void_p)),
                 ("step_hist", C.POINTER(C.c_void_p)), ("stats", C.POINTER(CloudStats_t)),
-                ("pixels", C.POINTER(C.c_void_p))]
+                ("pixels", C.POINTER(C.c_void_p)), ("census_bin", C.POINTER(C.c_void_p)),
+                ("census_path", C.POINTER(C.c_void_p))]
 
 
-ABI_VERSION = 3
+ABI_VERSION = 5
+CENSUS_PATH_FIX = float(1 << 24)   # residence-time units per length/c
 
 
 EXPORTS = ["rddmc_abi_version", "rddmc_last_error", "rddmc_table_bytes", "rddmc_tally_bytes",
@@ -166,6 +170,12 @@ class Batch:
             s.src_pos = self._ptr(np.asarray(m.src_pos, dtype=np.float64).reshape(-1, 3))
             s.src_x = self._ptr(m.src_x)
             s.n_packets = int(m.n_packets)
+            s.x_crit = float(m.x_crit)
+            s.dust_abs = self._ptr(m.dust_abs) if m.dust_abs is not None else None
+            s.dust_sca = self._ptr(m.dust_sca) if m.dust_sca is not None else None
+            s.src_t = self._ptr(np.asarray(m.src_t, dtype=np.float64).reshape(-1, 2)) if m.src_t is not None else None
+            s.n_census = 0 if m.census is None else len(m.census) - 1
+            s.census = self._ptr(m.census) if m.census is not None else None
         self._arr = arr
         self.c = Batch_t(len(self.meds), 0, arr)
 
@@ -265,6 +275,9 @@ class CloudTally:
     mc_steps: int = 0
     pixels: Optional[np.ndarray] = None   # 3D: escape counts per boundary cell (see include/rddmc.h)
     surrogate_calls: int = 0
+    absorbed: int = 0
+    census_bin: Optional[np.ndarray] = None    # (n_census+1, cells, bins) int64 packets per state at t_e
+    census_path: Optional[np.ndarray] = None   # (n_census, cells, bins) int64 residence, 2^-24 units
 
 
 def n_pixels(m) -> int:
@@ -285,8 +298,15 @@ def tally(b: Batch, d_tally, stream=None) -> List[CloudTally]:
     sh_ptrs = (C.c_void_p * n)(*[a.ctypes.data for a in sh])
     pix = [np.zeros(n_pixels(b.meds[i]), dtype=np.int64) for i in range(n)]
     px_ptrs = (C.c_void_p * n)(*[a.ctypes.data if a.size else None for a in pix])
+    ncen = [0 if m.census is None else len(m.census) - 1 for m in b.meds]
+    cb = [np.zeros((k + 1, m.n_cells_total, m.n_bins), dtype=np.int64) if k else np.zeros(0, dtype=np.int64)
+          for k, m in zip(ncen, b.meds)]
+    cp = [np.zeros((k, m.n_cells_total, m.n_bins), dtype=np.int64) if k else np.zeros(0, dtype=np.int64)
+          for k, m in zip(ncen, b.meds)]
+    cb_ptrs = (C.c_void_p * n)(*[a.ctypes.data if a.size else None for a in cb])
+    cp_ptrs = (C.c_void_p * n)(*[a.ctypes.data if a.size else None for a in cp])
     stats = (CloudStats_t * n)()
-    out = TallyOut_t(sp_ptrs, th_ptrs, sh_ptrs, stats, px_ptrs)
+    out = TallyOut_t(sp_ptrs, th_ptrs, sh_ptrs, stats, px_ptrs, cb_ptrs, cp_ptrs)
     _check(lib.rddmc_tally(b.ref(), C.c_void_p(d_tally.data_ptr()), d_tally.numel() * d_tally.element_size(),
                            C.byref(out), _stream(stream)))
     res = []
@@ -294,7 +314,8 @@ def tally(b: Batch, d_tally, stream=None) -> List[CloudTally]:
         z = stats[i]
         res.append(CloudTally(specs[i], th[i], sh[i], z.launched, z.escaped, z.capped, z.steps_total,
                               z.steps_max, z.steps_mean, z.t_mean, z.t_var, z.to_mc, z.to_ddmc, z.reflected,
-                              z.mc_steps, pix[i] if pix[i].size else None, z.surrogate_calls))
+                              z.mc_steps, pix[i] if pix[i].size else None, z.surrogate_calls, z.absorbed,
+                              cb[i] if cb[i].size else None, cp[i] if cp[i].size else None))
     return res
 
 

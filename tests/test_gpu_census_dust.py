@@ -1,0 +1,141 @@
+"""GPU time-dependent estimators (eq. 17: 'bin' counts at census times, 'path' residence
+times per census interval), emission windows and dust (Sec. 2.4) against the exact chain's
+transient law and absorption channel, the oracle walker, and exponential-integral transmission.
+
+Bars: census counts are binomial (the 3 sigma rule per state and time); a residence-time
+average lies in [0, 1] so its variance is at most its mean (5 such sigmas); fractions of
+escaped and absorbed packets within 4 binomial sigmas."""
+import math
+
+import numpy as np
+import pytest
+from scipy import special
+
+from oracle import chain, walk1dh
+from oracle import tables as tb
+from paper_1709_10187_amd import media, rddmc
+from tests._stats import assert_spectrum_matches, compare_exact, compare_two_samples
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu(m, n, seed=1):
+    print(f"[census/dust] {m.name} cells={m.n_cells[0]} bins={m.n_bins} packets={n}", flush=True)
+    p = rddmc.Problem(m.with_packets(n))
+    p.run(seed=seed)
+    return p.results()[0]
+
+
+def _check_census(g, ex, n, edges):
+    p = ex.at_edges.ravel()
+    got = g.census_bin.ravel() / n
+    assert np.all(got[p == 0] == 0)
+    sig = np.sqrt(np.maximum(p * (1 - p), 1e-300) / n)
+    z = np.abs(got - p) / np.where(p > 0, sig, 1.0)
+    sel = p * n >= 10
+    print(f"    census bin: {sel.sum()} cells, max |z| {z[sel].max():.2f}", flush=True)
+    assert np.sum(z[sel] > 3) <= max(2, int(0.005 * sel.sum())) and z[sel].max() < 5
+    dt = np.diff(edges)[:, None, None]
+    mean = (g.census_path / rddmc.CENSUS_PATH_FIX / (n * dt)).ravel()
+    want = ex.mean_in.ravel()
+    tol = 5 * np.sqrt(np.maximum(want, 1e-30) / n) + 1e-6
+    print(f"    census path: worst |err|/tol {np.max(np.abs(mean - want) / tol):.2f}", flush=True)
+    assert np.all(np.abs(mean - want) <= tol)
+
+
+@pytest.mark.parametrize("m", [media.slab(100.0, 1e4, 4, 6, x_max=4.0),
+                               media.sphere(300.0, 1e4, 5, 8, x_max=5.0, v_max=12.0)], ids=["slab", "sphere_outflow"])
+def test_census_estimators_match_exact_transient_law(m):
+    ref = chain.solve(m)
+    edges = np.array([0.0, 0.2, 0.5, 1.0, 2.0, 4.0]) * ref.t_mean
+    n = 1 << 20
+    g = _gpu(m.replace(census=edges), n)
+    assert g.escaped == n
+    _check_census(g, chain.transient(m, edges), n, edges)
+
+
+def test_grey_diffusion_census_matches_the_continuous_time_walk():
+    """The grey diffusion test (Sec. 3.1): 101 equal cells of a grey medium, a flash in the
+    central cell, census at t = {1, 2, 4, 8, 16} x 1e-2 t_diff with t_diff = k R^2 / 2c; the
+    bin and path estimators against the exact law of the discrete walk (the Bessel image sum
+    of the grey chain, pinned in the oracle's tests)."""
+    k = 1.0e3
+    m = media.slab(k, 1e4, 101, 1, x_max=1.0)
+    kbin = float(tb.build(m).k[0, 0])
+    t_diff = kbin / 2.0
+    edges = np.array([0.0, 1, 2, 4, 8, 16]) * 1e-2 * t_diff
+    n = 1 << 20
+    g = _gpu(m.replace(census=edges), n, seed=5)
+    _check_census(g, chain.transient(m, edges), n, edges)
+
+
+def test_emission_window_census_matches_exact_transient_law():
+    m = media.slab(100.0, 1e4, 4, 6, x_max=4.0)
+    ref = chain.solve(m)
+    ts, te = 0.3 * ref.t_mean, 1.1 * ref.t_mean
+    edges = np.array([0.0, 0.25, 0.5, 1.0, 1.5, 3.0]) * ref.t_mean
+    n = 1 << 20
+    g = _gpu(m.replace(census=edges, src_t=np.array([[ts, te]])), n, seed=7)
+    _check_census(g, chain.transient(m, edges, emit=(ts, te)), n, edges)
+    assert abs(g.t_mean - (ref.t_mean + 0.5 * (ts + te))) < 4.5 * math.sqrt(g.t_var / n)
+
+
+def test_dust_in_ddmc_states_matches_exact_chain():
+    m = media.sphere(400.0, 1e4, 6, 16, x_max=6.0, v_max=10.0)
+    m = m.replace(dust_abs=np.linspace(0.5, 2.0, 6), dust_sca=np.full(6, 3.0))
+    n = 1 << 20
+    g = _gpu(m, n, seed=9)
+    ref = chain.solve(m)
+    assert g.escaped + g.absorbed == n and g.capped == 0
+    pa = ref.absorbed
+    print(f"    absorbed {g.absorbed / n:.5f} vs {pa:.5f}", flush=True)
+    assert abs(g.absorbed / n - pa) < 4 * math.sqrt(pa * (1 - pa) / n)
+    r = compare_exact(g.spectrum.ravel(), ref.spectrum.ravel() / ref.total, g.escaped)
+    assert_spectrum_matches(r)
+    assert abs(g.t_mean - ref.t_mean) < 4 * math.sqrt(ref.t_var / g.escaped)
+
+
+@pytest.mark.parametrize("ka,ks", [(0.7, 0.0), (0.0, 0.7), (0.3, 0.4)])
+def test_dust_in_mc_states_against_transmission(ka, ks):
+    """Dust only (negligible Lya opacity, every state MC), central source in the slab |z| <= 1:
+    one event with probability E_2(k) + (1 - E_2(k)) k_a / k, k = k_a + k_s."""
+    m = media.slab(1e-9, 1e4, 1, 8, x_max=4.0, tau_threshold=1e30)
+    m = m.replace(dust_abs=np.array([ka]), dust_sca=np.array([ks]))
+    n = 1 << 21
+    g = _gpu(m, n, seed=11)
+    e2 = float(special.expn(2, ka + ks))
+    p1 = e2 + (1.0 - e2) * ka / (ka + ks)
+    assert abs(g.step_hist[0] / n - p1) <= 4 * math.sqrt(p1 * (1 - p1) / n)
+    if ks == 0.0:
+        assert abs(g.escaped / n - e2) < 4 * math.sqrt(e2 * (1 - e2) / n)
+    if ka == 0.0:
+        assert g.escaped == n
+    assert g.escaped + g.absorbed == n
+    spec = g.spectrum.sum(axis=0)
+    assert spec[1 + 3] + spec[1 + 4] == g.escaped
+
+
+def test_hybrid_dust_census_against_oracle_walker():
+    """Everything at once on a moving hybrid slab (continuous-MC wings, dust, an emission window
+    and a census): the GPU against the oracle walker as two samples (spectrum, absorbed
+    fraction, census counts summed over bins)."""
+    nc = 12
+    m = media.slab(1e4, 1e4, nc, 48, x_max=16.0, tau_threshold=10.0, vel=np.linspace(-30, 30, nc))
+    m = m.replace(dust_abs=np.full(nc, 0.8), dust_sca=np.full(nc, 2.0), src_t=np.array([[0.0, 2.0]]),
+                  census=np.array([0.0, 1.0, 2.0, 4.0, 8.0]))
+    ng, no = 1 << 18, 1 << 15
+    g = _gpu(m, ng, seed=13)
+    o = walk1dh.run(m, n_packets=no, seed=15)
+    assert g.escaped + g.absorbed == ng and o.escaped + o.absorbed == no
+    fa, fo = g.absorbed / ng, o.absorbed / no
+    assert abs(fa - fo) < 4.5 * math.sqrt(fo * (1 - fo) * (1 / ng + 1 / no))
+    assert_spectrum_matches(compare_two_samples(g.spectrum, o.spectrum))
+    # census counts per (time, cell): two binomial samples
+    gb = g.census_bin.sum(axis=2) / ng
+    ob = o.e_bin.sum(axis=2) / no
+    q = (gb * ng + ob * no) / (ng + no)
+    sig = np.sqrt(np.maximum(q * (1 - q), 1e-300) * (1 / ng + 1 / no))
+    z = np.abs(gb - ob) / np.where(q > 0, sig, 1.0)
+    sel = q * no >= 10
+    print(f"    census two-sample max |z| {z[sel].max():.2f} over {sel.sum()} cells", flush=True)
+    assert z[sel].max() < 5 and np.sum(z[sel] > 3) <= 2

@@ -5,6 +5,7 @@ wherever the Monte Carlo noise floor allows it (expected noise L1 <= 0.5 %); mea
 and escape-time moments within 4 standard errors of the exact values; integer tallies
 bit-identical across launch shapes and shard splits."""
 import math
+import os
 
 import numpy as np
 import pytest
@@ -123,6 +124,54 @@ def test_config_sphere_sampled_packets():
     res = p.results()[0]
     r = compare_exact(res.spectrum, ref.spectrum, n)
     assert_spectrum_matches(r)
+    _check_moments(res, ref, n)
+
+
+@pytest.mark.skipif(os.environ.get("RDDMC_WHOLE_JOB") != "1",
+                    reason="about ten minutes of GPU time: set RDDMC_WHOLE_JOB=1 to run")
+def test_config_sphere_whole_job_matches_exact_chain(capsys):
+    """The tau0 = 1e7 sphere at its stated size: all 2^22 packets (2.5e14 steps), walked as four
+    launches of 2^20 consecutive packet ids (tallies are bit-identical for any split) on two
+    streams with their own work counters, so that one launch's slowest packets run beside the
+    next one's bulk.  At this count the Monte Carlo noise L1 of the 512-bin spectrum is
+    ~0.42 %, so the full bar applies: the 3 sigma rule, L1 <= 1 %, and mean steps and escape
+    time within 4 standard errors of the exact chain."""
+    import time
+    import torch
+    m = media.config_sphere()
+    n = int(m.n_packets)
+    ref = chain.solve(m)
+    p = rddmc.Problem(m)
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    works = [p.work, torch.zeros_like(p.work)]
+    shard = 1 << 20
+    done = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k, first in enumerate(range(0, n, shard)):
+        st = streams[k % 2]
+        st.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(st):
+            rddmc.transport(p.batch, p.tables, p.tallies, works[k % 2], seed=0, first=first, count=shard, stream=st)
+            ev = torch.cuda.Event()
+            ev.record(st)
+        done.append((first, ev))
+    for first, ev in done:
+        ev.synchronize()
+        with capsys.disabled():
+            print(f"\n[walk] config_sphere whole job: ids {first}..{first + shard - 1} done "
+                  f"({time.perf_counter() - t0:.1f} s)", flush=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    res = p.results()[0]
+    r = compare_exact(res.spectrum, ref.spectrum, n)
+    with capsys.disabled():
+        print(f"[walk]   {dt:.1f} s: {n / dt:.4g} packets/s, {res.steps_total / dt:.4g} steps/s, slowest packet "
+              f"{res.steps_max} steps; L1 {r['L1']:.5f} (noise {r['expected_noise_L1']:.5f}), max |z| "
+              f"{r['max_abs_z']:.2f}, chi2 p {r['p_value']:.3g}", flush=True)
+    assert res.capped == 0 and res.launched == n
+    assert r["expected_noise_L1"] <= 0.005, r["expected_noise_L1"]
+    assert_spectrum_matches(r, l1_max=0.01)
     _check_moments(res, ref, n)
 
 
