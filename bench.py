@@ -12,6 +12,9 @@ walk of the same workload.
 Other workloads (``--workload``):
   sphere     the static uniform sphere tau0 = 1e7, 256 shells x 512 bins, 2^22 packets: one
              step is the whole job (about 7 minutes), or ``--block-packets`` consecutive ids;
+  sphere-efficient
+             the same sphere on the paper's efficient frequency grid (79 bins: a central bin
+             of 2 x_cw, unit-width wings to 2.5 (a tau0)^(1/3)), the whole job per step;
   sweep      batched sweep clouds in one hipGraph-captured launch with the autotuned schedule;
   surrogate  the learned escape surrogate against plain rDDMC on the same clouds and packets.
 
@@ -82,7 +85,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["cube", "sphere", "surrogate", "sweep"], default="cube")
+    ap.add_argument("--workload", choices=["cube", "sphere", "sphere-efficient", "surrogate", "sweep"], default="cube")
     ap.add_argument("--block-packets", type=int, default=0,
                     help="sphere: packets per step (0 = the whole 2^22-packet job)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -190,12 +193,18 @@ def bench_cube(args):
     return out
 
 
-def bench_sphere(args):
-    """The tau0 = 1e7 sphere; one step = the whole 2^22-packet job or a block of its ids."""
+def bench_sphere(args, efficient=False):
+    """The tau0 = 1e7 sphere; one step = the whole 2^22-packet job or a block of its ids.  With
+    `efficient`, on the paper's efficient frequency grid instead of 512 uniform bins."""
     from paper_1709_10187_amd import media, rddmc
     if args.copy_probe_mib > 0:
         copy_probe(args.copy_probe_mib)
     m = media.config_sphere()
+    grid = "256 shells x 512 bins, |x|<=6(a tau0)^(1/3)"
+    if efficient:
+        m = m.replace(bin_edges=media.efficient_edges(4.702e-4, 1.0e7, 1.0 / 256), name="sphere_tau1e7_efficient")
+        grid = (f"256 shells x {m.n_bins} bins of the efficient grid (central bin 2 x_cw = "
+                f"{m.bin_edges[m.n_bins // 2 + 1] - m.bin_edges[m.n_bins // 2]:.3f}, unit wings, |x|<=2.5(a tau0)^(1/3))")
     B = int(args.block_packets) or int(m.n_packets)
     log(f"building tables for {m.name}")
     prob = rddmc.Problem(m)
@@ -206,7 +215,7 @@ def bench_sphere(args):
     achieved = (res.steps_total / K) * OPS_PER_STEP / launch_s
     out = base_line(
         args, res.launched / sec, sec, "f32",
-        {"workload": "static uniform sphere tau0=1e7 T=1e4K, 256 shells x 512 bins, |x|<=6(a tau0)^(1/3), "
+        {"workload": f"static uniform sphere tau0=1e7 T=1e4K, {grid}, "
                      f"central source x=0, job of 2^22 packets; one step = packet ids 0..{B - 1}",
          "packets_per_step": B, "escaped": int(res.escaped), "steps_mean": res.steps_mean,
          "steps_max": int(res.steps_max), "t_mean_light_crossings": res.t_mean,
@@ -216,10 +225,11 @@ def bench_sphere(args):
     out["roofline"] = {
         "bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_OPS / 1e12, "unit": "T VALU lane-ops/s",
         "frac": achieved / PEAK_OPS,
-        "traffic": profiled_traffic("walk1d_sphere_tau1e7_job_pmc.md", "walk1d") if B == m.n_packets else None,
+        "traffic": (profiled_traffic("walk1d_sphere_tau1e7_job_pmc.md", "walk1d")
+                    if B == m.n_packets and not efficient else None),
         "kernel": "walk1d"}
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline_1d(m, args.cpu_packets or 12, args)
+        out["cpu_baseline"] = cpu_baseline_1d(m, args.cpu_packets or (16384 if efficient else 12), args)
     return out
 
 
@@ -380,7 +390,8 @@ def main():
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    fn = {"cube": bench_cube, "sphere": bench_sphere, "surrogate": bench_surrogate, "sweep": bench_sweep}
+    fn = {"cube": bench_cube, "sphere": bench_sphere, "sphere-efficient": lambda a: bench_sphere(a, efficient=True),
+          "surrogate": bench_surrogate, "sweep": bench_sweep}
     print(json.dumps(fn[args.workload](args)), flush=True)
 
 

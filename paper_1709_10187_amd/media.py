@@ -94,6 +94,46 @@ def uniform_edges(x_max: float, n_bins: int) -> np.ndarray:
     return (2.0 * i - n_bins) / n_bins * x_max
 
 
+def core_wing_crossover(a: float) -> float:
+    """x_cw, where the Doppler core exp(-x^2) meets the damping wing a / (sqrt(pi) x^2)
+    (Sec. 2.1): the root above 1 of x^2 - 2 ln x = ln(sqrt(pi) / a), by Newton's method."""
+    rhs = math.log(math.sqrt(math.pi) / a)
+    if rhs <= 1.0:
+        raise ValueError(f"damping a = {a} leaves no core: x^2 - 2 ln x >= 1 for every x")
+    x = max(1.5, math.sqrt(rhs + 2.0 * math.log(max(rhs, 1.0))))
+    for _ in range(60):
+        f = x * x - 2.0 * math.log(x) - rhs
+        x_new = x - f / (2.0 * x - 2.0 / x)
+        if abs(x_new - x) < 1e-15 * x:
+            return x_new
+        x = x_new
+    return x
+
+
+def efficient_edges(a: float, tau0: float, dz_over_R: float, x_max: Optional[float] = None,
+                    dx_wing: Optional[float] = None) -> np.ndarray:
+    """The frequency grid the paper recommends for pure rDDMC (Secs. 4.2 and 5.1): one central
+    bin at least 2 x_cw wide (binning skips the core's complete redistribution; it takes
+    max(2 x_cw, dx_wing)), wing bins of width dx_wing, an odd number of bins in all, over
+    |x| <= x_max.
+
+    dx_wing defaults to the width that matches the cell size by eq. 37,
+    dx^3 / (a tau0) = 2.5 (dz / R)^2, and never goes below 1 (the Fokker-Planck treatment of
+    the wings needs bins wider than the redistribution step); x_max defaults to
+    2.5 (a tau0)^(1/3).  The outermost wing bins end at or just beyond x_max."""
+    atau = a * tau0
+    if x_max is None:
+        x_max = 2.5 * atau ** (1.0 / 3.0)
+    if dx_wing is None:
+        dx_wing = max(1.0, (2.5 * atau * dz_over_R ** 2) ** (1.0 / 3.0))
+    h = max(core_wing_crossover(a), 0.5 * dx_wing)
+    if x_max <= h:
+        raise ValueError(f"x_max = {x_max} lies inside the central bin (x_cw = {h})")
+    n_w = int(math.ceil((x_max - h) / dx_wing - 1e-12))
+    wing = h + dx_wing * np.arange(n_w + 1, dtype=np.float64)
+    return np.concatenate([-wing[::-1], wing])
+
+
 def slab(tau0: float, T: float, n_cells: int, n_bins: int, x_max: Optional[float] = None,
          x_max_factor: float = 6.0, n_packets: int = 1 << 16, tau_threshold: float = 0.0,
          src_z: float = 0.0, src_x: float = 0.0, vel: Optional[np.ndarray] = None,

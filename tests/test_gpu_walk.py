@@ -175,6 +175,33 @@ def test_config_sphere_whole_job_matches_exact_chain(capsys):
     _check_moments(res, ref, n)
 
 
+@pytest.mark.parametrize("which", ["sphere_tau1e7", "converged_slab"])
+def test_efficient_grid_whole_job_matches_exact_chain(which):
+    """The paper's efficient frequency grid (one central bin of width max(2 x_cw, dx_wing),
+    eq. 37-matched wings): the tau0 = 1e7 sphere's whole 2^22-packet job (79 bins instead of
+    512: 2.6e4 steps per packet instead of 6e7) and the converged slab (a tau0 = 1e9, 81 bins)
+    at 2^22 packets, against the exact chain on the same grid with the full bar."""
+    if which == "sphere_tau1e7":
+        a = 4.702e-4
+        m = media.config_sphere()
+        m = m.replace(bin_edges=media.efficient_edges(a, 1.0e7, 1.0 / 256), name="sphere_tau1e7_efficient")
+    else:
+        a = 4.702e-4 / math.sqrt(1e-3)
+        m = media.validation_slab()
+        m = m.replace(bin_edges=media.efficient_edges(a, 1.0e9 / a, 2.0 / 201), name="vslab_efficient",
+                      n_packets=1 << 22)
+    ref = chain.solve(m)
+    n = int(m.n_packets)
+    p, res = _run(m, seed=4)
+    r = compare_exact(res.spectrum, ref.spectrum, n)
+    print(f"    {m.n_bins} bins: L1 {r['L1']:.5f} (noise {r['expected_noise_L1']:.5f}), max |z| {r['max_abs_z']:.2f}, "
+          f"steps/pk {res.steps_mean:.4g} vs {ref.steps:.4g}", flush=True)
+    assert res.capped == 0
+    assert r["expected_noise_L1"] <= 0.005
+    assert_spectrum_matches(r, l1_max=0.01)
+    _check_moments(res, ref, n)
+
+
 def test_bit_identical_across_launch_shapes_and_shards():
     m = media.slab(1e4, 1e4, 16, 33).with_packets(20000)
     outs = []
