@@ -279,6 +279,40 @@ class TransientResult:
     at_edges: np.ndarray      # (n+1, nc, nb): P(the packet is in state s at t_e)
     mean_in: np.ndarray       # (n, nc, nb): the occupation averaged over [t_e, t_e+1)
     escaped_by: np.ndarray    # (n+1,): P(escaped by t_e)
+    accel: np.ndarray = None  # (n, nc): eq. 18's optical-depth sum per cell and interval (1D)
+
+
+def _accel_weights(ch):
+    """Per state s = (c, j): the expected eq. 18 contribution of one unit of residence in s,
+    split into the cell it leaks out of and the cell it leaks into.  A step in s lasts
+    dl ~ Exp(K_s) and ends in leak f with probability r_f / K_s, independently of dl; a leak
+    along direction d (-1 through face 0, +1 through face 1) adds k_s dl d to cell c and, when
+    the neighbour c' is a grid cell, k_{c',j'} dl d to c' at the bin j' it lands in (Doppler
+    re-binning of eq. 20 for moving media).  Returns (out (ns,), into list of (dst cell,
+    weights (ns,)))."""
+    t, nb, K = ch["t"], ch["nb"], ch["K"]
+    nc = t.nc
+    if t.nf != 2:
+        raise ValueError("the acceleration estimator is tallied on 1D grids (slab z, sphere r)")
+    kk = t.k
+    edges = t.bin_edges
+    out = np.zeros(nc * nb)
+    into = np.zeros((nc, nc * nb))
+    for f, d in ((0, -1.0), (1, 1.0)):
+        p = t.rate_face[:, :, f] / K.reshape(nc, nb)          # P(leak through f | s)
+        out += (d * p * kk).ravel()
+        for c in range(nc):
+            n = t.nbr[c, f]
+            if n < 0:
+                continue
+            rho, sh = t.rho[c, f], t.shift[c, f]
+            if rho == 1.0 and sh == 0.0:
+                kn = kk[n]
+            else:
+                src_j, dst_j, wts = _overlaps(edges, rho * edges[:-1] + sh, rho * edges[1:] + sh)
+                kn = np.bincount(src_j, weights=wts * kk[n][dst_j], minlength=nb)
+            into[n, c * nb:(c + 1) * nb] += d * p[c] * kn
+    return out, into
 
 
 def transient(m, edges, tabs=None, emit=None) -> TransientResult:
@@ -325,5 +359,10 @@ def transient(m, edges, tabs=None, emit=None) -> TransientResult:
     # escaped by t: the escape flux integrated, int_0^t occ . esc_rate
     escaped = cum @ esc_rate
     nc = ns // nb
+    accel = None
+    if ch["t"].nf == 2:
+        res = cum[1:] - cum[:-1]                    # expected residence per (interval, state)
+        w_out, w_into = _accel_weights(ch)
+        accel = (res * w_out).reshape(len(edges) - 1, nc, nb).sum(axis=2) + res @ w_into.T
     return TransientResult(edges=edges, at_edges=at.reshape(len(edges), nc, nb),
-                           mean_in=mean.reshape(len(edges) - 1, nc, nb), escaped_by=escaped)
+                           mean_in=mean.reshape(len(edges) - 1, nc, nb), escaped_by=escaped, accel=accel)

@@ -44,6 +44,12 @@
  *    state is counted ('bin'), and its residence time in each state is summed per census
  *    interval ('path'); an MC packet's state is (cell, bin of its comoving x at the start of
  *    the flight).  Packets are emitted at t = 0, or uniformly over their source's window.
+ *  - Acceleration estimator (eq. 18), per cell and census interval, along z (slab) or r
+ *    (shells): a DDMC spatial leak of a step with residence [t0, t1) in state (c, j), moving
+ *    along d = -1 (face 0) or +1 (face 1), adds k_{c,j} d times the step's residence in each
+ *    interval to cell c (outward leakage), and k_{c',j'} d times the same to the cell c' it
+ *    enters when it lands there in a DDMC state (c', j') (inward leakage): both carry the
+ *    sign of the motion.  Leaks into continuous-MC states or vacuum count for c only.
  *
  * Random numbers: xoshiro256** per packet seeded by splitmix64(seed ^ id*golden).
  */
@@ -92,6 +98,7 @@ typedef struct {
     int64_t escaped, capped, to_mc, to_ddmc, reflected, absorbed;
     double *e_bin;         /* [(n_census+1)*nc*nb] counts of packets in each state at each census time */
     double *e_path;        /* [n_census*nc*nb] residence time in each state per census interval */
+    double *e_accel;       /* [n_census*nc] eq. 18 optical-depth sums (z or r component) */
 } oh_result;
 
 static int locate(const double *e, int nb, double x)
@@ -223,6 +230,17 @@ static void census_add(const oh_problem *P, oh_result *R, int64_t s, double t0, 
     }
 }
 
+/* eq. 18: a leak of a step that stayed over [t0, t1) adds v times its residence in each census
+ * interval to cell c */
+static void accel_add(const oh_problem *P, oh_result *R, int64_t c, double t0, double t1, double v)
+{
+    if (P->n_census <= 0) return;
+    for (int n = 0; n < P->n_census; ++n) {
+        double a = fmax(t0, P->census[n]), b = fmin(t1, P->census[n + 1]);
+        if (b > a) R->e_accel[(int64_t)n * P->nc + c] += v * (b - a);
+    }
+}
+
 static int64_t mc_state(const oh_problem *P, int64_t c, double x)
 {
     int j = locate(P->edges, P->nb, x);
@@ -289,6 +307,7 @@ static void walk_packet(const oh_problem *P, uint64_t id, uint64_t seed, uint64_
                 if (l < best) { best = l; ev = 4; }
             }
             census_add(P, R, s, t, t + best);
+            const double t_prev = t;
             t += best;
             if (ev == 4) { R->absorbed++; break; }   /* removed by dust after that residence */
             if (ev >= 2) {
@@ -305,6 +324,8 @@ static void walk_packet(const oh_problem *P, uint64_t id, uint64_t seed, uint64_
             }
             int f = ev;
             int64_t nc = P->nbr[c * 2 + f];
+            const double dir = f ? 1.0 : -1.0;
+            accel_add(P, R, c, t_prev, t, dir * P->k[s]);      /* outward leakage from c */
             double xin = P->edges[j] + (P->edges[j + 1] - P->edges[j]) * ru(&r);
             if (P->face_mc[s * 2 + f] || nc < 0) {
                 /* interface leak: MC at a uniform point of the face, isotropic outward */
@@ -328,6 +349,7 @@ static void walk_packet(const oh_problem *P, uint64_t id, uint64_t seed, uint64_
                 j = jn < 0 ? 0 : (jn > nb - 1 ? nb - 1 : jn);
             }
             c = nc;
+            if (P->thick[c * nb + j]) accel_add(P, R, c, t_prev, t, dir * P->k[c * nb + j]);   /* inward */
             if (!P->thick[c * nb + j]) {   /* re-binned into a thin state */
                 cell_point(P, c, &r, pos);
                 iso_dir(&r, n);
@@ -425,6 +447,8 @@ static void *worker(void *arg)
     size_t npath = P->n_census > 0 ? (size_t)P->n_census * nst : 0;
     L.e_bin = nbin ? calloc(nbin, 8) : NULL;
     L.e_path = npath ? calloc(npath, 8) : NULL;
+    size_t nacc = P->n_census > 0 ? (size_t)P->n_census * P->nc : 0;
+    L.e_accel = nacc ? calloc(nacc, 8) : NULL;
     for (;;) {
         uint64_t b = __sync_fetch_and_add(jb->next, 8);
         if (b >= jb->n) break;
@@ -443,8 +467,9 @@ static void *worker(void *arg)
     R->absorbed += L.absorbed;
     for (size_t i = 0; i < nbin; ++i) R->e_bin[i] += L.e_bin[i];
     for (size_t i = 0; i < npath; ++i) R->e_path[i] += L.e_path[i];
+    for (size_t i = 0; i < nacc; ++i) R->e_accel[i] += L.e_accel[i];
     pthread_mutex_unlock(jb->lock);
-    free(L.spectrum); free(L.time_hist); free(L.step_hist); free(L.e_bin); free(L.e_path);
+    free(L.spectrum); free(L.time_hist); free(L.step_hist); free(L.e_bin); free(L.e_path); free(L.e_accel);
     return NULL;
 }
 

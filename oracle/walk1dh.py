@@ -40,7 +40,7 @@ class _Result(C.Structure):
                 ("t_sum", C.c_double), ("t2_sum", C.c_double), ("steps_sum", C.c_double),
                 ("mc_steps_sum", C.c_double), ("steps2_sum", C.c_double), ("escaped", C.c_int64),
                 ("capped", C.c_int64), ("to_mc", C.c_int64), ("to_ddmc", C.c_int64), ("reflected", C.c_int64),
-                ("absorbed", C.c_int64), ("e_bin", C.c_void_p), ("e_path", C.c_void_p)]
+                ("absorbed", C.c_int64), ("e_bin", C.c_void_p), ("e_path", C.c_void_p), ("e_accel", C.c_void_p)]
 
 
 _lib = None
@@ -77,6 +77,7 @@ class Walk1DHResult:
     absorbed: int = 0
     e_bin: np.ndarray = None   # (n_census+1, nc, nb) packets in each state at each census time
     e_path: np.ndarray = None  # (n_census, nc, nb) residence time per census interval
+    e_accel: np.ndarray = None  # (n_census, nc) eq. 18 optical-depth sums (z or r component)
 
     @property
     def t_mean(self):
@@ -146,10 +147,12 @@ def run(m, n_packets=None, seed=0, first_id=0, max_steps=(1 << 62), n_threads=No
     nce = 0 if m.census is None else len(m.census) - 1
     e_bin = np.zeros((nce + 1, t.nc, t.nb)) if nce else None
     e_path = np.zeros((nce, t.nc, t.nb)) if nce else None
+    e_accel = np.zeros((nce, t.nc)) if nce else None
     R = _Result(spec.ctypes.data, th.ctypes.data, sh.ctypes.data, 0.0, 0.0, 0.0, 0.0, 0.0, 0, 0, 0, 0, 0, 0,
-                e_bin.ctypes.data if nce else None, e_path.ctypes.data if nce else None)
+                e_bin.ctypes.data if nce else None, e_path.ctypes.data if nce else None,
+                e_accel.ctypes.data if nce else None)
     rc = lib.oh_run(C.byref(P), first_id, n, seed, max_steps, n_threads or os.cpu_count() or 1, C.byref(R))
     if rc != 0:
         raise RuntimeError("oh_run failed")
     return Walk1DHResult(spec, th, sh, R.t_sum, R.t2_sum, R.steps_sum, R.mc_steps_sum, R.steps2_sum, R.escaped,
-                         R.capped, R.to_mc, R.to_ddmc, R.reflected, n, R.absorbed, e_bin, e_path)
+                         R.capped, R.to_mc, R.to_ddmc, R.reflected, n, R.absorbed, e_bin, e_path, e_accel)

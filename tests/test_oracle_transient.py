@@ -101,3 +101,72 @@ def test_dust_absorption_is_the_killed_gamblers_ruin(N, start, q):
     want = math.cosh(th * (start - L / 2.0)) / math.cosh(th * L / 2.0)
     assert r.total == pytest.approx(want, rel=1e-10)
     assert r.total + r.absorbed == pytest.approx(1.0, abs=1e-12)
+
+
+@pytest.mark.parametrize("N,start", [(9, 5), (11, 3)])
+def test_acceleration_steady_grey_slab_is_the_net_face_crossings(N, start):
+    """Eq. 18 over one long interval on a grey slab whose every state has the same total rate K:
+    each leak across a face adds k dl along its motion to both cells it touches, E[dl] = 1/K,
+    so cell i collects (k/K) times the expected net upward crossings of its two faces,
+    P_top - 1{m > i} and P_top - 1{m >= i} (walk from cell m absorbed at 0 and N+1,
+    P_top = m / (N+1))."""
+    m0, kbin, dz = _grey(N)
+    t = tb.build(m0)
+    np.testing.assert_allclose(t.K[:, 0], t.K[0, 0], rtol=1e-12)
+    K = float(t.K[0, 0])
+    zc = -1 + dz * (start - 0.5)
+    m = m0.replace(src_pos=np.array([[zc, 0, 0]]))
+    t_end = 400.0 * chain.solve(m).t_mean
+    r = chain.transient(m, np.array([0.0, t_end]))
+    assert r.escaped_by[-1] == pytest.approx(1.0, abs=1e-12)
+    p_top = start / (N + 1.0)
+    i = np.arange(1, N + 1)
+    want = kbin / K * (2.0 * p_top - (start > i) - (start >= i))
+    np.testing.assert_allclose(r.accel[0], want, rtol=1e-9, atol=1e-12)
+
+
+def test_acceleration_per_interval_against_the_bessel_walk():
+    """The same estimator per census interval: cell i collects k r / K times the time integral
+    of P_{i-1}(t) - P_{i+1}(t) over the interval (the hop rate r each way, P_0 = P_{N+1} = 0),
+    with P from the image sum of the continuous-time walk."""
+    from scipy import integrate
+    N, start = 9, 4
+    m0, kbin, dz = _grey(N)
+    K = float(tb.build(m0).K[0, 0])
+    m = m0.replace(src_pos=np.array([[-1 + dz * (start - 0.5), 0, 0]]))
+    r_hop = 1.0 / (3.0 * kbin * dz * dz)
+    assert K == pytest.approx(2.0 * r_hop, rel=1e-12)
+    L = N + 1
+    edges = np.array([0.0, 0.5, 2.0, 6.0]) / r_hop
+    res = chain.transient(m, edges)
+
+    def P(n, t):
+        if n < 1 or n > N:
+            return 0.0
+        z = 2.0 * r_hop * t
+        return sum(special.ive(n - start + 2 * k * L, z) - special.ive(n + start + 2 * k * L, z)
+                   for k in range(-8, 9))
+
+    for it in range(len(edges) - 1):
+        for i in range(1, N + 1):
+            val, _ = integrate.quad(lambda s: P(i - 1, s) - P(i + 1, s), edges[it], edges[it + 1],
+                                    epsabs=1e-13, epsrel=1e-11, limit=200)
+            assert res.accel[it, i - 1] == pytest.approx(kbin * r_hop / K * val, rel=1e-7, abs=1e-10)
+
+
+def test_walker_acceleration_matches_exact_chain():
+    """The literal walker's per-leak sums against the chain's expectation on a small moving
+    sphere (Doppler re-binning decides the inward leak's bin): eight independent batches give
+    the standard error."""
+    from oracle import walk1dh
+    m = media.sphere(400.0, 1e4, 4, 10, x_max=6.0, v_max=25.0)
+    ref = chain.solve(m)
+    edges = np.array([0.0, 0.3, 1.0, 3.0]) * ref.t_mean
+    m = m.replace(census=edges)
+    ex = chain.transient(m, edges).accel
+    n = 1 << 14
+    runs = np.array([walk1dh.run(m, n_packets=n, seed=100 + b).e_accel / n for b in range(8)])
+    mean, se = runs.mean(axis=0), runs.std(axis=0, ddof=1) / math.sqrt(len(runs))
+    z = np.abs(mean - ex) / np.maximum(se, 1e-12)
+    print(f"walker vs chain eq. 18: max |z| {z.max():.2f}")
+    assert np.all(np.abs(mean - ex) <= 5.0 * se + 1e-9 * np.abs(ex).max())
