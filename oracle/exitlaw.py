@@ -70,9 +70,38 @@ def exit_law(t, cell, j_in) -> ExitLaw:
     return ExitLaw(prob=prob, steps=float(v.sum()), t_mean=float(v @ tau), t2=float(2.0 * np.sum(v * tau * m1)))
 
 
-def simulate(t, cell, j_in, n, seed=0):
+def exit_time_moments(t, cell, j_in):
+    """E[T | exit bin j_out] and E[T^2 | exit bin j_out] for a walk entered in bin j_in, from
+    first-step analysis per exit bin (columns): with h(k) = P(leak at j_out | start k),
+    m(k) = E[T 1{leak at j_out} | k] and s(k) = E[T^2 1{...} | k],
+      (I - Q) h = e_jout p_s(j_out),  (I - Q) m = tau h,  (I - Q) s = 2 tau m,
+    (a step in k lasts tau_k on average, its square 2 tau_k^2 on average, independently of
+    where it goes); then E[T | j_out] = m(j_in) / h(j_in), E[T^2 | j_out] = s(j_in) / h(j_in).
+    Bins with h(j_in) = 0 get NaN."""
+    nb = t.nb
+    ab, tau = _banded_IQ(t, cell)
+    K = t.K[cell]
+    ps = t.rate_face[cell].sum(axis=1) / K
+    m1 = np.full(nb, np.nan)
+    m2 = np.full(nb, np.nan)
+    for jo in range(nb):
+        if ps[jo] <= 0.0:
+            continue
+        e = np.zeros(nb)
+        e[jo] = ps[jo]
+        h = linalg.solve_banded((1, 1), ab, e)
+        m = linalg.solve_banded((1, 1), ab, tau * h)
+        sq = linalg.solve_banded((1, 1), ab, 2.0 * tau * m)
+        if h[j_in] > 0.0:
+            m1[jo] = m[j_in] / h[j_in]
+            m2[jo] = sq[j_in] / h[j_in]
+    return m1, m2
+
+
+def simulate(t, cell, j_in, n, seed=0, per_bin=False):
     """Brute-force sampling of the same in-cell chain (test pin for exit_law): returns
-    counts (n_faces, nb), mean steps and mean time."""
+    counts (n_faces, nb), mean steps and mean time (and, with ``per_bin``, the sums of T and
+    T^2 of the walks that leaked at each exit bin)."""
     rng = np.random.default_rng(seed)
     nb, nf = t.nb, t.nf
     rates = np.concatenate([t.rate_dn[cell][:, None], t.rate_up[cell][:, None], t.rate_face[cell]], axis=1)
@@ -83,6 +112,8 @@ def simulate(t, cell, j_in, n, seed=0):
     times = np.zeros(n)
     j = np.full(n, j_in)
     alive = np.ones(n, dtype=bool)
+    t_sum = np.zeros(nb)
+    t2_sum = np.zeros(nb)
     while np.any(alive):
         idx = np.nonzero(alive)[0]
         jj = j[idx]
@@ -98,7 +129,12 @@ def simulate(t, cell, j_in, n, seed=0):
         leak = ev >= 2
         li = idx[leak]
         np.add.at(counts, (ev[leak] - 2, jj[leak]), 1)
+        if per_bin:
+            np.add.at(t_sum, jj[leak], times[li])
+            np.add.at(t2_sum, jj[leak], times[li] ** 2)
         alive[li] = False
+    if per_bin:
+        return counts, float(steps.mean()), float(times.mean()), t_sum, t2_sum
     return counts, float(steps.mean()), float(times.mean())
 
 
