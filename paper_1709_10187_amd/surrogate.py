@@ -27,6 +27,11 @@ from . import media, rddmc
 _A_1E4 = 4.702e-4
 _VTH_1E4 = 12.85
 
+# Training recipe: probe media, sub-walks per probe, epochs (Adam, cosine-decayed rate).
+TRAIN_PROBES = 8192
+TRAIN_PER_PROBE = 128
+TRAIN_EPOCHS = 40
+
 
 @dataclasses.dataclass
 class Domain:

@@ -73,17 +73,18 @@ def test_subwalk_data_matches_exact_exit_law(args):
 @pytest.fixture(scope="module")
 def trained():
     t0 = time.time()
-    probes = sg.sample_probes(2048, DOM, seed=11)
-    print(f"[surrogate] generating 2048 x 128 sub-walks (tau {DOM.tau_min:g}..{DOM.tau_max:g}, "
-          f"dx {DOM.dx_min}..{DOM.dx_max})", flush=True)
-    data = sg.generate(probes, 128, DOM, seed=12, max_steps=1 << 30)
+    probes = sg.sample_probes(sg.TRAIN_PROBES, DOM, seed=11)
+    print(f"[surrogate] generating {sg.TRAIN_PROBES} x {sg.TRAIN_PER_PROBE} sub-walks (tau {DOM.tau_min:g}.."
+          f"{DOM.tau_max:g}, dx {DOM.dx_min}..{DOM.dx_max})", flush=True)
+    data = sg.generate(probes, sg.TRAIN_PER_PROBE, DOM, seed=12, max_steps=1 << 30)
     print(f"[surrogate]   {data.n} samples in {time.time() - t0:.1f} s", flush=True)
     net = rddmc.Mdn(max_batch=4096, seed=0)
+    loss0 = float(net.loss_grad(data.x[:4096].contiguous(), data.y[:4096].contiguous()).cpu()[0])
     t1 = time.time()
-    hist = sg.train(net, data, epochs=60, lr=2e-3, lr_final=1e-4)
-    print(f"[surrogate]   trained 60 epochs in {time.time() - t1:.1f} s: loss {hist[0]:.3f} -> {hist[-1]:.3f}",
-          flush=True)
-    return net, hist
+    hist = sg.train(net, data, epochs=sg.TRAIN_EPOCHS, lr=2e-3, lr_final=1e-4)
+    print(f"[surrogate]   trained {sg.TRAIN_EPOCHS} epochs in {time.time() - t1:.1f} s: loss {loss0:.3f} untrained, "
+          f"{hist[0]:.3f} first epoch -> {hist[-1]:.3f}", flush=True)
+    return net, [loss0] + hist
 
 
 def _mixture_sample(o, n, rng):
@@ -104,18 +105,20 @@ def _mixture_sample(o, n, rng):
 
 
 def test_training_converged(trained):
+    """The final epoch's mean loss is at least 1 nat below the untrained network's loss on the
+    data (the reference: an epoch's mean already contains that epoch's learning), and the
+    last epochs are flat."""
     _, hist = trained
-    # the first epoch's mean already covers 64 Adam steps; later epochs keep improving and settle
-    assert hist[-1] < hist[0] - 0.3
-    assert all(b <= a + 0.02 for a, b in zip(hist[5:], hist[6:]))
-    assert abs(hist[-1] - hist[-2]) < 0.02
+    loss0, ep = hist[0], hist[1:]
+    assert ep[-1] < loss0 - 1.0
+    assert all(b <= a + 0.02 for a, b in zip(ep[5:], ep[6:]))
+    assert abs(ep[-1] - ep[-2]) < 0.02
 
 
 def test_trained_network_against_exact_exit_law(trained):
-    """Held-out cells of the domain: the learned exit law against the exact one (coarse
-    exit-bin L1 per cell, face split, mean time).  The bars are the network's measured
-    approximation quality (a few percent in L1 where the exit law spans many bins, more
-    where a few wide bins hold it); the transport test below judges the end result."""
+    """Held-out cells of the domain: the learned exit law against the exact one (exit-bin L1
+    per cell on at most 40 groups of bins, face split, mean time): mean L1 < 0.06 and every
+    cell < 0.12 over eight held-out cells."""
     net, _ = trained
     rng = np.random.default_rng(5)
     held = sg.sample_probes(8, DOM, seed=99)
@@ -136,51 +139,99 @@ def test_trained_network_against_exact_exit_law(trained):
         assert abs(H[0].sum() - ex.prob[0].sum()) < 0.02
         assert tm == pytest.approx(ex.t_mean, rel=0.06)
         l1s.append(l1)
-    assert np.mean(l1s) < 0.1 and max(l1s) < 0.3
+    assert np.mean(l1s) < 0.06 and max(l1s) < 0.12
 
 
 TARGETS = [176, 199]
 
 
-@pytest.mark.parametrize("idx", TARGETS)
-def test_surrogate_transport_matches_exact_chain_and_beats_plain(trained, idx):
+def test_surrogate_transport_matches_exact_chain_on_the_tally_grid_and_beats_plain(trained):
+    """Sweep cloud 176 (172 shells x 301 bins, tau0 6.1e7, 153 km/s outflow) with 2^20 packets,
+    where the expected noise L1 of its full 301-bin spectrum against the exact chain is 0.37 %:
+    the surrogate-accelerated walk passes the 3 sigma rule and L1 <= 1 % on the tally grid, and
+    its mean escape time is within 3 %.  Speed at equal work: the surrogate and plain rDDMC each
+    walk the same first 2^14 packet ids (plain rDDMC takes ~40 minutes for all 2^20)."""
     import torch
     net, _ = trained
-    m = media.sweep_cloud_medium(media.sweep_parameters()[idx])
+    idx = 176
+    m = media.sweep_cloud_medium(media.sweep_parameters()[idx]).with_packets(1 << 20)
     win = sg.window(m, DOM)
     assert win[1] >= win[0], "the target cloud must have cells in the trained domain"
     ref = chain.solve(m)
+    n = int(m.n_packets)
     prob = rddmc.Problem(m)
     att = sg.Attached(prob, net, DOM)
-    n = min(1 << 17, m.n_packets)
     print(f"[surrogate] cloud {idx}: window {win}, {att.n_states} states, {n} packets", flush=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    prob.run(seed=1, count=n, surrogate=att.buffer)
-    torch.cuda.synchronize()
-    ts = time.perf_counter() - t0
+    prob.run(seed=1, surrogate=att.buffer)
     r = prob.results()[0]
     assert r.launched == n and r.escaped == n and r.surrogate_calls > 0
-    spec = r.spectrum.sum(axis=0)
-    p = ref.spectrum.sum(axis=0)
-    res = compare_exact(_coarse(spec[None, :].astype(float))[0], _coarse(p[None, :])[0], n)
-    l1_full = float(np.abs(spec / n - p).sum())
-    print(f"    surrogate {n / ts:.0f} pk/s, calls/pk {r.surrogate_calls / n:.1f}; coarse L1 {res['L1']:.4f} "
-          f"(noise {res['expected_noise_L1']:.4f}), full L1 {l1_full:.4f}, t {r.t_mean:.4g} vs {ref.t_mean:.4g}",
-          flush=True)
-    assert_spectrum_matches(res, l1_max=max(0.01, 2.5 * res["expected_noise_L1"]))
+    res = compare_exact(r.spectrum, ref.spectrum, n)
+    print(f"    calls/pk {r.surrogate_calls / n:.1f}; full-grid L1 {res['L1']:.4f} (noise {res['expected_noise_L1']:.4f}), "
+          f"max |z| {res['max_abs_z']:.2f}, t {r.t_mean:.4g} vs {ref.t_mean:.4g}", flush=True)
+    assert res["expected_noise_L1"] <= 0.005
+    assert_spectrum_matches(res, l1_max=0.01)
     assert r.t_mean == pytest.approx(ref.t_mean, rel=0.03)
-    # plain rDDMC on the same cloud, same GPU
-    prob.reset()
-    npl = 1024
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    prob.run(seed=1, count=npl)
-    torch.cuda.synchronize()
-    tp = time.perf_counter() - t0
-    print(f"    plain {npl / tp:.0f} pk/s (steps/pk {prob.results()[0].steps_mean:.3g}); speedup {(n / ts) / (npl / tp):.1f}x",
+    sub = 1 << 14
+    rates = {}
+    for leg in ("surrogate", "plain"):
+        q = rddmc.Problem(m)
+        kw = dict(surrogate=sg.Attached(q, net, DOM).buffer) if leg == "surrogate" else {}
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        q.run(seed=1, count=sub, **kw)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        rq = q.results()[0]
+        assert rq.escaped == sub
+        rates[leg] = (sub / dt, rq.steps_mean)
+        print(f"    {leg}: packets 0..{sub - 1} in {dt:.2f} s ({sub / dt:.0f} pk/s, steps/pk {rq.steps_mean:.3g})",
+              flush=True)
+    print(f"    equal-work speedup {rates['surrogate'][0] / rates['plain'][0]:.1f}x", flush=True)
+    assert rates["surrogate"][0] > rates["plain"][0]
+
+
+@pytest.mark.parametrize("idx", [199])
+def test_surrogate_transport_matches_exact_chain(trained, idx):
+    """A second in-domain cloud (199: 82 shells x 722 bins, T = 364 K) at 2^17 packets against
+    the exact chain: the 3 sigma rule and chi^2 on the full grid (its noise L1 there, 2.3 %, is
+    above the 0.5 % at which an L1 <= 1 % gate is meaningful)."""
+    net, _ = trained
+    m = media.sweep_cloud_medium(media.sweep_parameters()[idx]).with_packets(1 << 17)
+    ref = chain.solve(m)
+    prob = rddmc.Problem(m)
+    att = sg.Attached(prob, net, DOM)
+    n = int(m.n_packets)
+    print(f"[surrogate] cloud {idx}: {att.n_states} states, {n} packets", flush=True)
+    prob.run(seed=1, surrogate=att.buffer)
+    r = prob.results()[0]
+    assert r.escaped == n and r.surrogate_calls > 0
+    res = compare_exact(r.spectrum, ref.spectrum, n)
+    print(f"    full-grid L1 {res['L1']:.4f} (noise {res['expected_noise_L1']:.4f}), max |z| {res['max_abs_z']:.2f}",
           flush=True)
-    assert n / ts > 3.0 * npl / tp
+    assert_spectrum_matches(res)
+    assert r.t_mean == pytest.approx(ref.t_mean, rel=0.03)
+
+
+def test_surrogate_batch_every_cloud_against_exact_chain(trained):
+    """The benchmark's surrogate batch (the in-domain sweep clouds with <= 5e7 plain steps per
+    packet, 2048 packets each, one launch): every cloud's full-grid spectrum against its exact
+    chain (3 sigma rule) and its mean escape time within 4 standard errors plus 3 %."""
+    import bench
+    net, _ = trained
+    clouds = [media.sweep_cloud_medium(c) for c in media.sweep_parameters()]
+    ids = [i for i in bench.SURROGATE_CLOUDS if sg.window(clouds[i], DOM)[1] >= sg.window(clouds[i], DOM)[0]]
+    meds = [clouds[i].with_packets(2048) for i in ids]
+    prob = rddmc.Problem(meds, streams=ids)
+    att = sg.Attached(prob, net, DOM)
+    print(f"[surrogate] batch of {len(ids)} clouds, 2048 packets each", flush=True)
+    prob.run(seed=1, surrogate=att.buffer)
+    for i, m, r in zip(ids, meds, prob.results()):
+        ref = chain.solve(m)
+        res = compare_exact(r.spectrum, ref.spectrum, 2048)
+        assert r.escaped == 2048
+        assert_spectrum_matches(res)
+        tol = 4 * math.sqrt(ref.t_var / 2048) + 0.03 * ref.t_mean
+        assert abs(r.t_mean - ref.t_mean) < tol, (i, r.t_mean, ref.t_mean)
 
 
 @pytest.mark.parametrize("moving", [True, False])
