@@ -298,15 +298,15 @@ def bench_surrogate(args):
     from paper_1709_10187_amd import surrogate as sg
     dom = sg.Domain(tau_min=1.0e5, tau_max=1.0e6, dx_min=0.5, dx_max=4.5)
     t0 = time.perf_counter()
-    probes = sg.sample_probes(2048, dom, seed=11)
-    log("surrogate: 2048 x 128 sub-walks")
-    data = sg.generate(probes, 128, dom, seed=12, max_steps=1 << 30)
+    probes = sg.sample_probes(sg.TRAIN_PROBES, dom, seed=11)
+    log(f"surrogate: {sg.TRAIN_PROBES} x {sg.TRAIN_PER_PROBE} sub-walks")
+    data = sg.generate(probes, sg.TRAIN_PER_PROBE, dom, seed=12, max_steps=1 << 30)
     torch.cuda.synchronize()
     t_data = time.perf_counter() - t0
     net = rddmc.Mdn(max_batch=4096, seed=0)
     t1 = time.perf_counter()
     log(f"surrogate: training on {data.n} samples")
-    hist = sg.train(net, data, epochs=60, lr=2e-3, lr_final=1e-4)
+    hist = sg.train(net, data, epochs=sg.TRAIN_EPOCHS, lr=2e-3, lr_final=1e-4)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t1
     clouds = [media.sweep_cloud_medium(c) for c in media.sweep_parameters()]

@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define RDDMC_ABI_VERSION 5
+#define RDDMC_ABI_VERSION 6
 
 typedef enum {
     RDDMC_OK = 0,
@@ -108,6 +108,14 @@ enum { RDDMC_SLAB = 0, RDDMC_SPHERE = 1, RDDMC_CART3D = 2 };
  *                number of packets in it at each census time ('bin' estimator) and the
  *                residence time in it during each interval, in units of 2^-24 length/c
  *                ('path' estimator); E_ij,n follows by the packet energy over dV dx (and dt).
+ *                Per cell and interval they also hold eq. 18's optical-depth sum, the
+ *                acceleration estimator without its energy, c, rho and dt factors: a DDMC
+ *                spatial leak of a step that stayed over [t0, t1) in (i, j), moving along
+ *                d = -1 (face 0) or +1 (face 1), adds k_ij d times the step's residence in
+ *                each interval to cell i (outward leakage) and k_i'j' d to the cell i' it
+ *                enters when it lands there in a DDMC state (i', j') (inward leakage); z
+ *                component for slabs, radial for spheres; leaks into continuous-MC states
+ *                or vacuum count for i only.
  *                1D clouds only; n_census = 0 and census = NULL for none.
  * A 1D batch in which any cloud uses x_crit, dust, emission windows or a census is walked by
  * the hybrid 1D walk.
@@ -159,11 +167,11 @@ typedef struct {
  *                packets left hands them to a cooperative walk in which a whole wave
  *                advances one packet (0 = automatic (16), < 0 = never).  Results are
  *                bit-identical either way.
- *   surrogate    1D clouds: learned escape surrogate (rddmc_surrogate_attach) or NULL for
- *                plain rDDMC; with it, a packet in a state of its cloud's surrogate window
- *                leaves the cell by one exit drawn from the learned law (checked before
- *                every step in moving clouds, at even step counts in static ones, in the
- *                lane walk and the cooperative tail walk alike).
+ *   surrogate    1D clouds: learned escape surrogate (rddmc_surrogate_attach), exact exit
+ *                kernel (rddmc_exitkernel_build) or NULL for plain rDDMC; with one, a packet
+ *                in a state of its cloud's window leaves the cell by one exit drawn from that
+ *                law (checked before every step in moving clouds, at even step counts in
+ *                static ones, in the lane walk and the cooperative tail walk alike).
  */
 typedef struct {
     uint64_t seed;
@@ -174,7 +182,7 @@ typedef struct {
     int32_t grid;
     int32_t chunk;
     int32_t tail_lanes;
-    const void *surrogate;   /* device buffer written by rddmc_surrogate_attach, or NULL */
+    const void *surrogate;   /* rddmc_surrogate_attach or rddmc_exitkernel_build buffer, or NULL */
 } rddmc_run;
 
 /* Per-cloud summary filled by rddmc_tally (FP64 host-side normalisation of the exact
@@ -215,6 +223,8 @@ typedef struct {
  *                 state (cell * n_bins + bin) at each census time, time-major.
  *   census_path[c] (with a census) int64 [n_census * n_cells * n_bins]: residence time in each
  *                 state during each census interval, units of 2^-24 length/c, interval-major.
+ *   census_accel[c] (with a census) int64 [n_census * n_cells]: eq. 18 optical-depth sums
+ *                 per cell and interval (signed), units of 2^-24, interval-major.
  * Any pointer array may be NULL to skip that output.
  */
 typedef struct {
@@ -225,9 +235,11 @@ typedef struct {
     int64_t **pixels;
     int64_t **census_bin;
     int64_t **census_path;
+    int64_t **census_accel;
 } rddmc_tally_out;
 
 #define RDDMC_CENSUS_PATH_FIX 16777216.0   /* residence-time units per length/c (2^24) */
+#define RDDMC_CENSUS_ACCEL_FIX 16777216.0  /* eq. 18 optical-depth units (2^24 per unit) */
 
 /* ---- queries ------------------------------------------------------------------------- */
 
@@ -413,6 +425,47 @@ rddmc_status rddmc_surrogate_window(const rddmc_batch *batch, const rddmc_surrog
 rddmc_status rddmc_surrogate_attach(const rddmc_batch *batch, const void *d_tables, void *d_params, void *d_work,
                                     int64_t max_batch, const rddmc_surrogate_cfg *cfg, void *d_surr, size_t bytes,
                                     void *stream);
+
+/* ---- exact per-cell exit kernel (a non-learned accelerator) ---------------------------
+ *
+ * The same hook as the learned surrogate (pass the buffer as rddmc_run.surrogate): a packet
+ * in a window state (cell i, bin j) of a pure-DDMC 1D cloud leaves cell i by one exit drawn
+ * from the EXACT law of its in-cell walk (Sec. 2.3: the frequency moves of eq. 11 between
+ * the cell's bins until the first spatial leak).  With A = I - Q the in-cell jump matrix,
+ * built from the walk's own integer event thresholds, the exit (face f, exit bin j') has
+ * probability [A^-T e_j](j') p_f(j'); the time spent is drawn from the lognormal whose mean
+ * and second moment are the exact conditional ones, E[T | j'] and E[T^2 | j'] (two more
+ * transposed solves with D = diag(1/K)).  The leak from (i, j') then happens as in a walk
+ * step (x uniform in the bin, the Doppler map of eq. 20).  Escape spectra are therefore the
+ * plain walk's in law; escape-time means and variances are exact, the time distribution's
+ * shape within a cell approximate.  FP64 solves whose eliminations add only non-negative
+ * terms (pivots in Grassmann-Taksar-Heyman form), so cells with leak probabilities of 1e-12
+ * per step are solved to full precision.
+ *
+ * Window of a cloud: its interior cells (slab: 1 .. nc-2; sphere: 0 .. nc-2) x the contiguous
+ * bins around the longest expected sub-walk in which every window cell's expected sub-walk is
+ * at least min_steps steps.  A row keeps the exit bins whose leak probability reaches `tail`
+ * (the kept law renormalised; 24 bytes per kept bin). */
+typedef struct {
+    double min_steps;          /* >= 1: shortest expected sub-walk worth one exit draw            */
+    double tail;               /* in [0, 1e-6]: exit bins below this probability are dropped     */
+} rddmc_exitkernel_cfg;
+
+/* Device scratch (256-byte aligned, caller-owned) that the two calls below need. */
+rddmc_status rddmc_exitkernel_scratch_bytes(const rddmc_batch *batch, size_t *bytes);
+
+/* Solve the windows' chains and report the buffer size, the number of window states and,
+ * if h_windows != NULL, each cloud's window {i_lo, i_hi, j_lo, j_hi} (empty: i_hi < i_lo).
+ * d_tables from rddmc_build_leakage.  Synchronises.
+ * Errors: EINVAL, ESIZE (scratch), EUNSUPPORTED (3D or hybrid batch), ENUMERIC, EHIP. */
+rddmc_status rddmc_exitkernel_bytes(const rddmc_batch *batch, const void *d_tables, const rddmc_exitkernel_cfg *cfg,
+                                    void *d_scratch, size_t scratch_bytes, size_t *bytes, uint64_t *n_states,
+                                    int32_t *h_windows, void *stream);
+
+/* Write the exit kernel into d_ek (>= rddmc_exitkernel_bytes, 256-byte aligned, caller-owned;
+ * the same cfg).  Synchronises.  Errors: as rddmc_exitkernel_bytes, ESIZE for d_ek. */
+rddmc_status rddmc_exitkernel_build(const rddmc_batch *batch, const void *d_tables, const rddmc_exitkernel_cfg *cfg,
+                                    void *d_scratch, size_t scratch_bytes, void *d_ek, size_t bytes, void *stream);
 
 /* ---- learned escape surrogate: mixture-density network --------------------------------
  *

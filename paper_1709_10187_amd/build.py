@@ -12,7 +12,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "librddmc.so")
-SOURCES = ["capi.hip", "build.hip", "transport.hip", "transport3d.hip", "transport1dh.hip", "mdn.hip", "surrogate.hip"]
+SOURCES = ["capi.hip", "build.hip", "transport.hip", "transport3d.hip", "transport1dh.hip", "mdn.hip", "surrogate.hip",
+           "exitkernel.hip"]
 ARCH = os.environ.get("RDDMC_OFFLOAD_ARCH", "gfx950")
 
 

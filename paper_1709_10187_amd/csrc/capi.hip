@@ -327,7 +327,8 @@ rddmc_status make_layout(const rddmc_batch *b, Layout &L)
         if (c.n_census > 0) {
             c.census_bin_off = c.tally_words;
             c.census_path_off = c.census_bin_off + (uint64_t)(c.n_census + 1) * c.n_states;
-            c.tally_words = c.census_path_off + (uint64_t)c.n_census * c.n_states;
+            c.census_accel_off = c.census_path_off + (uint64_t)c.n_census * c.n_states;
+            c.tally_words = c.census_accel_off + (uint64_t)c.n_census * c.nc;
         }
         tally += c.tally_words;
     }
@@ -613,6 +614,8 @@ rddmc_status rddmc_tally(const rddmc_batch *batch, const void *d_tally, size_t t
             std::memcpy(out->census_bin[ci], w + c.census_bin_off, 8ull * (c.n_census + 1) * c.n_states);
         if (c.n_census > 0 && out->census_path && out->census_path[ci])
             std::memcpy(out->census_path[ci], w + c.census_path_off, 8ull * c.n_census * c.n_states);
+        if (c.n_census > 0 && out->census_accel && out->census_accel[ci])
+            std::memcpy(out->census_accel[ci], w + c.census_accel_off, 8ull * c.n_census * c.nc);
     }
     return RDDMC_OK;
 }
@@ -854,6 +857,213 @@ rddmc_status rddmc_surrogate_samples(const rddmc_batch *batch, const void *d_tab
                            reinterpret_cast<unsigned long long *>(d_steps), s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);   // the host start arrays are read asynchronously
     return e == hipSuccess ? RDDMC_OK : hip_fail(e, "sub-walk kernel");
+}
+
+/* ---- exact per-cell exit kernel -------------------------------------------------------- */
+
+namespace {
+
+constexpr uint64_t kEkChunk = 4096;   // window states per row-kernel launch
+constexpr int kEkArraysHost = 7;      // per-bin chain arrays per cell (exitkernel.hip)
+
+struct EkPlan {
+    SurrHeader h{};
+    std::vector<SurrCloud> clouds;
+    std::vector<ExitRec> recs;
+    uint64_t bytes = 0;
+};
+
+struct EkScratch {
+    uint64_t cb = 0, mn = 0, sc = 0, sp = 0, total = 0;   // offsets and size
+};
+
+EkScratch ek_scratch_layout(const Layout &L)
+{
+    EkScratch S;
+    uint64_t need_cb = 0, need_nb = 0;
+    for (const DevCloud &c : L.clouds) {
+        need_cb = std::max<uint64_t>(need_cb, 8ull * kEkArraysHost * c.nc * c.nb);
+        need_nb = std::max<uint64_t>(need_nb, (uint64_t)c.nb);
+    }
+    S.cb = 0;
+    S.mn = align_up(need_cb);
+    S.sc = align_up(S.mn + 8ull * need_nb);
+    S.sp = align_up(S.sc + 24ull * need_nb * kEkChunk);
+    S.total = align_up(S.sp + 8ull * kEkChunk);
+    return S;
+}
+
+rddmc_status ek_check(const rddmc_batch *b, const rddmc_exitkernel_cfg *cfg, Layout &L)
+{
+    if (!cfg) return fail(RDDMC_EINVAL, "cfg is NULL");
+    if (!(cfg->min_steps >= 1.0) || !std::isfinite(cfg->min_steps))
+        return fail(RDDMC_EINVAL, "min_steps must be finite and >= 1");
+    if (!(cfg->tail >= 0.0 && cfg->tail <= 1e-6)) return fail(RDDMC_EINVAL, "tail must lie in [0, 1e-6]");
+    rddmc_status st = make_layout(b, L);
+    if (st != RDDMC_OK) return st;
+    if (L.h.geometry == RDDMC_CART3D || L.h.hybrid1d)
+        return fail(RDDMC_EUNSUPPORTED, "the exit kernel runs with pure-DDMC 1D batches only");
+    return RDDMC_OK;
+}
+
+// Windows (interior cells x the contiguous bins around the longest expected sub-walk where every
+// window cell's expected sub-walk is at least min_steps) and each window state's kept exit-bin
+// span.  Runs kernels and synchronises.
+rddmc_status ek_plan(const rddmc_batch *b, const Layout &L, const void *d_tables, const rddmc_exitkernel_cfg &cfg,
+                     uint8_t *scr, const EkScratch &X, hipStream_t s, EkPlan &P)
+{
+    const int n = b->n_clouds;
+    P.clouds.assign(n, SurrCloud{0, -1, 0, -1, 0, 0});
+    P.recs.clear();
+    uint64_t row = 0;
+    double *cb = reinterpret_cast<double *>(scr + X.cb);
+    double *mn = reinterpret_cast<double *>(scr + X.mn);
+    double *sc = reinterpret_cast<double *>(scr + X.sc);
+    int2 *sp = reinterpret_cast<int2 *>(scr + X.sp);
+    const uint8_t *tb = static_cast<const uint8_t *>(d_tables);
+    hipError_t e;
+    for (int ci = 0; ci < n; ++ci) {
+        const DevCloud &c = L.clouds[ci];
+        SurrCloud w{0, -1, 0, -1, (uint64_t)P.recs.size(), 0};
+        const int i_lo = c.geometry == RDDMC_SPHERE ? 0 : 1, i_hi = c.nc - 2;
+        if (i_hi >= i_lo) {
+            if ((e = launch_ek_prep(tb, c, cb, s)) != hipSuccess) return hip_fail(e, "exit kernel: chain arrays");
+            if ((e = launch_ek_minsteps(cb, c.nc, c.nb, i_lo, i_hi, mn, s)) != hipSuccess)
+                return hip_fail(e, "exit kernel: sub-walk lengths");
+            std::vector<double> h(c.nb);
+            if ((e = hipMemcpyAsync(h.data(), mn, 8ull * c.nb, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+                (e = hipStreamSynchronize(s)) != hipSuccess)
+                return hip_fail(e, "exit kernel: sub-walk lengths read-back");
+            int j0 = 0;
+            for (int j = 1; j < c.nb; ++j)
+                if (h[j] > h[j0]) j0 = j;
+            if (h[j0] >= cfg.min_steps) {
+                int jl = j0, jh = j0;
+                while (jl > 0 && h[jl - 1] >= cfg.min_steps) --jl;
+                while (jh < c.nb - 1 && h[jh + 1] >= cfg.min_steps) ++jh;
+                w.i_lo = i_lo;
+                w.i_hi = i_hi;
+                w.j_lo = jl;
+                w.j_hi = jh;
+                const int nj = jh - jl + 1;
+                const uint64_t nst = (uint64_t)(i_hi - i_lo + 1) * nj;
+                std::vector<int2> span(kEkChunk);
+                for (uint64_t q0 = 0; q0 < nst; q0 += kEkChunk) {
+                    const uint64_t cnt = std::min<uint64_t>(kEkChunk, nst - q0);
+                    if ((e = launch_ek_rows(cb, c.nc, c.nb, i_lo, jl, nj, q0, cnt, cfg.tail, sc, sp, nullptr, nullptr,
+                                            s)) != hipSuccess)
+                        return hip_fail(e, "exit kernel: row spans");
+                    if ((e = hipMemcpyAsync(span.data(), sp, 8ull * cnt, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+                        (e = hipStreamSynchronize(s)) != hipSuccess)
+                        return hip_fail(e, "exit kernel: row spans read-back");
+                    for (uint64_t t = 0; t < cnt; ++t) {
+                        const int m = span[t].y;
+                        if (m < 1 || span[t].x < 0 || span[t].x + m > c.nb)
+                            return fail(RDDMC_ENUMERIC, "exit kernel: cloud %d has an empty exit law", ci);
+                        P.recs.push_back(ExitRec{row, span[t].x, m});
+                        row += 24ull * m;
+                    }
+                }
+            }
+        }
+        P.clouds[ci] = w;
+    }
+    P.h.n_clouds = n;
+    P.h.kind = kSurrExact;
+    P.h.off_clouds = align_up(sizeof(SurrHeader));
+    P.h.off_records = align_up(P.h.off_clouds + sizeof(SurrCloud) * n);
+    P.h.n_records = P.recs.size();
+    P.h.off_rows = align_up(P.h.off_records + sizeof(ExitRec) * P.recs.size());
+    P.bytes = P.h.off_rows + row;
+    return RDDMC_OK;
+}
+
+}  // namespace
+
+rddmc_status rddmc_exitkernel_scratch_bytes(const rddmc_batch *batch, size_t *bytes)
+{
+    if (!bytes) return fail(RDDMC_EINVAL, "bytes is NULL");
+    Layout L;
+    rddmc_status st = make_layout(batch, L);
+    if (st != RDDMC_OK) return st;
+    *bytes = ek_scratch_layout(L).total;
+    return RDDMC_OK;
+}
+
+rddmc_status rddmc_exitkernel_bytes(const rddmc_batch *batch, const void *d_tables, const rddmc_exitkernel_cfg *cfg,
+                                    void *d_scratch, size_t scratch_bytes, size_t *bytes, uint64_t *n_states,
+                                    int32_t *h_windows, void *stream)
+{
+    Layout L;
+    rddmc_status st = ek_check(batch, cfg, L);
+    if (st != RDDMC_OK) return st;
+    if (!d_tables || !d_scratch || !bytes) return fail(RDDMC_EINVAL, "NULL argument");
+    const EkScratch X = ek_scratch_layout(L);
+    if ((uintptr_t)d_scratch % kAlign) return fail(RDDMC_EINVAL, "d_scratch must be 256-byte aligned");
+    if (scratch_bytes < X.total)
+        return fail(RDDMC_ESIZE, "scratch %zu < required %llu", scratch_bytes, (unsigned long long)X.total);
+    EkPlan P;
+    st = ek_plan(batch, L, d_tables, *cfg, static_cast<uint8_t *>(d_scratch), X, reinterpret_cast<hipStream_t>(stream),
+                 P);
+    if (st != RDDMC_OK) return st;
+    *bytes = P.bytes;
+    if (n_states) *n_states = P.h.n_records;
+    if (h_windows)
+        for (int c = 0; c < batch->n_clouds; ++c) {
+            h_windows[4 * c + 0] = P.clouds[c].i_lo;
+            h_windows[4 * c + 1] = P.clouds[c].i_hi;
+            h_windows[4 * c + 2] = P.clouds[c].j_lo;
+            h_windows[4 * c + 3] = P.clouds[c].j_hi;
+        }
+    return RDDMC_OK;
+}
+
+rddmc_status rddmc_exitkernel_build(const rddmc_batch *batch, const void *d_tables, const rddmc_exitkernel_cfg *cfg,
+                                    void *d_scratch, size_t scratch_bytes, void *d_ek, size_t bytes, void *stream)
+{
+    Layout L;
+    rddmc_status st = ek_check(batch, cfg, L);
+    if (st != RDDMC_OK) return st;
+    if (!d_tables || !d_scratch || !d_ek) return fail(RDDMC_EINVAL, "NULL argument");
+    if ((uintptr_t)d_scratch % kAlign || (uintptr_t)d_ek % kAlign)
+        return fail(RDDMC_EINVAL, "d_scratch and d_ek must be 256-byte aligned");
+    const EkScratch X = ek_scratch_layout(L);
+    if (scratch_bytes < X.total)
+        return fail(RDDMC_ESIZE, "scratch %zu < required %llu", scratch_bytes, (unsigned long long)X.total);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    uint8_t *scr = static_cast<uint8_t *>(d_scratch);
+    EkPlan P;
+    st = ek_plan(batch, L, d_tables, *cfg, scr, X, s, P);
+    if (st != RDDMC_OK) return st;
+    if (bytes < P.bytes)
+        return fail(RDDMC_ESIZE, "exit-kernel buffer %zu < required %llu", bytes, (unsigned long long)P.bytes);
+    uint8_t *base = static_cast<uint8_t *>(d_ek);
+    std::vector<uint8_t> hdr(P.h.off_rows, 0);
+    std::memcpy(hdr.data(), &P.h, sizeof P.h);
+    std::memcpy(hdr.data() + P.h.off_clouds, P.clouds.data(), sizeof(SurrCloud) * P.clouds.size());
+    if (!P.recs.empty()) std::memcpy(hdr.data() + P.h.off_records, P.recs.data(), sizeof(ExitRec) * P.recs.size());
+    hipError_t e = hipMemcpyAsync(base, hdr.data(), hdr.size(), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(exit-kernel header)");
+    double *cb = reinterpret_cast<double *>(scr + X.cb);
+    double *sc = reinterpret_cast<double *>(scr + X.sc);
+    const uint8_t *tb = static_cast<const uint8_t *>(d_tables);
+    const ExitRec *recs = reinterpret_cast<const ExitRec *>(base + P.h.off_records);
+    for (int ci = 0; ci < batch->n_clouds; ++ci) {
+        const SurrCloud &w = P.clouds[ci];
+        if (w.i_hi < w.i_lo) continue;
+        const DevCloud &c = L.clouds[ci];
+        if ((e = launch_ek_prep(tb, c, cb, s)) != hipSuccess) return hip_fail(e, "exit kernel: chain arrays");
+        const int nj = w.j_hi - w.j_lo + 1;
+        const uint64_t nst = (uint64_t)(w.i_hi - w.i_lo + 1) * nj;
+        for (uint64_t q0 = 0; q0 < nst; q0 += kEkChunk) {
+            const uint64_t cnt = std::min<uint64_t>(kEkChunk, nst - q0);
+            if ((e = launch_ek_rows(cb, c.nc, c.nb, w.i_lo, w.j_lo, nj, q0, cnt, cfg->tail, sc, nullptr,
+                                    recs + w.rec_off, base + P.h.off_rows, s)) != hipSuccess)
+                return hip_fail(e, "exit kernel: rows");
+        }
+    }
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    return RDDMC_OK;
 }
 
 /* ---- mixture-density network of the escape surrogate --------------------------------- */

@@ -102,10 +102,12 @@ struct alignas(16) DevCloud {
     uint64_t off_src_t;          // f64 [2 n_src]: emission window per source entry (0 = flash)
     uint64_t off_census;         // f64 [n_census + 1] census times
     uint64_t census_bin_off;     // int64 word offsets (in the cloud's tally block) of the 'bin'
-    uint64_t census_path_off;    //   counts [(n_census+1) n_states] and 'path' times [n_census n_states]
+    uint64_t census_path_off;    //   counts [(n_census+1) n_states], 'path' times [n_census n_states]
+    uint64_t census_accel_off;   //   and eq. 18 sums [n_census nc]
 };
 
 constexpr double kPathFix = RDDMC_CENSUS_PATH_FIX;   // residence-time fixed point (2^24 per length/c)
+constexpr double kAccelFix = RDDMC_CENSUS_ACCEL_FIX; // eq. 18 optical-depth fixed point (2^24)
 
 struct alignas(16) DevHeader {
     int32_t n_clouds;

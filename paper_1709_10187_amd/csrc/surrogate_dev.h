@@ -36,13 +36,35 @@ struct alignas(16) SurrCloud {
     uint64_t pad;
 };
 
+constexpr int32_t kSurrMdn = 0;     // records: learned mixture laws (kSurrRec floats each)
+constexpr int32_t kSurrExact = 1;   // records: ExitRec headers of exact exit-kernel rows
+
 struct alignas(16) SurrHeader {
     int32_t n_clouds;
-    int32_t pad;
+    int32_t kind;            // kSurrMdn or kSurrExact
     uint64_t off_clouds;     // SurrCloud [n_clouds]
-    uint64_t off_records;    // float [n_records * kSurrRec]
+    uint64_t off_records;    // kSurrMdn: float [n_records * kSurrRec]; kSurrExact: ExitRec [n_records]
     uint64_t n_records;
+    uint64_t off_rows;       // kSurrExact: the row pool (ExitRec.row_off is relative to it)
+    uint64_t pad;
 };
+
+// Exact exit-kernel row of one window state: 2m doubles, the CDF over (face 0, exit bins
+// j_lo .. j_lo+m-1) then (face 1, the same bins), then m float2 {mu, sigma} of the lognormal
+// exit time given the exit bin.
+struct ExitRec {
+    uint64_t row_off;        // bytes from SurrHeader.off_rows
+    int32_t j_lo, m;
+};
+
+// Exit-kernel builders (exitkernel.hip): per-cell chain arrays d_cb (7 nb nc doubles), the
+// per-bin minimum of the expected sub-walk length over cells [i_lo, i_hi], and per window
+// state either the kept exit-bin span (d_rows == nullptr) or the row.
+hipError_t launch_ek_prep(const uint8_t *d_tables, const DevCloud &c, double *d_cb, hipStream_t s);
+hipError_t launch_ek_minsteps(const double *d_cb, int nc, int nb, int i_lo, int i_hi, double *d_out, hipStream_t s);
+hipError_t launch_ek_rows(const double *d_cb, int nc, int nb, int i_lo, int j_lo, int nj, uint64_t q0, uint64_t cnt,
+                          double tail, double *d_scratch, int2 *d_span, const ExitRec *d_recs, uint8_t *d_rows,
+                          hipStream_t s);
 
 __device__ inline void surr_features(const DevCloud &c, const uint8_t *tb, int i, int j, float *f, float &S,
                                      float &w)

@@ -179,8 +179,8 @@ __device__ __forceinline__ bool in_window(const Packet1D &p, const SurrWin &w)
 // Philox pair slot (the step count is rounded up to even, then advanced by 2), drawn in
 // its own counter domain.
 template <bool MOVING>
-__device__ void surrogate_exit(Packet1D &p, const SurrWin &sw, const float *__restrict__ recs,
-                               const uint8_t *__restrict__ tb, const DevCloud &c, const WalkArgs &a)
+__device__ void mdn_exit(Packet1D &p, const SurrWin &sw, const float *__restrict__ recs,
+                         const uint8_t *__restrict__ tb, const DevCloud &c, const WalkArgs &a)
 {
     p.steps = (p.steps + 1ull) & ~1ull;
     const uint64_t pair = p.steps >> 1;
@@ -258,6 +258,52 @@ __device__ __forceinline__ void rebin(Packet1D &p, int face, float4 cm, uint32_t
         jn = locate_bin(e, p.nb, (double)rho * x + (double)sh);
     }
     p.j = jn < 0 ? 0 : (jn > p.nb - 1 ? p.nb - 1 : jn);
+}
+
+// Replace the rest of the packet's walk inside its cell by one exit drawn from the exact law of
+// its in-cell walk (the exact exit kernel, same window and check points as the learned
+// surrogate): (face, exit bin) from the state's row CDF with a 53-bit uniform, then the spatial
+// leak from the exit bin exactly as a walk step takes it (x uniform in the bin and the Doppler
+// map of eq. 20 in moving clouds), and the time from the lognormal with the exact conditional
+// mean and second moment.  One Philox block in the surrogate's counter domain per exit.
+template <bool MOVING>
+__device__ void exact_exit(Packet1D &p, const SurrWin &sw, const uint8_t *__restrict__ tb, const DevCloud &c,
+                           const WalkArgs &a)
+{
+    p.steps = (p.steps + 1ull) & ~1ull;
+    const uint64_t pair = p.steps >> 1;
+    const u32x4 r = philox4x32_10((uint32_t)pair, kDomSurr | (uint32_t)(pair >> 32), p.pid, p.key, a.key0, a.key1);
+    const SurrHeader *SH = reinterpret_cast<const SurrHeader *>(a.surr);
+    const int64_t idx = (int64_t)sw.rec_off + (int64_t)(p.i - sw.i_lo) * (sw.j_hi - sw.j_lo + 1) + (p.j - sw.j_lo);
+    const ExitRec er = reinterpret_cast<const ExitRec *>(a.surr + SH->off_records)[idx];
+    const double *cdf = reinterpret_cast<const double *>(a.surr + SH->off_rows + er.row_off);
+    const double u = (double)(((uint64_t)r.x << 21) | (r.y >> 11)) * 1.1102230246251565e-16;   // [0, 1), 2^-53
+    int lo = 0, hi = 2 * er.m - 1;   // first outcome whose CDF exceeds u (the last is 1)
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (u < cdf[mid]) hi = mid; else lo = mid + 1;
+    }
+    const int face = lo >= er.m ? 1 : 0;
+    const int k = lo - face * er.m;
+    const float2 tp = reinterpret_cast<const float2 *>(cdf + 2 * er.m)[k];
+    const float zn = normcdfinvf(((float)(r.w >> 8) + 0.5f) * 5.9604644775390625e-8f);
+    p.t += (double)__expf(fmaf(tp.y, zn, tp.x));
+    p.j = er.j_lo + k;
+    if (MOVING && p.moving) rebin(p, face, p.cmap[p.i], r.z, c, tb);
+    p.i += face ? 1 : -1;
+    p.steps += 2ull;
+    ++p.surr_calls;
+}
+
+// A cell exit from the surrogate buffer: the learned law or the exact kernel.
+template <bool MOVING>
+__device__ __forceinline__ void surrogate_exit(Packet1D &p, const SurrWin &sw, const float *__restrict__ recs,
+                                               const uint8_t *__restrict__ tb, const DevCloud &c, const WalkArgs &a)
+{
+    if (reinterpret_cast<const SurrHeader *>(a.surr)->kind == kSurrExact)
+        exact_exit<MOVING>(p, sw, tb, c, a);
+    else
+        mdn_exit<MOVING>(p, sw, recs, tb, c, a);
 }
 
 // Rare path of a step: the event word tied with a threshold's high word (resolved with an

@@ -193,6 +193,26 @@ __device__ void census_add(const DevCloud &c, const uint8_t *__restrict__ tb, un
     }
 }
 
+// Eq. 18: a leak of a step that stayed over [t0, t1) adds v times its residence in each census
+// interval to `cell` (signed fixed point, 2^-24).
+__device__ void accel_add(const DevCloud &c, const uint8_t *__restrict__ tb, unsigned long long *__restrict__ tally,
+                          int cell, double t0, double t1, double v)
+{
+    const double *ct = reinterpret_cast<const double *>(tb + c.off_census);
+    const int n = c.n_census;
+    int lo = 0, hi = n + 1;   // first census time >= t0
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (ct[mid] < t0) lo = mid + 1; else hi = mid;
+    }
+    unsigned long long *w = tally + c.tally_off + c.census_accel_off;
+    for (int i = lo > 0 ? lo - 1 : 0; i < n && ct[i] < t1; ++i) {
+        const double a0 = fmax(t0, ct[i]), b0 = fmin(t1, ct[i + 1]);
+        if (b0 > a0)
+            atomicAdd(&w[(uint64_t)i * c.nc + cell], (unsigned long long)(long long)rint(v * (b0 - a0) * kAccelFix));
+    }
+}
+
 __device__ void finish1(Pk1 &p, const DevCloud &c, unsigned long long *__restrict__ tally, bool escaped, int row,
                         int slot, bool absorbed = false)
 {
@@ -239,6 +259,7 @@ __device__ void ddmc_step1(Pk1 &p, const DevCloud &c, const uint8_t *__restrict_
     const uint32_t tw = draw(p.r, a), ew = draw(p.r, a);
     const double dl = (double)ddmc_path(tw, __uint_as_float(rec.x));
     if (c.n_census > 0) census_add(c, tb, tally, s, p.t, p.t + dl);
+    const double t0 = p.t;
     p.t += dl;
     int ev;
     bool have_lo = false;
@@ -287,6 +308,9 @@ __device__ void ddmc_step1(Pk1 &p, const DevCloud &c, const uint8_t *__restrict_
     // spatial leak: face 0 or 1 from the state's split
     const uint32_t v = draw(p.r, a) >> 1;
     const int f = v >= reinterpret_cast<const uint32_t *>(tb + c.off_face_split)[s] ? 1 : 0;
+    const double *kt = reinterpret_cast<const double *>(tb + c.off_k);
+    const double dir = f ? 1.0 : -1.0;
+    if (c.n_census > 0) accel_add(c, tb, tally, p.cell, t0, p.t, dir * kt[s]);   // outward leakage (eq. 18)
     const float xin = bin_x(c, tb, p.j, uf(draw(p.r, a)));
     const int nbc = neighbour1(c, p.cell, f);
     const float4 *mcell = reinterpret_cast<const float4 *>(tb + c.off_mcell);
@@ -320,6 +344,7 @@ __device__ void ddmc_step1(Pk1 &p, const DevCloud &c, const uint8_t *__restrict_
         }
     }
     p.cell = nbc;
+    bool ddmc_in = true;
     if (c.moving) {
         const uint4 rn = reinterpret_cast<const uint4 *>(tb + c.off_hot)[(int64_t)p.cell * nb + p.j];
         if (!(rn.w & kFlagThick)) {   // re-binned into a thin state: MC in the new cell
@@ -329,8 +354,11 @@ __device__ void ddmc_step1(Pk1 &p, const DevCloud &c, const uint8_t *__restrict_
             p.x = xs;
             p.mc = true;
             ++p.tomc;
+            ddmc_in = false;
         }
     }
+    if (c.n_census > 0 && ddmc_in)   // inward leakage into a DDMC state (eq. 18)
+        accel_add(c, tb, tally, p.cell, t0, p.t, dir * kt[(int64_t)p.cell * nb + p.j]);
 }
 
 // One continuous-MC event (a scattering or a boundary crossing) of a packet in a thin state.

@@ -59,6 +59,10 @@ class SurrogateCfg_t(C.Structure):
                 ("g_min", C.c_double), ("g_max", C.c_double), ("x_core", C.c_double)]
 
 
+class ExitKernelCfg_t(C.Structure):
+    _fields_ = [("min_steps", C.c_double), ("tail", C.c_double)]
+
+
 class CloudStats_t(C.Structure):
     _fields_ = [("launched", C.c_uint64), ("escaped", C.c_uint64), ("capped", C.c_uint64),
                 ("steps_total", C.c_uint64), ("steps_max", C.c_uint64), ("steps_mean", C.c_double),
@@ -72,18 +76,20 @@ class TallyOut_t(C.Structure):
     _fields_ = [("spectrum", C.POINTER(C.c_void_p)), ("time_hist", C.POINTER(C.c_void_p)),
                 ("step_hist", C.POINTER(C.c_void_p)), ("stats", C.POINTER(CloudStats_t)),
                 ("pixels", C.POINTER(C.c_void_p)), ("census_bin", C.POINTER(C.c_void_p)),
-                ("census_path", C.POINTER(C.c_void_p))]
+                ("census_path", C.POINTER(C.c_void_p)), ("census_accel", C.POINTER(C.c_void_p))]
 
 
-ABI_VERSION = 5
+ABI_VERSION = 6
 CENSUS_PATH_FIX = float(1 << 24)   # residence-time units per length/c
+CENSUS_ACCEL_FIX = float(1 << 24)  # eq. 18 optical-depth units
 
 
 EXPORTS = ["rddmc_abi_version", "rddmc_last_error", "rddmc_table_bytes", "rddmc_tally_bytes",
            "rddmc_work_bytes", "rddmc_build_leakage", "rddmc_transport", "rddmc_transport_static", "rddmc_tally_reset",
            "rddmc_tally", "rddmc_read_tables", "rddmc_philox_fill", "rddmc_mdn_bytes", "rddmc_mdn_init",
            "rddmc_mdn_set", "rddmc_mdn_get", "rddmc_mdn_forward", "rddmc_mdn_loss_grad", "rddmc_mdn_adam",
-           "rddmc_surrogate_samples", "rddmc_surrogate_bytes", "rddmc_surrogate_window", "rddmc_surrogate_attach"]
+           "rddmc_surrogate_samples", "rddmc_surrogate_bytes", "rddmc_surrogate_window", "rddmc_surrogate_attach",
+           "rddmc_exitkernel_scratch_bytes", "rddmc_exitkernel_bytes", "rddmc_exitkernel_build"]
 
 _lib = None
 
@@ -125,11 +131,17 @@ def load(path: str = LIB_PATH):
                                           C.POINTER(C.c_uint64)]
     lib.rddmc_surrogate_window.argtypes = [C.POINTER(Batch_t), cfgp, C.c_int32, vp]
     lib.rddmc_surrogate_attach.argtypes = [C.POINTER(Batch_t), vp, vp, vp, C.c_int64, cfgp, vp, sz, vp]
+    ekp = C.POINTER(ExitKernelCfg_t)
+    lib.rddmc_exitkernel_scratch_bytes.argtypes = [C.POINTER(Batch_t), C.POINTER(sz)]
+    lib.rddmc_exitkernel_bytes.argtypes = [C.POINTER(Batch_t), vp, ekp, vp, sz, C.POINTER(sz), C.POINTER(C.c_uint64),
+                                           vp, vp]
+    lib.rddmc_exitkernel_build.argtypes = [C.POINTER(Batch_t), vp, ekp, vp, sz, vp, sz, vp]
     for name in ("rddmc_build_leakage", "rddmc_transport", "rddmc_transport_static", "rddmc_tally_reset", "rddmc_tally",
                  "rddmc_read_tables", "rddmc_philox_fill", "rddmc_mdn_bytes", "rddmc_mdn_init",
                  "rddmc_mdn_set", "rddmc_mdn_get", "rddmc_mdn_forward", "rddmc_mdn_loss_grad",
                  "rddmc_mdn_adam", "rddmc_surrogate_samples", "rddmc_surrogate_bytes",
-                 "rddmc_surrogate_window", "rddmc_surrogate_attach"):
+                 "rddmc_surrogate_window", "rddmc_surrogate_attach", "rddmc_exitkernel_scratch_bytes",
+                 "rddmc_exitkernel_bytes", "rddmc_exitkernel_build"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -278,6 +290,7 @@ class CloudTally:
     absorbed: int = 0
     census_bin: Optional[np.ndarray] = None    # (n_census+1, cells, bins) int64 packets per state at t_e
     census_path: Optional[np.ndarray] = None   # (n_census, cells, bins) int64 residence, 2^-24 units
+    census_accel: Optional[np.ndarray] = None  # (n_census, cells) int64 eq. 18 optical-depth sums, 2^-24 units
 
 
 def n_pixels(m) -> int:
@@ -303,10 +316,13 @@ def tally(b: Batch, d_tally, stream=None) -> List[CloudTally]:
           for k, m in zip(ncen, b.meds)]
     cp = [np.zeros((k, m.n_cells_total, m.n_bins), dtype=np.int64) if k else np.zeros(0, dtype=np.int64)
           for k, m in zip(ncen, b.meds)]
+    ca = [np.zeros((k, m.n_cells_total), dtype=np.int64) if k else np.zeros(0, dtype=np.int64)
+          for k, m in zip(ncen, b.meds)]
     cb_ptrs = (C.c_void_p * n)(*[a.ctypes.data if a.size else None for a in cb])
     cp_ptrs = (C.c_void_p * n)(*[a.ctypes.data if a.size else None for a in cp])
+    ca_ptrs = (C.c_void_p * n)(*[a.ctypes.data if a.size else None for a in ca])
     stats = (CloudStats_t * n)()
-    out = TallyOut_t(sp_ptrs, th_ptrs, sh_ptrs, stats, px_ptrs, cb_ptrs, cp_ptrs)
+    out = TallyOut_t(sp_ptrs, th_ptrs, sh_ptrs, stats, px_ptrs, cb_ptrs, cp_ptrs, ca_ptrs)
     _check(lib.rddmc_tally(b.ref(), C.c_void_p(d_tally.data_ptr()), d_tally.numel() * d_tally.element_size(),
                            C.byref(out), _stream(stream)))
     res = []
@@ -315,7 +331,8 @@ def tally(b: Batch, d_tally, stream=None) -> List[CloudTally]:
         res.append(CloudTally(specs[i], th[i], sh[i], z.launched, z.escaped, z.capped, z.steps_total,
                               z.steps_max, z.steps_mean, z.t_mean, z.t_var, z.to_mc, z.to_ddmc, z.reflected,
                               z.mc_steps, pix[i] if pix[i].size else None, z.surrogate_calls, z.absorbed,
-                              cb[i] if cb[i].size else None, cp[i] if cp[i].size else None))
+                              cb[i] if cb[i].size else None, cp[i] if cp[i].size else None,
+                              ca[i] if ca[i].size else None))
     return res
 
 
@@ -344,6 +361,31 @@ def read_tables(b: Batch, d_tables, cloud=0, want_rates=True, stream=None):
 def philox_fill(k0, k1, c0, c1, c2, c3, n, d_out, stream=None):
     lib = load()
     _check(lib.rddmc_philox_fill(k0, k1, c0, c1, c2, c3, n, C.c_void_p(d_out.data_ptr()), _stream(stream)))
+
+
+class ExitKernel:
+    """The exact per-cell exit kernel of a Problem's batch (rddmc_exitkernel_*); pass
+    ``.buffer`` as ``run(surrogate=...)``.  ``windows`` lists each cloud's (i_lo, i_hi, j_lo, j_hi)."""
+
+    def __init__(self, problem, min_steps: float = 64.0, tail: float = 1e-13, stream=None):
+        import torch
+        lib = load()
+        b = problem.batch
+        self.cfg = ExitKernelCfg_t(float(min_steps), float(tail))
+        sb = C.c_size_t()
+        _check(lib.rddmc_exitkernel_scratch_bytes(b.ref(), C.byref(sb)))
+        scratch = torch.empty(max(int(sb.value), 256), dtype=torch.uint8, device=problem.tables.device)
+        nbytes, nst = C.c_size_t(), C.c_uint64()
+        win = np.zeros(4 * len(b.meds), dtype=np.int32)
+        _check(lib.rddmc_exitkernel_bytes(b.ref(), C.c_void_p(problem.tables.data_ptr()), C.byref(self.cfg),
+                                          C.c_void_p(scratch.data_ptr()), sb.value, C.byref(nbytes), C.byref(nst),
+                                          win.ctypes.data, _stream(stream)))
+        self.n_states = int(nst.value)
+        self.windows = [tuple(int(v) for v in win[4 * c:4 * c + 4]) for c in range(len(b.meds))]
+        self.buffer = torch.empty(max(int(nbytes.value), 256), dtype=torch.uint8, device=problem.tables.device)
+        _check(lib.rddmc_exitkernel_build(b.ref(), C.c_void_p(problem.tables.data_ptr()), C.byref(self.cfg),
+                                          C.c_void_p(scratch.data_ptr()), sb.value,
+                                          C.c_void_p(self.buffer.data_ptr()), nbytes.value, _stream(stream)))
 
 
 class Problem:

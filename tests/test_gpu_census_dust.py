@@ -139,3 +139,56 @@ def test_hybrid_dust_census_against_oracle_walker():
     sel = q * no >= 10
     print(f"    census two-sample max |z| {z[sel].max():.2f} over {sel.sum()} cells", flush=True)
     assert z[sel].max() < 5 and np.sum(z[sel] > 3) <= 2
+
+
+def _accel_batches(m, n, seeds):
+    p = rddmc.Problem(m.with_packets(n))
+    out = []
+    for sd in seeds:
+        p.reset()
+        p.run(seed=sd)
+        g = p.results()[0]
+        assert g.escaped + g.absorbed + g.capped == n
+        out.append(g.census_accel / rddmc.CENSUS_ACCEL_FIX / n)
+    out = np.array(out)
+    return out.mean(axis=0), out.std(axis=0, ddof=1) / math.sqrt(len(out))
+
+
+@pytest.mark.parametrize("m", [media.sphere(400.0, 1e4, 4, 10, x_max=6.0, v_max=25.0),
+                               media.slab(200.0, 1e4, 5, 8, x_max=5.0)], ids=["sphere_outflow", "slab"])
+def test_acceleration_estimator_matches_exact_chain(m):
+    """Eq. 18's optical-depth sums per cell and census interval (outward and inward leakage
+    along the motion) against the chain's exact expectation: eight independent seeds of 2^17
+    packets give the standard error; every cell within 5 of them."""
+    ref = chain.solve(m)
+    edges = np.array([0.0, 0.3, 1.0, 3.0, 10.0]) * ref.t_mean
+    m = m.replace(census=edges)
+    ex = chain.transient(m, edges).accel
+    print(f"[census/dust] eq. 18 on {m.name}: 8 x 2^17 packets", flush=True)
+    mean, se = _accel_batches(m, 1 << 17, range(21, 29))
+    z = np.abs(mean - ex) / np.maximum(se, 1e-12)
+    print(f"    max |z| {z.max():.2f}", flush=True)
+    assert np.all(np.abs(mean - ex) <= 5.0 * se + 1e-7 * np.abs(ex).max())
+
+
+def test_acceleration_grey_slab_net_crossings():
+    """Steady eq. 18 on a grey slab whose every state has the same total rate K (vacuum faces
+    leak at the interior rate): cell i collects (k/K)(2 P_top - 1{m > i} - 1{m >= i}) for a
+    walk from cell m, P_top = m / (N + 1)."""
+    N, start = 9, 3
+    k = 50.0
+    m0 = media.slab(k, 1e4, N, 1, x_max=1.0)
+    dz = 2.0 / N
+    t = tb.build(m0)
+    kbin = float(t.k[0, 0])
+    m = m0.replace(lam=kbin * dz / 2.0, src_pos=np.array([[-1 + dz * (start - 0.5), 0, 0]]))
+    t = tb.build(m)
+    K = float(t.K[0, 0])
+    np.testing.assert_allclose(t.K[:, 0], K, rtol=1e-12)
+    t_end = 400.0 * chain.solve(m).t_mean
+    m = m.replace(census=np.array([0.0, t_end]))
+    mean, se = _accel_batches(m, 1 << 17, range(31, 39))
+    i = np.arange(1, N + 1)
+    want = kbin / K * (2.0 * start / (N + 1.0) - (start > i) - (start >= i))
+    print(f"    grey slab: max |z| {np.max(np.abs(mean[0] - want) / se[0]):.2f}", flush=True)
+    assert np.all(np.abs(mean[0] - want) <= 5.0 * se[0] + 1e-6)

@@ -1,0 +1,163 @@
+"""GPU exact per-cell exit kernel: its rows against the single-cell exit-law oracle (O5), and
+the accelerated walk against the exact chain (O2).
+
+Bars: exit probabilities within 1e-5 relative (the tables' own FP64 parity) of O5 wherever
+they exceed 1e-7, with at most the dropped tail missing; the conditional exit-time mean and
+second moment within 2e-5 and 5e-5 relative (FP32 storage of the lognormal's parameters);
+escape spectra on the full tally grid by the 3 sigma rule and L1 <= 1 % where the noise
+allows it; mean escape time within 4 standard errors, its variance within 5 %; tallies
+bit-identical across the lane walk and the cooperative tail walk."""
+import math
+import struct
+import time
+
+import numpy as np
+import pytest
+
+from oracle import chain, exitlaw
+from oracle import tables as tb
+from paper_1709_10187_amd import media, rddmc
+from tests._stats import assert_spectrum_matches, compare_exact
+
+pytestmark = pytest.mark.gpu
+
+
+def _decode(ek):
+    """Host view of an exit-kernel buffer: {cloud: window}, and rows[(cloud, i, j)] =
+    (j_lo, cdf (2m,), mu (m,), sigma (m,))."""
+    buf = ek.buffer.cpu().numpy().tobytes()
+    n_clouds, kind, off_clouds, off_records, n_records, off_rows = struct.unpack_from("<iiQQQQ", buf, 0)
+    assert kind == 1
+    rows = {}
+    wins = {}
+    for c in range(n_clouds):
+        i_lo, i_hi, j_lo, j_hi, rec_off = struct.unpack_from("<iiiiQ", buf, off_clouds + 32 * c)
+        wins[c] = (i_lo, i_hi, j_lo, j_hi)
+        if i_hi < i_lo:
+            continue
+        nj = j_hi - j_lo + 1
+        for i in range(i_lo, i_hi + 1):
+            for j in range(j_lo, j_hi + 1):
+                q = rec_off + (i - i_lo) * nj + (j - j_lo)
+                row_off, jl, m = struct.unpack_from("<Qii", buf, off_records + 16 * q)
+                base = off_rows + row_off
+                cdf = np.frombuffer(buf, dtype=np.float64, count=2 * m, offset=base)
+                tp = np.frombuffer(buf, dtype=np.float32, count=2 * m, offset=base + 16 * m).reshape(m, 2)
+                rows[(c, i, j)] = (jl, cdf, tp[:, 0].astype(np.float64), tp[:, 1].astype(np.float64))
+    return wins, rows
+
+
+@pytest.mark.parametrize("m", [
+    media.slab(2e4, 1e4, 6, 40, x_max=10.0, vel=np.linspace(-20.0, 20.0, 6)),
+    media.sphere(3e4, 1e3, 5, 33, x_max=12.0, v_max=40.0),
+], ids=["moving_slab", "outflow_sphere"])
+def test_rows_match_the_exact_exit_law(m):
+    p = rddmc.Problem(m)
+    ek = rddmc.ExitKernel(p, min_steps=16.0, tail=1e-13)
+    wins, rows = _decode(ek)
+    i_lo, i_hi, j_lo, j_hi = wins[0]
+    print(f"[exitkernel] {m.name}: window cells {i_lo}..{i_hi}, bins {j_lo}..{j_hi}, {ek.n_states} states", flush=True)
+    assert i_hi >= i_lo and j_hi > j_lo
+    t = tb.build(m)
+    worst_p = worst_t = 0.0
+    for (c, i, j), (jl, cdf, mu, sg) in rows.items():
+        if (i + j) % 3:
+            continue                      # a third of the states keeps the oracle's time short
+        ex = exitlaw.exit_law(t, i, j)
+        mm = len(mu)
+        prob = np.diff(np.concatenate([[0.0], cdf])).reshape(2, mm)
+        want = ex.prob[:, jl:jl + mm]
+        assert ex.prob.sum() - want.sum() < 1e-9      # only the dropped tail is missing
+        big = want > 1e-7
+        rel = np.abs(prob[big] - want[big] / want.sum()) / (want[big] / want.sum())
+        worst_p = max(worst_p, float(rel.max()))
+        assert np.all(rel < 1e-5), (i, j)
+        m1, m2 = exitlaw.exit_time_moments(t, i, j)
+        pj = want.sum(axis=0)
+        ok = pj > 1e-7
+        g1 = np.exp(mu + 0.5 * sg * sg)
+        g2 = np.exp(2.0 * mu + 2.0 * sg * sg)
+        e1 = np.abs(g1[ok] / m1[jl:jl + mm][ok] - 1.0)
+        e2 = np.abs(g2[ok] / m2[jl:jl + mm][ok] - 1.0)
+        worst_t = max(worst_t, float(e1.max()))
+        assert np.all(e1 < 2e-5) and np.all(e2 < 5e-5), (i, j, e1.max(), e2.max())
+    print(f"    worst relative error: probabilities {worst_p:.2e}, mean exit time {worst_t:.2e}", flush=True)
+
+
+def _check_moments(res, ref, n):
+    assert abs(res.t_mean - ref.t_mean) < 4 * math.sqrt(ref.t_var / n), (res.t_mean, ref.t_mean)
+    assert res.t_var == pytest.approx(ref.t_var, rel=max(0.05, 8 / math.sqrt(n)))
+
+
+@pytest.mark.parametrize("which", ["sphere_tau1e7_whole_job", "sweep_cloud_176"])
+def test_accelerated_walk_matches_exact_chain(which):
+    """The tau0 = 1e7 sphere's whole 2^22-packet job, and sweep cloud 176 (moving, tau0 6.1e7)
+    at 2^20 packets, with the exit kernel against the exact chain on the full tally grid."""
+    if which == "sphere_tau1e7_whole_job":
+        m = media.config_sphere()
+    else:
+        m = media.sweep_cloud_medium(media.sweep_parameters()[176]).with_packets(1 << 20)
+    ref = chain.solve(m)
+    n = int(m.n_packets)
+    p = rddmc.Problem(m)
+    t0 = time.perf_counter()
+    ek = rddmc.ExitKernel(p, min_steps=64.0)
+    import torch
+    torch.cuda.synchronize()
+    tb_s = time.perf_counter() - t0
+    print(f"[exitkernel] {m.name}: {ek.n_states} window states {ek.windows[0]}, "
+          f"{ek.buffer.numel() / 2**20:.1f} MiB, built in {tb_s:.2f} s; {n} packets", flush=True)
+    t0 = time.perf_counter()
+    p.run(seed=3, surrogate=ek.buffer)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    res = p.results()[0]
+    r = compare_exact(res.spectrum, ref.spectrum, n)
+    print(f"    {dt:.2f} s ({n / dt:.4g} packets/s), exits/pk {res.surrogate_calls / n:.4g}, steps/pk "
+          f"{res.steps_mean:.4g} (plain: {ref.steps:.4g}); L1 {r['L1']:.5f} (noise {r['expected_noise_L1']:.5f}), "
+          f"max |z| {r['max_abs_z']:.2f}; t {res.t_mean:.5g} vs {ref.t_mean:.5g}", flush=True)
+    assert res.launched == n and res.escaped == n and res.capped == 0 and res.surrogate_calls > 0
+    assert r["expected_noise_L1"] <= 0.005
+    assert_spectrum_matches(r, l1_max=0.01)
+    _check_moments(res, ref, n)
+
+
+@pytest.mark.parametrize("moving", [True, False])
+def test_exit_kernel_runs_bit_identical_across_tail_modes_and_shapes(moving):
+    c = media.sweep_parameters()[176]
+    if not moving:
+        import dataclasses
+        c = dataclasses.replace(c, v_max=0.0)
+    m = media.sweep_cloud_medium(c)
+    p = rddmc.Problem(m)
+    ek = rddmc.ExitKernel(p, min_steps=32.0)
+    out = []
+    for kw in (dict(tail_lanes=-1), dict(tail_lanes=0), dict(tail_lanes=64), dict(block=128, grid=37, chunk=5)):
+        p.reset()
+        p.run(seed=5, count=8192, surrogate=ek.buffer, **kw)
+        r = p.results()[0]
+        assert r.escaped == 8192 and r.surrogate_calls > 0
+        out.append(p.tallies.cpu().numpy().copy())
+    for o in out[1:]:
+        np.testing.assert_array_equal(o, out[0])
+
+
+def test_exit_kernel_equal_work_speed_against_plain():
+    """Sweep cloud 176, the same first 2^14 packet ids with and without the exit kernel."""
+    import torch
+    m = media.sweep_cloud_medium(media.sweep_parameters()[176])
+    rates = {}
+    for leg in ("exit kernel", "plain"):
+        q = rddmc.Problem(m)
+        kw = dict(surrogate=rddmc.ExitKernel(q, min_steps=64.0).buffer) if leg == "exit kernel" else {}
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        q.run(seed=1, count=1 << 14, **kw)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        rq = q.results()[0]
+        assert rq.escaped == 1 << 14
+        rates[leg] = (1 << 14) / dt
+        print(f"[exitkernel] {leg}: {dt:.2f} s, {rates[leg]:.0f} pk/s, steps/pk {rq.steps_mean:.4g}", flush=True)
+    print(f"    equal-work speedup {rates['exit kernel'] / rates['plain']:.1f}x", flush=True)
+    assert rates["exit kernel"] > rates["plain"]
