@@ -98,6 +98,9 @@ def parse():
     ap.add_argument("--tail-lanes", type=int, default=0,
                     help="1D: hand a wave's packets to the cooperative walk at <= this many (0 = default)")
     ap.add_argument("--surrogate-packets", type=int, default=2048, help="packets per cloud, surrogate workload")
+    ap.add_argument("--exit-kernel", action="store_true",
+                    help="sphere workloads: walk with the exact per-cell exit kernel (built untimed)")
+    ap.add_argument("--ek-min-steps", type=float, default=64.0, help="exit-kernel window: shortest expected sub-walk")
     return ap.parse_args()
 
 
@@ -208,7 +211,16 @@ def bench_sphere(args, efficient=False):
     B = int(args.block_packets) or int(m.n_packets)
     log(f"building tables for {m.name}")
     prob = rddmc.Problem(m)
-    sec, per = timed_steps(prob, args.steps, args.warmup, first=0, count=B, tail_lanes=args.tail_lanes)
+    extra, ek_info = {}, {}
+    if args.exit_kernel:
+        t0 = time.perf_counter()
+        ek = rddmc.ExitKernel(prob, min_steps=args.ek_min_steps)
+        ek_info = {"exit_kernel": {"window": list(ek.windows[0]), "states": ek.n_states,
+                                   "mib": ek.buffer.numel() / 2 ** 20, "build_s": time.perf_counter() - t0,
+                                   "min_steps": args.ek_min_steps}}
+        extra["surrogate"] = ek.buffer
+        log(f"exit kernel: {ek.n_states} window states, {ek_info['exit_kernel']['mib']:.1f} MiB")
+    sec, per = timed_steps(prob, args.steps, args.warmup, first=0, count=B, tail_lanes=args.tail_lanes, **extra)
     res = prob.results()[0]
     K = args.steps
     launch_s = sum(per) / K
@@ -220,14 +232,20 @@ def bench_sphere(args, efficient=False):
          "packets_per_step": B, "escaped": int(res.escaped), "steps_mean": res.steps_mean,
          "steps_max": int(res.steps_max), "t_mean_light_crossings": res.t_mean,
          "launch_ms": [1e3 * p for p in per],
-         "precision": "f32 walk, f64 tables and clock, i64 tallies, Philox4x32-10"},
+         "precision": "f32 walk, f64 tables and clock, i64 tallies, Philox4x32-10", **ek_info},
         packet_steps_per_s=res.steps_total / sec)
+    if args.exit_kernel:
+        out["config"]["exit_kernel"]["exits_per_packet"] = res.surrogate_calls / res.launched
+        out["config"]["workload"] += ("; cell sub-walks drawn from the exact per-cell exit kernel (spectrum exact in "
+                                      "law, escape-time mean and variance exact)")
     out["roofline"] = {
         "bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_OPS / 1e12, "unit": "T VALU lane-ops/s",
         "frac": achieved / PEAK_OPS,
         "traffic": (profiled_traffic("walk1d_sphere_tau1e7_job_pmc.md", "walk1d")
                     if B == m.n_packets and not efficient else None),
         "kernel": "walk1d"}
+    if args.exit_kernel:
+        out["roofline"] = None   # exits are table gathers and solves' draws, not DDMC steps
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_1d(m, args.cpu_packets or (16384 if efficient else 12), args)
     return out

@@ -433,9 +433,10 @@ rddmc_status rddmc_surrogate_attach(const rddmc_batch *batch, const void *d_tabl
  * from the EXACT law of its in-cell walk (Sec. 2.3: the frequency moves of eq. 11 between
  * the cell's bins until the first spatial leak).  With A = I - Q the in-cell jump matrix,
  * built from the walk's own integer event thresholds, the exit (face f, exit bin j') has
- * probability [A^-T e_j](j') p_f(j'); the time spent is drawn from the lognormal whose mean
- * and second moment are the exact conditional ones, E[T | j'] and E[T^2 | j'] (two more
- * transposed solves with D = diag(1/K)).  The leak from (i, j') then happens as in a walk
+ * probability [A^-T e_j](j') p_f(j'); the time spent has the exact conditional mean and
+ * variance given j' (two more transposed solves with D = diag(1/K)): a shifted exponential
+ * when its squared coefficient of variation c2 <= 1, else a balanced mixture of two
+ * exponentials.  The leak from (i, j') then happens as in a walk
  * step (x uniform in the bin, the Doppler map of eq. 20).  Escape spectra are therefore the
  * plain walk's in law; escape-time means and variances are exact, the time distribution's
  * shape within a cell approximate.  FP64 solves whose eliminations add only non-negative

@@ -863,7 +863,7 @@ rddmc_status rddmc_surrogate_samples(const rddmc_batch *batch, const void *d_tab
 
 namespace {
 
-constexpr uint64_t kEkChunk = 4096;   // window states per row-kernel launch
+constexpr uint64_t kEkChunk = 16384;  // window states per row-kernel launch
 constexpr int kEkArraysHost = 7;      // per-bin chain arrays per cell (exitkernel.hip)
 
 struct EkPlan {

@@ -17,8 +17,8 @@
 //
 // A row keeps the exit bins [j_lo, j_lo + m) outside of which every bin's leak probability is
 // below the caller's tail (the kept law is renormalised), as a CDF over (face 0, bins...),
-// (face 1, bins...) and, per exit bin, the lognormal (mu, sigma) whose mean and second moment
-// are the exact conditional ones.
+// (face 1, bins...) and, per exit bin, the exact conditional mean m1 = E[T | j'] and squared
+// coefficient of variation c2 = E[T^2 | j'] / m1^2 - 1 of the time spent.
 #include <hip/hip_runtime.h>
 
 #include "rddmc_internal.h"
@@ -161,8 +161,7 @@ __global__ void ek_rows(const double *__restrict__ cb, int nc, int nb, int i_lo,
         float2 par = make_float2(0.0f, 0.0f);
         if (a1 > 0.0) {
             const double m1 = w2[o] / a1, m2 = 2.0 * w3[o] / a1;
-            const double s2 = fmax(0.0, log(m2 / (m1 * m1)));
-            par = make_float2((float)(log(m1) - 0.5 * s2), (float)sqrt(s2));
+            par = make_float2((float)m1, (float)fmax(0.0, m2 / (m1 * m1) - 1.0));
         }
         tp[k] = par;
     }

@@ -262,10 +262,16 @@ __device__ __forceinline__ void rebin(Packet1D &p, int face, float4 cm, uint32_t
 
 // Replace the rest of the packet's walk inside its cell by one exit drawn from the exact law of
 // its in-cell walk (the exact exit kernel, same window and check points as the learned
-// surrogate): (face, exit bin) from the state's row CDF with a 53-bit uniform, then the spatial
+// surrogate): (face, exit bin) from the state's row CDF with a 32-bit uniform, then the spatial
 // leak from the exit bin exactly as a walk step takes it (x uniform in the bin and the Doppler
-// map of eq. 20 in moving clouds), and the time from the lognormal with the exact conditional
-// mean and second moment.  One Philox block in the surrogate's counter domain per exit.
+// map of eq. 20 in moving clouds).  The time has the exact conditional mean m1 and squared
+// coefficient of variation c2: m1 (1 - sqrt(c2)) + m1 sqrt(c2) E for c2 <= 1, else a balanced
+// mixture of two exponentials (probabilities q and 1 - q, means m1 / 2q and m1 / 2(1 - q),
+// q = 1 / ((1 + c2)(1 + sqrt((c2 - 1) / (c2 + 1))))), with q on the 2^-24 grid of the uniform
+// that picks the branch so that the mean stays m1 exactly.  E = -ln u with u a 24-bit uniform
+// (its largest value, 17.3, leaves out 6e-7 of an exponential's mean).  One Philox block in the
+// surrogate's counter domain per exit: x for the CDF, y for the branch, z for the re-binning, w
+// for E.
 template <bool MOVING>
 __device__ void exact_exit(Packet1D &p, const SurrWin &sw, const uint8_t *__restrict__ tb, const DevCloud &c,
                            const WalkArgs &a)
@@ -277,7 +283,7 @@ __device__ void exact_exit(Packet1D &p, const SurrWin &sw, const uint8_t *__rest
     const int64_t idx = (int64_t)sw.rec_off + (int64_t)(p.i - sw.i_lo) * (sw.j_hi - sw.j_lo + 1) + (p.j - sw.j_lo);
     const ExitRec er = reinterpret_cast<const ExitRec *>(a.surr + SH->off_records)[idx];
     const double *cdf = reinterpret_cast<const double *>(a.surr + SH->off_rows + er.row_off);
-    const double u = (double)(((uint64_t)r.x << 21) | (r.y >> 11)) * 1.1102230246251565e-16;   // [0, 1), 2^-53
+    const double u = (double)r.x * 2.3283064365386962890625e-10;   // [0, 1) on the 2^-32 grid
     int lo = 0, hi = 2 * er.m - 1;   // first outcome whose CDF exceeds u (the last is 1)
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
@@ -285,9 +291,19 @@ __device__ void exact_exit(Packet1D &p, const SurrWin &sw, const uint8_t *__rest
     }
     const int face = lo >= er.m ? 1 : 0;
     const int k = lo - face * er.m;
-    const float2 tp = reinterpret_cast<const float2 *>(cdf + 2 * er.m)[k];
-    const float zn = normcdfinvf(((float)(r.w >> 8) + 0.5f) * 5.9604644775390625e-8f);
-    p.t += (double)__expf(fmaf(tp.y, zn, tp.x));
+    const float2 tp = reinterpret_cast<const float2 *>(cdf + 2 * er.m)[k];   // {m1, c2}
+    const float ex = -__logf(((float)(r.w >> 8) + 0.5f) * 5.9604644775390625e-8f);
+    float dt;
+    if (tp.y <= 1.0f) {
+        const float b = tp.x * sqrtf(tp.y);
+        dt = fmaf(b, ex, tp.x - b);
+    } else {
+        const float q = 1.0f / ((1.0f + tp.y) * (1.0f + sqrtf((tp.y - 1.0f) / (tp.y + 1.0f))));
+        const uint32_t nq = (uint32_t)fminf(fmaxf(rintf(q * 16777216.0f), 1.0f), 8388608.0f);
+        const float qk = (float)nq * 5.9604644775390625e-8f;
+        dt = ((r.y >> 8) < nq ? tp.x / (2.0f * qk) : tp.x / (2.0f * (1.0f - qk))) * ex;
+    }
+    p.t += (double)dt;
     p.j = er.j_lo + k;
     if (MOVING && p.moving) rebin(p, face, p.cmap[p.i], r.z, c, tb);
     p.i += face ? 1 : -1;
