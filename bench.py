@@ -16,6 +16,8 @@ Other workloads (``--workload``):
              the same sphere on the paper's efficient frequency grid (79 bins: a central bin
              of 2 x_cw, unit-width wings to 2.5 (a tau0)^(1/3)), the whole job per step;
   sweep      batched sweep clouds in one hipGraph-captured launch with the autotuned schedule;
+  sweep-full all 256 sweep clouds at their stated packet counts (2^14..2^18 each) in one launch
+             with the exact per-cell exit kernel, clouds ordered longest first by a pilot walk;
   surrogate  the learned escape surrogate against plain rDDMC on the same clouds and packets.
 
 Prints one JSON line.  ``--gpus`` must be 1 (the path runs on one GPU).
@@ -85,7 +87,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["cube", "sphere", "sphere-efficient", "surrogate", "sweep"], default="cube")
+    ap.add_argument("--workload", choices=["cube", "sphere", "sphere-efficient", "surrogate", "sweep", "sweep-full"], default="cube")
     ap.add_argument("--block-packets", type=int, default=0,
                     help="sphere: packets per step (0 = the whole 2^22-packet job)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -101,6 +103,7 @@ def parse():
     ap.add_argument("--exit-kernel", action="store_true",
                     help="sphere workloads: walk with the exact per-cell exit kernel (built untimed)")
     ap.add_argument("--ek-min-steps", type=float, default=64.0, help="exit-kernel window: shortest expected sub-walk")
+    ap.add_argument("--segments", type=int, default=16, help="sweep-full: packet-id segments of the step")
     return ap.parse_args()
 
 
@@ -147,6 +150,44 @@ def timed_steps(prob, steps, warmup, **kw):
     total = outer[0].elapsed_time(outer[1]) / 1e3
     per = [a.elapsed_time(b) / 1e3 for a, b in ev]
     return total, per
+
+
+def segmented_step(prob, seed, n_seg, **kw):
+    """One step as n_seg consecutive packet-id segments launched alternately on two streams
+    with their own work counters (a segment's slowest packets run beside the next one's bulk;
+    tallies are the same for any split).  A line is logged as each segment completes.  Returns
+    (seconds between events bracketing all segments, per-segment seconds from its launch to
+    its completion)."""
+    import torch
+    from paper_1709_10187_amd import rddmc
+    total = prob.total_packets
+    seg = (total + n_seg - 1) // n_seg
+    cur = torch.cuda.current_stream()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    works = [prob.work, torch.zeros_like(prob.work)]
+    prob.reset()
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(cur)
+    t0 = time.perf_counter()
+    marks = []
+    for k, first in enumerate(range(0, total, seg)):
+        st = streams[k % 2]
+        st.wait_event(start)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(st)
+        rddmc.transport(prob.batch, prob.tables, prob.tallies, works[k % 2], seed=seed, first=first,
+                        count=min(seg, total - first), stream=st, **kw)
+        b.record(st)
+        marks.append((first, a, b))
+    for st in streams:
+        cur.wait_stream(st)
+    stop.record(cur)
+    for first, a, b in marks:
+        b.synchronize()
+        log(f"segment from packet {first} done ({time.perf_counter() - t0:.1f} s)")
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop) / 1e3, [a.elapsed_time(b) / 1e3 for _, a, b in marks]
 
 
 def base_line(args, value, sec, dtype, config, **extra):
@@ -309,6 +350,51 @@ def bench_sweep(args):
     return out
 
 
+def bench_sweep_full(args):
+    """All 256 sweep clouds at their stated packet counts in one rddmc_transport launch with the
+    exact per-cell exit kernel.  The clouds are queued longest first: a pilot walk of 64 packets
+    per cloud (capped at 2^20 steps, untimed) estimates each cloud's steps per packet, so the
+    clouds whose packets take longest start first and the launch does not end on them."""
+    import torch
+    from paper_1709_10187_amd import media, rddmc
+    meds = media.config_sweep()
+    n_cl = len(meds)
+    t0 = time.perf_counter()
+    log(f"sweep-full: pilot of 64 packets per cloud over {n_cl} clouds")
+    pilot = rddmc.Problem([m.with_packets(64) for m in meds], streams=list(range(n_cl)))
+    ekp = rddmc.ExitKernel(pilot, min_steps=args.ek_min_steps)
+    pilot.run(seed=987654321, surrogate=ekp.buffer, max_steps=1 << 20)
+    cost = [r.steps_mean for r in pilot.results()]
+    del pilot, ekp
+    torch.cuda.empty_cache()
+    order = sorted(range(n_cl), key=lambda i: -cost[i])
+    t_pilot = time.perf_counter() - t0
+    log(f"sweep-full: building tables and exit kernels ({t_pilot:.1f} s of pilot)")
+    prob = rddmc.Problem([meds[i] for i in order], streams=order)
+    t1 = time.perf_counter()
+    ek = rddmc.ExitKernel(prob, min_steps=args.ek_min_steps)
+    torch.cuda.synchronize()
+    t_ek = time.perf_counter() - t1
+    args.steps, args.warmup = 1, 0
+    sec, per = segmented_step(prob, seed=0, n_seg=args.segments, surrogate=ek.buffer)
+    res = prob.results()
+    n = sum(r.launched for r in res)
+    steps = sum(r.steps_total for r in res)
+    exits = sum(r.surrogate_calls for r in res)
+    out = base_line(
+        args, n / sec, sec, "f32",
+        {"workload": f"all {n_cl} sweep clouds (PCG64(3): tau0 10^U(4,9), T 10^U(2,5) K, 32..512 shells, "
+                     "256..1024 bins, 0..200 km/s outflow) at their stated 2^U(14,18) packets, one launch, cell "
+                     "sub-walks drawn from the exact per-cell exit kernel, clouds queued longest first by a pilot",
+         "packets": int(n), "escaped": int(sum(r.escaped for r in res)), "capped": int(sum(r.capped for r in res)),
+         "exits_per_packet": exits / n, "exit_kernel_states": ek.n_states,
+         "exit_kernel_mib": ek.buffer.numel() / 2 ** 20, "exit_kernel_build_s": t_ek, "pilot_s": t_pilot,
+         "order_first": order[:8], "launch_ms": [1e3 * p for p in per]},
+        packet_steps_per_s=steps / sec)
+    out["roofline"] = None
+    return out
+
+
 def bench_surrogate(args):
     """Learned escape surrogate against plain rDDMC: the same clouds, the same packet ids."""
     import torch
@@ -409,7 +495,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     fn = {"cube": bench_cube, "sphere": bench_sphere, "sphere-efficient": lambda a: bench_sphere(a, efficient=True),
-          "surrogate": bench_surrogate, "sweep": bench_sweep}
+          "surrogate": bench_surrogate, "sweep": bench_sweep, "sweep-full": bench_sweep_full}
     print(json.dumps(fn[args.workload](args)), flush=True)
 
 

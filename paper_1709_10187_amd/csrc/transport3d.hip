@@ -50,6 +50,7 @@ struct Pk {
     int64_t cell;
     int j;
     bool mc, active;
+    bool pend;           // a DDMC step chose a spatial leak that has not been applied yet
     float3 pos, n;
     float x;
     double t;
@@ -171,9 +172,10 @@ __device__ __forceinline__ void enter(Pk &p, int nix, int niy, int niz, int64_t 
     p.cell = ncell;
 }
 
-// One DDMC step of a packet in a thick state.
-__device__ void ddmc_step(Pk &p, const DevCloud &c, const uint8_t *__restrict__ tb, const Walk3Args &a,
-                          unsigned long long *__restrict__ tally)
+// The draw and event of one DDMC step of a packet in a thick state: the path length, then a
+// frequency leak (eq. 11) is applied at once; a spatial leak is only marked (pend) and applied
+// by ddmc_leak, with the next random words of the packet's stream, before its next step.
+__device__ void ddmc_event(Pk &p, const DevCloud &c, const uint8_t *__restrict__ tb, const Walk3Args &a)
 {
     const int nb = c.nb;
     const int64_t s = p.cell * nb + p.j;
@@ -201,7 +203,19 @@ __device__ void ddmc_step(Pk &p, const DevCloud &c, const uint8_t *__restrict__ 
         }
         return;
     }
-    // spatial leak: the face from the state's cumulative split
+    p.pend = true;
+}
+
+// The spatial leak a DDMC step chose (p.pend): the face from the state's cumulative split, then
+// the move into the neighbour (Doppler re-binning of eq. 20), a conversion to continuous MC
+// through an interface face, or an escape.
+__device__ void ddmc_leak(Pk &p, const DevCloud &c, const uint8_t *__restrict__ tb, const Walk3Args &a,
+                          unsigned long long *__restrict__ tally)
+{
+    p.pend = false;
+    const int nb = c.nb;
+    const int64_t s = p.cell * nb + p.j;
+    const uint4 rec = reinterpret_cast<const uint4 *>(tb + c.off_hot)[s];
     const uint32_t v = draw(p.r, a) >> 1;
     const uint32_t *fs = reinterpret_cast<const uint32_t *>(tb + c.off_face_split) + s * 5;
     int f = 0;
@@ -361,7 +375,7 @@ __device__ __forceinline__ uint64_t shfl64(uint64_t v, int src)
 }
 
 template <bool SINGLE>
-__global__ __launch_bounds__(256) void walk3d(const uint8_t *__restrict__ tb, Walk3Args a,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void walk3d(const uint8_t *__restrict__ tb, Walk3Args a,
                                               unsigned long long *__restrict__ tally,
                                               unsigned long long *__restrict__ work)
 {
@@ -375,6 +389,7 @@ __global__ __launch_bounds__(256) void walk3d(const uint8_t *__restrict__ tb, Wa
     Pk p;
     p.active = false;
     p.mc = false;
+    p.pend = false;
     p.cl = 0; p.ix = p.iy = p.iz = 0; p.cell = 0; p.j = 0;
     p.pos = make_float3(0.f, 0.f, 0.f);
     p.n = make_float3(0.f, 0.f, 1.f);
@@ -428,6 +443,7 @@ __global__ __launch_bounds__(256) void walk3d(const uint8_t *__restrict__ tb, Wa
                         p.steps = 0;
                         p.mcs = p.tomc = p.toddmc = p.refl = 0u;
                         p.active = true;
+                        p.pend = false;
                         const uint4 rec = reinterpret_cast<const uint4 *>(tb + c.off_hot)[st];
                         p.mc = !(rec.w & kFlagThick);
                         if (p.mc) {   // a thin source state starts as an MC packet at the source
@@ -443,10 +459,12 @@ __global__ __launch_bounds__(256) void walk3d(const uint8_t *__restrict__ tb, Wa
         }
         if (!__any(p.active)) break;
 
-        // Mode-batched passes: a pass advances either the wave's DDMC lanes by up to two steps
-        // or its continuous-MC lanes by one event, never both, so a wave with a few MC lanes
-        // does not issue the long MC path on every step.  The MC lanes wait for a pass of
-        // their own until they are at least a quarter as many as the DDMC lanes, or every
+        // Event-batched passes: a pass advances the wave's DDMC lanes by up to two steps, or
+        // applies the spatial leaks its DDMC steps chose, or advances its continuous-MC lanes
+        // by one event, never two of these, so a wave does not issue the long leak or MC path
+        // for one lane.  A lane whose step chose a spatial leak waits for a leak pass (taken
+        // once such lanes are an eighth of the stepping ones, or every sixteenth pass); MC
+        // lanes wait until they are at least a quarter as many as the DDMC lanes, or every
         // eighth pass.  Each pass starts by generating every taking part lane's next random
         // block together (two frequency steps read one block).  Every packet still takes its
         // own steps in its own order from its own stream, so the results do not depend on
@@ -454,22 +472,27 @@ __global__ __launch_bounds__(256) void walk3d(const uint8_t *__restrict__ tb, Wa
         const DevCloud &c = clouds[SINGLE ? 0 : p.cl];
         const float lambda = (float)c.lambda;
         for (int k = 0; k < a.chunk; ++k) {
-            if (p.active && p.steps >= a.max_steps) finish(p, c, tally, false, 0, 0);
+            if (p.active && !p.pend && p.steps >= a.max_steps) finish(p, c, tally, false, 0, 0);
             const uint64_t bm = __ballot(p.active && p.mc);
-            const uint64_t bd = __ballot(p.active && !p.mc);
-            if (!(bm | bd)) break;
-            const int nm = __popcll(bm), nd = __popcll(bd);
-            const bool mc_pass = nm > 0 && (4 * nm >= nd || (k & 7) == 7);
-            if (p.active && p.mc == mc_pass) {
+            const uint64_t bl = __ballot(p.active && p.pend);
+            const uint64_t bd = __ballot(p.active && !p.mc && !p.pend);
+            if (!(bm | bd | bl)) break;
+            const int nm = __popcll(bm), nl = __popcll(bl), nd = __popcll(bd);
+            const int mode = (nm > 0 && (4 * nm >= nd + nl || (k & 7) == 7)) ? 2
+                             : (nl > 0 && (8 * nl >= nd || (k & 15) == 15 || nd == 0)) ? 1 : 0;
+            if (p.active && (mode == 2 ? p.mc : (mode == 1 ? p.pend : !p.mc && !p.pend))) {
                 prefetch(p.r, a);
-                ++p.steps;
-                if (mc_pass) {
+                if (mode == 2) {
+                    ++p.steps;
                     mc_step(p, c, tb, a, tally, vtab, u0tab, lambda);
+                } else if (mode == 1) {
+                    ddmc_leak(p, c, tb, a, tally);
                 } else {
-                    ddmc_step(p, c, tb, a, tally);
-                    if (p.active && !p.mc && p.steps < a.max_steps) {
+                    ++p.steps;
+                    ddmc_event(p, c, tb, a);
+                    if (!p.mc && !p.pend && p.steps < a.max_steps) {
                         ++p.steps;
-                        ddmc_step(p, c, tb, a, tally);
+                        ddmc_event(p, c, tb, a);
                     }
                 }
             }
