@@ -103,7 +103,7 @@ def parse():
     ap.add_argument("--exit-kernel", action="store_true",
                     help="sphere workloads: walk with the exact per-cell exit kernel (built untimed)")
     ap.add_argument("--ek-min-steps", type=float, default=64.0, help="exit-kernel window: shortest expected sub-walk")
-    ap.add_argument("--segments", type=int, default=16, help="sweep-full: packet-id segments of the step")
+    ap.add_argument("--segments", type=int, default=64, help="sweep-full: packet-id segments of the step")
     return ap.parse_args()
 
 
@@ -155,7 +155,8 @@ def timed_steps(prob, steps, warmup, **kw):
 def segmented_step(prob, seed, n_seg, **kw):
     """One step as n_seg consecutive packet-id segments launched alternately on two streams
     with their own work counters (a segment's slowest packets run beside the next one's bulk;
-    tallies are the same for any split).  A line is logged as each segment completes.  Returns
+    tallies are the same for any split).  A line is logged as each segment completes (its
+    completion event is polled every 0.2 s).  Returns
     (seconds between events bracketing all segments, per-segment seconds from its launch to
     its completion)."""
     import torch
@@ -183,9 +184,17 @@ def segmented_step(prob, seed, n_seg, **kw):
     for st in streams:
         cur.wait_stream(st)
     stop.record(cur)
-    for first, a, b in marks:
-        b.synchronize()
-        log(f"segment from packet {first} done ({time.perf_counter() - t0:.1f} s)")
+    pending = list(marks)
+    while pending:
+        left = []
+        for first, a, b in pending:
+            if b.query():
+                log(f"segment from packet {first} done ({time.perf_counter() - t0:.1f} s)")
+            else:
+                left.append((first, a, b))
+        pending = left
+        if pending:
+            time.sleep(0.2)
     torch.cuda.synchronize()
     return start.elapsed_time(stop) / 1e3, [a.elapsed_time(b) / 1e3 for _, a, b in marks]
 

@@ -877,9 +877,8 @@ struct EkScratch {
     uint64_t cb = 0, mn = 0, sc = 0, sp = 0, total = 0;   // offsets and size
 };
 
-EkScratch ek_scratch_layout(const Layout &L)
+void ek_scratch_layout(const Layout &L, EkScratch &S)
 {
-    EkScratch S;
     uint64_t need_cb = 0, need_nb = 0;
     for (const DevCloud &c : L.clouds) {
         need_cb = std::max<uint64_t>(need_cb, 8ull * kEkArraysHost * c.nc * c.nb);
@@ -890,7 +889,6 @@ EkScratch ek_scratch_layout(const Layout &L)
     S.sc = align_up(S.mn + 8ull * need_nb);
     S.sp = align_up(S.sc + 24ull * need_nb * kEkChunk);
     S.total = align_up(S.sp + 8ull * kEkChunk);
-    return S;
 }
 
 rddmc_status ek_check(const rddmc_batch *b, const rddmc_exitkernel_cfg *cfg, Layout &L)
@@ -986,7 +984,9 @@ rddmc_status rddmc_exitkernel_scratch_bytes(const rddmc_batch *batch, size_t *by
     Layout L;
     rddmc_status st = make_layout(batch, L);
     if (st != RDDMC_OK) return st;
-    *bytes = ek_scratch_layout(L).total;
+    EkScratch X;
+    ek_scratch_layout(L, X);
+    *bytes = X.total;
     return RDDMC_OK;
 }
 
@@ -998,7 +998,8 @@ rddmc_status rddmc_exitkernel_bytes(const rddmc_batch *batch, const void *d_tabl
     rddmc_status st = ek_check(batch, cfg, L);
     if (st != RDDMC_OK) return st;
     if (!d_tables || !d_scratch || !bytes) return fail(RDDMC_EINVAL, "NULL argument");
-    const EkScratch X = ek_scratch_layout(L);
+    EkScratch X;
+    ek_scratch_layout(L, X);
     if ((uintptr_t)d_scratch % kAlign) return fail(RDDMC_EINVAL, "d_scratch must be 256-byte aligned");
     if (scratch_bytes < X.total)
         return fail(RDDMC_ESIZE, "scratch %zu < required %llu", scratch_bytes, (unsigned long long)X.total);
@@ -1027,7 +1028,8 @@ rddmc_status rddmc_exitkernel_build(const rddmc_batch *batch, const void *d_tabl
     if (!d_tables || !d_scratch || !d_ek) return fail(RDDMC_EINVAL, "NULL argument");
     if ((uintptr_t)d_scratch % kAlign || (uintptr_t)d_ek % kAlign)
         return fail(RDDMC_EINVAL, "d_scratch and d_ek must be 256-byte aligned");
-    const EkScratch X = ek_scratch_layout(L);
+    EkScratch X;
+    ek_scratch_layout(L, X);
     if (scratch_bytes < X.total)
         return fail(RDDMC_ESIZE, "scratch %zu < required %llu", scratch_bytes, (unsigned long long)X.total);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);

@@ -463,7 +463,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void w
         // applies the spatial leaks its DDMC steps chose, or advances its continuous-MC lanes
         // by one event, never two of these, so a wave does not issue the long leak or MC path
         // for one lane.  A lane whose step chose a spatial leak waits for a leak pass (taken
-        // once such lanes are an eighth of the stepping ones, or every sixteenth pass); MC
+        // once such lanes are a sixteenth of the stepping ones, or every 32nd pass); MC
         // lanes wait until they are at least a quarter as many as the DDMC lanes, or every
         // eighth pass.  Each pass starts by generating every taking part lane's next random
         // block together (two frequency steps read one block).  Every packet still takes its
@@ -479,7 +479,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void w
             if (!(bm | bd | bl)) break;
             const int nm = __popcll(bm), nl = __popcll(bl), nd = __popcll(bd);
             const int mode = (nm > 0 && (4 * nm >= nd + nl || (k & 7) == 7)) ? 2
-                             : (nl > 0 && (8 * nl >= nd || (k & 15) == 15 || nd == 0)) ? 1 : 0;
+                             : (nl > 0 && (16 * nl >= nd || (k & 31) == 31 || nd == 0)) ? 1 : 0;
             if (p.active && (mode == 2 ? p.mc : (mode == 1 ? p.pend : !p.mc && !p.pend))) {
                 prefetch(p.r, a);
                 if (mode == 2) {
