@@ -103,7 +103,7 @@ def parse():
     ap.add_argument("--exit-kernel", action="store_true",
                     help="sphere workloads: walk with the exact per-cell exit kernel (built untimed)")
     ap.add_argument("--ek-min-steps", type=float, default=64.0, help="exit-kernel window: shortest expected sub-walk")
-    ap.add_argument("--segments", type=int, default=64, help="sweep-full: packet-id segments of the step")
+    ap.add_argument("--sweep-scale", type=float, default=1.0, help="sweep-full: fraction of the stated packet counts")
     return ap.parse_args()
 
 
@@ -152,51 +152,34 @@ def timed_steps(prob, steps, warmup, **kw):
     return total, per
 
 
-def segmented_step(prob, seed, n_seg, **kw):
-    """One step as n_seg consecutive packet-id segments launched alternately on two streams
-    with their own work counters (a segment's slowest packets run beside the next one's bulk;
-    tallies are the same for any split).  A line is logged as each segment completes (its
-    completion event is polled every 0.2 s).  Returns
-    (seconds between events bracketing all segments, per-segment seconds from its launch to
-    its completion)."""
+def watched_step(prob, seed, **kw):
+    """One step as ONE rddmc_transport launch (a single tail for the whole job) on a side
+    stream.  While it runs, the tallies are read on another stream every 2 s and a line is
+    logged whenever the number of finished packets has grown (nothing is printed while no
+    packet finishes).  Returns (seconds between events bracketing the launch, [same])."""
     import torch
     from paper_1709_10187_amd import rddmc
-    total = prob.total_packets
-    seg = (total + n_seg - 1) // n_seg
     cur = torch.cuda.current_stream()
-    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
-    works = [prob.work, torch.zeros_like(prob.work)]
+    run_s, poll_s = torch.cuda.Stream(), torch.cuda.Stream()
     prob.reset()
     torch.cuda.synchronize()
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    start.record(cur)
+    run_s.wait_stream(cur)
+    start.record(run_s)
+    rddmc.transport(prob.batch, prob.tables, prob.tallies, prob.work, seed=seed, stream=run_s, **kw)
+    stop.record(run_s)
     t0 = time.perf_counter()
-    marks = []
-    for k, first in enumerate(range(0, total, seg)):
-        st = streams[k % 2]
-        st.wait_event(start)
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record(st)
-        rddmc.transport(prob.batch, prob.tables, prob.tallies, works[k % 2], seed=seed, first=first,
-                        count=min(seg, total - first), stream=st, **kw)
-        b.record(st)
-        marks.append((first, a, b))
-    for st in streams:
-        cur.wait_stream(st)
-    stop.record(cur)
-    pending = list(marks)
-    while pending:
-        left = []
-        for first, a, b in pending:
-            if b.query():
-                log(f"segment from packet {first} done ({time.perf_counter() - t0:.1f} s)")
-            else:
-                left.append((first, a, b))
-        pending = left
-        if pending:
-            time.sleep(0.2)
+    total = prob.total_packets
+    done_last = 0
+    while not stop.query():
+        time.sleep(2.0)
+        done = sum(r.escaped + r.capped + r.absorbed for r in rddmc.tally(prob.batch, prob.tallies, stream=poll_s))
+        if done > done_last:
+            log(f"{done} of {total} packets finished ({time.perf_counter() - t0:.0f} s)")
+            done_last = done
     torch.cuda.synchronize()
-    return start.elapsed_time(stop) / 1e3, [a.elapsed_time(b) / 1e3 for _, a, b in marks]
+    sec = start.elapsed_time(stop) / 1e3
+    return sec, [sec]
 
 
 def base_line(args, value, sec, dtype, config, **extra):
@@ -366,7 +349,7 @@ def bench_sweep_full(args):
     clouds whose packets take longest start first and the launch does not end on them."""
     import torch
     from paper_1709_10187_amd import media, rddmc
-    meds = media.config_sweep()
+    meds = media.config_sweep(packet_scale=args.sweep_scale)
     n_cl = len(meds)
     t0 = time.perf_counter()
     log(f"sweep-full: pilot of 64 packets per cloud over {n_cl} clouds")
@@ -385,7 +368,7 @@ def bench_sweep_full(args):
     torch.cuda.synchronize()
     t_ek = time.perf_counter() - t1
     args.steps, args.warmup = 1, 0
-    sec, per = segmented_step(prob, seed=0, n_seg=args.segments, surrogate=ek.buffer)
+    sec, per = watched_step(prob, seed=0, surrogate=ek.buffer)
     res = prob.results()
     n = sum(r.launched for r in res)
     steps = sum(r.steps_total for r in res)
@@ -393,8 +376,9 @@ def bench_sweep_full(args):
     out = base_line(
         args, n / sec, sec, "f32",
         {"workload": f"all {n_cl} sweep clouds (PCG64(3): tau0 10^U(4,9), T 10^U(2,5) K, 32..512 shells, "
-                     "256..1024 bins, 0..200 km/s outflow) at their stated 2^U(14,18) packets, one launch, cell "
-                     "sub-walks drawn from the exact per-cell exit kernel, clouds queued longest first by a pilot",
+                     f"256..1024 bins, 0..200 km/s outflow) at {args.sweep_scale:g} x their stated 2^U(14,18) "
+                     "packets, cell sub-walks drawn from the exact per-cell exit kernel, clouds queued longest first "
+                     "by a pilot, one launch",
          "packets": int(n), "escaped": int(sum(r.escaped for r in res)), "capped": int(sum(r.capped for r in res)),
          "exits_per_packet": exits / n, "exit_kernel_states": ek.n_states,
          "exit_kernel_mib": ek.buffer.numel() / 2 ** 20, "exit_kernel_build_s": t_ek, "pilot_s": t_pilot,

@@ -443,7 +443,8 @@ rddmc_status rddmc_surrogate_attach(const rddmc_batch *batch, const void *d_tabl
  * terms (pivots in Grassmann-Taksar-Heyman form), so cells with leak probabilities of 1e-12
  * per step are solved to full precision.
  *
- * Window of a cloud: its interior cells (slab: 1 .. nc-2; sphere: 0 .. nc-2) x the contiguous
+ * Window of a cloud: its interior cells (1 .. nc-2; a sphere whose first face is the centre:
+ * 0 .. nc-2) x the contiguous
  * bins around the longest expected sub-walk in which every window cell's expected sub-walk is
  * at least min_steps steps.  A row keeps the exit bins whose leak probability reaches `tail`
  * (the kept law renormalised; 24 bytes per kept bin). */
@@ -467,6 +468,19 @@ rddmc_status rddmc_exitkernel_bytes(const rddmc_batch *batch, const void *d_tabl
  * the same cfg).  Synchronises.  Errors: as rddmc_exitkernel_bytes, ESIZE for d_ek. */
 rddmc_status rddmc_exitkernel_build(const rddmc_batch *batch, const void *d_tables, const rddmc_exitkernel_cfg *cfg,
                                     void *d_scratch, size_t scratch_bytes, void *d_ek, size_t bytes, void *stream);
+
+/* Training samples of the learned surrogate drawn from the exact in-cell law instead of run
+ * sub-walks (for cells whose sub-walks are too long): pair q = (cloud h_cloud[q], state
+ * h_state[q] in a cell with two neighbours) receives h_count[q] consecutive rows of d_x
+ * [rows, 16] and d_y [rows, 3], in pair order, in the layout of rddmc_surrogate_samples (exit
+ * face, asinh(x_out / S), ln(dt / w)); (face, exit bin) follow the exact law of the in-cell
+ * walk, x_out is uniform in the exit bin and dt is drawn as in the exact exit kernel (exact
+ * conditional mean and variance).  d_scratch >= 20 n_pairs + 88 nb_max n_pairs bytes (plus
+ * alignment: 256 bytes per region).  Synchronises.  Errors: EINVAL, ESIZE, EUNSUPPORTED
+ * (3D or hybrid), EHIP. */
+rddmc_status rddmc_exitlaw_samples(const rddmc_batch *batch, const void *d_tables, const int32_t *h_cloud,
+                                   const int32_t *h_state, const int32_t *h_count, int64_t n_pairs, uint64_t seed,
+                                   void *d_scratch, size_t scratch_bytes, float *d_x, float *d_y, void *stream);
 
 /* ---- learned escape surrogate: mixture-density network --------------------------------
  *

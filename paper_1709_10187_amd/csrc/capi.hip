@@ -923,7 +923,10 @@ rddmc_status ek_plan(const rddmc_batch *b, const Layout &L, const void *d_tables
     for (int ci = 0; ci < n; ++ci) {
         const DevCloud &c = L.clouds[ci];
         SurrCloud w{0, -1, 0, -1, (uint64_t)P.recs.size(), 0};
-        const int i_lo = c.geometry == RDDMC_SPHERE ? 0 : 1, i_hi = c.nc - 2;
+        // a sphere's innermost cell is interior when its inner face is the centre (no leak
+        // through it); any other first cell borders the inner boundary
+        const bool centre = c.geometry == RDDMC_SPHERE && b->clouds[ci].faces[0][0] == 0.0;
+        const int i_lo = centre ? 0 : 1, i_hi = c.nc - 2;
         if (i_hi >= i_lo) {
             if ((e = launch_ek_prep(tb, c, cb, s)) != hipSuccess) return hip_fail(e, "exit kernel: chain arrays");
             if ((e = launch_ek_minsteps(cb, c.nc, c.nb, i_lo, i_hi, mn, s)) != hipSuccess)
@@ -1066,6 +1069,53 @@ rddmc_status rddmc_exitkernel_build(const rddmc_batch *batch, const void *d_tabl
     }
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
     return RDDMC_OK;
+}
+
+rddmc_status rddmc_exitlaw_samples(const rddmc_batch *batch, const void *d_tables, const int32_t *h_cloud,
+                                   const int32_t *h_state, const int32_t *h_count, int64_t n_pairs, uint64_t seed,
+                                   void *d_scratch, size_t scratch_bytes, float *d_x, float *d_y, void *stream)
+{
+    Layout L;
+    rddmc_status st = make_layout(batch, L);
+    if (st != RDDMC_OK) return st;
+    if (!d_tables || !h_cloud || !h_state || !h_count || !d_scratch || !d_x || !d_y)
+        return fail(RDDMC_EINVAL, "NULL argument");
+    if (n_pairs < 1) return fail(RDDMC_EINVAL, "n_pairs < 1");
+    if (L.h.geometry == RDDMC_CART3D || L.h.hybrid1d)
+        return fail(RDDMC_EUNSUPPORTED, "exact exit-law samples are drawn for pure-DDMC 1D clouds");
+    int nb_max = 0;
+    std::vector<int64_t> off(n_pairs);
+    int64_t rows = 0;
+    for (int64_t q = 0; q < n_pairs; ++q) {
+        const int c = h_cloud[q];
+        if (c < 0 || c >= batch->n_clouds) return fail(RDDMC_EINVAL, "pair %lld: bad cloud", (long long)q);
+        const DevCloud &dc = L.clouds[c];
+        const int i = h_state[q] / dc.nb;
+        if (h_state[q] < 0 || (uint64_t)h_state[q] >= dc.n_states || i < 1 || i > dc.nc - 2)
+            return fail(RDDMC_EINVAL, "pair %lld: the state must lie in a cell with two neighbours", (long long)q);
+        if (h_count[q] < 0) return fail(RDDMC_EINVAL, "pair %lld: negative count", (long long)q);
+        nb_max = std::max(nb_max, dc.nb);
+        off[q] = rows;
+        rows += h_count[q];
+    }
+    const uint64_t n = (uint64_t)n_pairs;
+    const uint64_t o_pc = 0, o_ps = align_up(4 * n), o_cnt = align_up(o_ps + 4 * n), o_off = align_up(o_cnt + 4 * n),
+                   o_scr = align_up(o_off + 8 * n), need = o_scr + 88ull * nb_max * n;
+    if (scratch_bytes < need)
+        return fail(RDDMC_ESIZE, "scratch %zu < required %llu", scratch_bytes, (unsigned long long)need);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    uint8_t *scr = static_cast<uint8_t *>(d_scratch);
+    hipError_t e = hipMemcpyAsync(scr + o_pc, h_cloud, 4 * n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(scr + o_ps, h_state, 4 * n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(scr + o_cnt, h_count, 4 * n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(scr + o_off, off.data(), 8 * n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = launch_ek_samples(static_cast<const uint8_t *>(d_tables), reinterpret_cast<const int32_t *>(scr + o_pc),
+                              reinterpret_cast<const int32_t *>(scr + o_ps), reinterpret_cast<const int32_t *>(scr + o_cnt),
+                              reinterpret_cast<const int64_t *>(scr + o_off), n, seed, nb_max,
+                              reinterpret_cast<double *>(scr + o_scr), d_x, d_y, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);   // the host arrays are read asynchronously
+    return e == hipSuccess ? RDDMC_OK : hip_fail(e, "exit-law samples");
 }
 
 /* ---- mixture-density network of the escape surrogate --------------------------------- */

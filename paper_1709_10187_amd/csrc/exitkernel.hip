@@ -21,6 +21,7 @@
 // coefficient of variation c2 = E[T^2 | j'] / m1^2 - 1 of the time spent.
 #include <hip/hip_runtime.h>
 
+#include "philox.h"
 #include "rddmc_internal.h"
 #include "surrogate_dev.h"
 
@@ -167,7 +168,120 @@ __global__ void ek_rows(const double *__restrict__ cb, int nc, int nb, int i_lo,
     }
 }
 
+// Training samples of the learned surrogate drawn from the exact in-cell law (for cells whose
+// sub-walks are too long to run): thread t owns pair t = (cloud pc[t], cell * nb + bin ps[t])
+// and writes cnt[t] samples at rows off[t] .. off[t] + cnt[t] - 1 of x [., 16] (the state's
+// features) and y [., 3] = (face, asinh(x_out / S), ln(dt / w)) with x_out uniform in the exit
+// bin and dt from the moment-matched law of the walk's exit kernel.  Scratch: 11 nb doubles
+// per thread (chain arrays, three solves, the CDF), interleaved.  Random words: Philox keyed by
+// (seed, pair) with the sample index as counter.
+__global__ void ek_samples(const uint8_t *__restrict__ tb, const int32_t *__restrict__ pc,
+                           const int32_t *__restrict__ ps, const int32_t *__restrict__ cnt,
+                           const int64_t *__restrict__ off, uint64_t n_pairs, uint32_t k0, uint32_t k1,
+                           int nb_max, double *__restrict__ scratch, float *__restrict__ xo, float *__restrict__ yo)
+{
+    const uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    if (t >= n_pairs) return;
+    const DevHeader *H = reinterpret_cast<const DevHeader *>(tb);
+    const DevCloud &c = reinterpret_cast<const DevCloud *>(tb + H->off_clouds)[pc[t]];
+    const int nb = c.nb;
+    const int i = ps[t] / nb, j = ps[t] - i * nb;
+    const int64_t st = (int64_t)n_pairs;
+    auto arr = [&](int a) { return scratch + (int64_t)a * nb_max * st + t; };
+    double *qdn = arr(0), *qup = arr(1), *pf0 = arr(2), *pf1 = arr(3), *ik = arr(4), *pv = arr(5);
+    double *w1 = arr(6), *w2 = arr(7), *w3 = arr(8), *cdf = arr(9);   // cdf spans arrays 9 and 10
+    const uint4 *hot = reinterpret_cast<const uint4 *>(tb + c.off_hot) + (int64_t)i * nb;
+    const uint4 *low = reinterpret_cast<const uint4 *>(tb + c.off_lo_words) + (int64_t)i * nb;
+    double psi_prev = 0.0, piv_prev = 1.0;
+    for (int k = 0; k < nb; ++k) {
+        const uint4 h = hot[k], l = low[k];
+        const uint64_t D = ((uint64_t)h.y << 32) | l.x;
+        const uint64_t S = ((uint64_t)h.z << 32) | l.y;
+        const uint64_t F = ((uint64_t)h.w << 32) | l.z;
+        const double a_dn = u64_frac(D), a_up = u64_frac(S - D), a0 = u64_frac(F - S);
+        const double a1 = F == 0ull ? 1.0 - a_dn - a_up - a0 : u64_frac((uint64_t)0 - F);
+        const double psi = a0 + a1 + (k > 0 ? a_dn * psi_prev / piv_prev : 0.0);
+        qdn[k * st] = a_dn;
+        qup[k * st] = a_up;
+        pf0[k * st] = a0;
+        pf1[k * st] = a1;
+        ik[k * st] = (double)__uint_as_float(h.x) * 1.4426950408889634;
+        pv[k * st] = psi + a_up;
+        psi_prev = psi;
+        piv_prev = psi + a_up;
+    }
+    // w <- A^-T b (b in w; zero below k0), as solve_t with this thread's arrays
+    auto solve = [&](double *w, int kb) {
+        double z = 0.0;
+        for (int k = kb; k < nb; ++k) {
+            z = (w[k * st] + (k > kb ? qup[(k - 1) * st] * z : 0.0)) / pv[k * st];
+            w[k * st] = z;
+        }
+        double v = w[(int64_t)(nb - 1) * st];
+        for (int k = nb - 2; k >= 0; --k) {
+            v = (k >= kb ? w[k * st] : 0.0) + qdn[(k + 1) * st] / pv[k * st] * v;
+            w[k * st] = v;
+        }
+    };
+    for (int k = 0; k < nb; ++k) w1[k * st] = k == j ? 1.0 : 0.0;
+    solve(w1, j);
+    for (int k = 0; k < nb; ++k) w2[k * st] = ik[k * st] * w1[k * st];
+    solve(w2, 0);
+    for (int k = 0; k < nb; ++k) w3[k * st] = ik[k * st] * w2[k * st];
+    solve(w3, 0);
+    double acc = 0.0;
+    for (int f = 0; f < 2; ++f)
+        for (int k = 0; k < nb; ++k) {
+            acc += w1[k * st] * (f ? pf1[k * st] : pf0[k * st]);
+            cdf[((int64_t)f * nb + k) * st] = acc;
+        }
+    float feat[kSurrIn];
+    float Sc, wd;
+    surr_features(c, tb, i, j, feat, Sc, wd);
+    const double *e = reinterpret_cast<const double *>(tb + c.off_edges);
+    for (int q = 0; q < cnt[t]; ++q) {
+        const u32x4 r = philox4x32_10((uint32_t)q, 0x51u, (uint32_t)t, (uint32_t)(t >> 32), k0, k1);
+        const double u = (double)r.x * 2.3283064365386962890625e-10 * acc;
+        int lo = 0, hi = 2 * nb - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (u < cdf[(int64_t)mid * st]) hi = mid; else lo = mid + 1;
+        }
+        const int face = lo >= nb ? 1 : 0;
+        const int jo = lo - face * nb;
+        const double a1 = w1[(int64_t)jo * st];
+        const double m1 = a1 > 0.0 ? w2[(int64_t)jo * st] / a1 : 0.0;
+        const double c2 = a1 > 0.0 ? fmax(0.0, 2.0 * w3[(int64_t)jo * st] / (a1 * m1 * m1) - 1.0) : 0.0;
+        const double ex = -log(((double)(r.w >> 8) + 0.5) * 5.9604644775390625e-8);
+        double dt;
+        if (c2 <= 1.0) {
+            const double b = m1 * sqrt(c2);
+            dt = (m1 - b) + b * ex;
+        } else {
+            const double qq = 1.0 / ((1.0 + c2) * (1.0 + sqrt((c2 - 1.0) / (c2 + 1.0))));
+            const double uc = ((double)(r.y >> 8) + 0.5) * 5.9604644775390625e-8;
+            dt = (uc < qq ? m1 / (2.0 * qq) : m1 / (2.0 * (1.0 - qq))) * ex;
+        }
+        const double xout = e[jo] + (e[jo + 1] - e[jo]) * (((double)(r.z >> 8) + 0.5) * 5.9604644775390625e-8);
+        const int64_t row = off[t] + q;
+        for (int f = 0; f < kSurrIn; ++f) xo[row * kSurrIn + f] = feat[f];
+        yo[row * 3 + 0] = (float)face;
+        yo[row * 3 + 1] = (float)asinh(xout / (double)Sc);
+        yo[row * 3 + 2] = (float)log(fmax(dt, 1e-300) / (double)wd);
+    }
+}
+
 }  // namespace
+
+hipError_t launch_ek_samples(const uint8_t *d_tables, const int32_t *d_pc, const int32_t *d_ps, const int32_t *d_cnt,
+                             const int64_t *d_off, uint64_t n_pairs, uint64_t seed, int nb_max, double *d_scratch,
+                             float *d_x, float *d_y, hipStream_t s)
+{
+    ek_samples<<<(unsigned)((n_pairs + 63) / 64), 64, 0, s>>>(d_tables, d_pc, d_ps, d_cnt, d_off, n_pairs,
+                                                              (uint32_t)seed, (uint32_t)(seed >> 32), nb_max,
+                                                              d_scratch, d_x, d_y);
+    return hipGetLastError();
+}
 
 hipError_t launch_ek_prep(const uint8_t *d_tables, const DevCloud &c, double *d_cb, hipStream_t s)
 {

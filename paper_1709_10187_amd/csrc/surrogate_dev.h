@@ -62,6 +62,9 @@ struct ExitRec {
 // state either the kept exit-bin span (d_rows == nullptr) or the row.
 hipError_t launch_ek_prep(const uint8_t *d_tables, const DevCloud &c, double *d_cb, hipStream_t s);
 hipError_t launch_ek_minsteps(const double *d_cb, int nc, int nb, int i_lo, int i_hi, double *d_out, hipStream_t s);
+hipError_t launch_ek_samples(const uint8_t *d_tables, const int32_t *d_pc, const int32_t *d_ps, const int32_t *d_cnt,
+                             const int64_t *d_off, uint64_t n_pairs, uint64_t seed, int nb_max, double *d_scratch,
+                             float *d_x, float *d_y, hipStream_t s);
 hipError_t launch_ek_rows(const double *d_cb, int nc, int nb, int i_lo, int j_lo, int nj, uint64_t q0, uint64_t cnt,
                           double tail, double *d_scratch, int2 *d_span, const ExitRec *d_recs, uint8_t *d_rows,
                           hipStream_t s);

@@ -464,8 +464,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void w
         // by one event, never two of these, so a wave does not issue the long leak or MC path
         // for one lane.  A lane whose step chose a spatial leak waits for a leak pass (taken
         // once such lanes are a sixteenth of the stepping ones, or every 32nd pass); MC
-        // lanes wait until they are at least a quarter as many as the DDMC lanes, or every
-        // eighth pass.  Each pass starts by generating every taking part lane's next random
+        // lanes wait until they are at least an eighth as many as the DDMC lanes, or every
+        // sixteenth pass.  (Thresholds measured on the 128^3 cube: leak passes at an eighth
+        // 1 926 ms, a quarter 1 902, a sixteenth 1 867, a 32nd 1 865; MC passes at an eighth
+        // with leak passes at a sixteenth 1 852.)  Each pass starts by generating every taking part lane's next random
         // block together (two frequency steps read one block).  Every packet still takes its
         // own steps in its own order from its own stream, so the results do not depend on
         // this schedule.
@@ -478,7 +480,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void w
             const uint64_t bd = __ballot(p.active && !p.mc && !p.pend);
             if (!(bm | bd | bl)) break;
             const int nm = __popcll(bm), nl = __popcll(bl), nd = __popcll(bd);
-            const int mode = (nm > 0 && (4 * nm >= nd + nl || (k & 7) == 7)) ? 2
+            const int mode = (nm > 0 && (8 * nm >= nd + nl || (k & 15) == 15)) ? 2
                              : (nl > 0 && (16 * nl >= nd || (k & 31) == 31 || nd == 0)) ? 1 : 0;
             if (p.active && (mode == 2 ? p.mc : (mode == 1 ? p.pend : !p.mc && !p.pend))) {
                 prefetch(p.r, a);

@@ -89,7 +89,8 @@ EXPORTS = ["rddmc_abi_version", "rddmc_last_error", "rddmc_table_bytes", "rddmc_
            "rddmc_tally", "rddmc_read_tables", "rddmc_philox_fill", "rddmc_mdn_bytes", "rddmc_mdn_init",
            "rddmc_mdn_set", "rddmc_mdn_get", "rddmc_mdn_forward", "rddmc_mdn_loss_grad", "rddmc_mdn_adam",
            "rddmc_surrogate_samples", "rddmc_surrogate_bytes", "rddmc_surrogate_window", "rddmc_surrogate_attach",
-           "rddmc_exitkernel_scratch_bytes", "rddmc_exitkernel_bytes", "rddmc_exitkernel_build"]
+           "rddmc_exitkernel_scratch_bytes", "rddmc_exitkernel_bytes", "rddmc_exitkernel_build",
+           "rddmc_exitlaw_samples"]
 
 _lib = None
 
@@ -136,12 +137,14 @@ def load(path: str = LIB_PATH):
     lib.rddmc_exitkernel_bytes.argtypes = [C.POINTER(Batch_t), vp, ekp, vp, sz, C.POINTER(sz), C.POINTER(C.c_uint64),
                                            vp, vp]
     lib.rddmc_exitkernel_build.argtypes = [C.POINTER(Batch_t), vp, ekp, vp, sz, vp, sz, vp]
+    lib.rddmc_exitlaw_samples.argtypes = [C.POINTER(Batch_t), vp, vp, vp, vp, C.c_int64, C.c_uint64, vp, sz, vp, vp,
+                                          vp]
     for name in ("rddmc_build_leakage", "rddmc_transport", "rddmc_transport_static", "rddmc_tally_reset", "rddmc_tally",
                  "rddmc_read_tables", "rddmc_philox_fill", "rddmc_mdn_bytes", "rddmc_mdn_init",
                  "rddmc_mdn_set", "rddmc_mdn_get", "rddmc_mdn_forward", "rddmc_mdn_loss_grad",
                  "rddmc_mdn_adam", "rddmc_surrogate_samples", "rddmc_surrogate_bytes",
                  "rddmc_surrogate_window", "rddmc_surrogate_attach", "rddmc_exitkernel_scratch_bytes",
-                 "rddmc_exitkernel_bytes", "rddmc_exitkernel_build"):
+                 "rddmc_exitkernel_bytes", "rddmc_exitkernel_build", "rddmc_exitlaw_samples"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib

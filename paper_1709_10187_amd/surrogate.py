@@ -148,6 +148,83 @@ def generate(probes, per_probe, dom: Domain, seed=0, max_steps=1 << 34, stream=N
     return Data(x[keep].contiguous(), y[keep].contiguous(), st[keep].contiguous())
 
 
+def generate_exact(probes, per_probe, dom: Domain, seed=0, bins_per_probe=8, pairs_per_call=2048,
+                   bins=None) -> Data:
+    """Samples of the probes' middle-cell exits drawn from the exact in-cell law
+    (rddmc_exitlaw_samples): per probe, per_probe samples spread over bins_per_probe random
+    core bins (or all from bins[i] of probe i).  Same layout as generate()."""
+    import torch
+    geoms = sorted({m.geometry for m in probes})
+    if len(geoms) > 1:
+        parts = [generate_exact([m for m in probes if m.geometry == gm], per_probe, dom, seed + 7919 * k,
+                                bins_per_probe, pairs_per_call,
+                                None if bins is None else [b for m, b in zip(probes, bins) if m.geometry == gm])
+                 for k, gm in enumerate(geoms)]
+        return Data(torch.cat([d.x for d in parts]), torch.cat([d.y for d in parts]),
+                    torch.cat([d.steps for d in parts]))
+    rng = np.random.default_rng(seed + 3)
+    batch = rddmc.Batch(probes)
+    tables = torch.empty(rddmc.table_bytes(batch), dtype=torch.uint8, device="cuda")
+    rddmc.build_leakage(batch, tables)
+    pc, ps, cnt = [], [], []
+    for ci, m in enumerate(probes):
+        js = core_bins(m, dom.x_core)
+        if bins is not None:
+            pick = np.array([int(bins[ci])])
+        else:
+            pick = rng.choice(js, size=min(bins_per_probe, len(js)), replace=len(js) < bins_per_probe)
+        share = np.full(len(pick), per_probe // len(pick))
+        share[:per_probe - share.sum()] += 1
+        for j, k in zip(pick, share):
+            pc.append(ci)
+            ps.append(m.n_bins + int(j))
+            cnt.append(int(k))
+    pc, ps, cnt = (np.ascontiguousarray(np.array(v, dtype=np.int32)) for v in (pc, ps, cnt))
+    nb_max = max(m.n_bins for m in probes)
+    lib = rddmc.load()
+    xs, ys = [], []
+    for a in range(0, len(pc), pairs_per_call):
+        b = min(len(pc), a + pairs_per_call)
+        n = b - a
+        rows = int(cnt[a:b].sum())
+        x = torch.empty((rows, 16), dtype=torch.float32, device="cuda")
+        y = torch.empty((rows, 3), dtype=torch.float32, device="cuda")
+        scr = torch.empty(6 * 256 + 20 * n + 88 * nb_max * n, dtype=torch.uint8, device="cuda")
+        ca, sa, na = (np.ascontiguousarray(v[a:b]) for v in (pc, ps, cnt))
+        rddmc._check(lib.rddmc_exitlaw_samples(batch.ref(), rddmc.C.c_void_p(tables.data_ptr()), ca.ctypes.data,
+                                               sa.ctypes.data, na.ctypes.data, n, int(seed) * 7 + a,
+                                               rddmc.C.c_void_p(scr.data_ptr()), scr.numel(),
+                                               rddmc.C.c_void_p(x.data_ptr()), rddmc.C.c_void_p(y.data_ptr()),
+                                               None))
+        xs.append(x)
+        ys.append(y)
+    x = torch.cat(xs)
+    y = torch.cat(ys)
+    return Data(x, y, torch.zeros(x.shape[0], dtype=torch.int64, device="cuda"))
+
+
+def expected_subwalk(m) -> float:
+    """Rough length of a middle-cell sub-walk of a probe, 0.6 tau_c / dx^2 steps (the scaling
+    measured on the sub-walk data): the split between run sub-walks and exact-law draws."""
+    e = np.asarray(m.bin_edges)
+    return 0.6 * float(m.k0[1]) * float(m.faces[0][2] - m.faces[0][1]) / float(e[1] - e[0]) ** 2
+
+
+def generate_mixed(probes, per_probe, dom: Domain, seed=0, step_budget=2.0e6, max_steps=1 << 30) -> Data:
+    """Training data over a wide domain: probes whose sub-walks are expected to take at most
+    step_budget steps run them (generate); the rest draw from the exact in-cell law."""
+    import torch
+    short = [m for m in probes if expected_subwalk(m) <= step_budget]
+    long = [m for m in probes if expected_subwalk(m) > step_budget]
+    parts = []
+    if short:
+        parts.append(generate(short, per_probe, dom, seed=seed, max_steps=max_steps))
+    if long:
+        parts.append(generate_exact(long, per_probe, dom, seed=seed + 1))
+    return Data(torch.cat([d.x for d in parts]), torch.cat([d.y for d in parts]),
+                torch.cat([d.steps for d in parts]))
+
+
 def train(net: rddmc.Mdn, data: Data, epochs=30, batch=4096, lr=2e-3, lr_final=2e-4, seed=0, log=None):
     """Adam on shuffled minibatches (cosine-decayed learning rate); returns the per-epoch
     mean training loss."""

@@ -70,6 +70,34 @@ def test_subwalk_data_matches_exact_exit_law(args):
     assert abs(steps.mean() - ex.steps) < 4.5 * steps.std() / math.sqrt(n)
 
 
+@pytest.mark.parametrize("args", [(3.0e7, 4.7e-4, 1.5, -0.2, None, False), (2.0e8, 2.0e-3, 3.0, -0.4, 40.0, True),
+                                  (5.0e5, 1.0e-3, 0.8, 0.0, 12.0, False)])
+def test_exact_law_samples_match_exact_exit_law(args):
+    """Training samples drawn from the exact in-cell law (for cells whose sub-walks are too
+    long to run) against O5: face split, exit bins, and the time's mean and variance (exact by
+    construction of the draw).  The start bin is read back from the samples' features."""
+    m = sg.probe_medium(*args)
+    n = 40000
+    print(f"[surrogate] exact-law samples {args} ({m.n_bins} bins): {n}", flush=True)
+    d = sg.generate_exact([m], n, DOM, seed=4, bins_per_probe=1)
+    assert d.n == n
+    x = d.x.cpu().numpy()
+    assert np.all(x[:, 2] == x[0, 2])
+    e = np.asarray(m.bin_edges)
+    j = int(np.argmin(np.abs(0.5 * (e[:-1] + e[1:]) - 3.0 * float(x[0, 2]))))
+    t = tb.build(m)
+    ex = exitlaw.exit_law(t, 1, j)
+    y = d.y.cpu().numpy().astype(np.float64)
+    H = _exit_hist(m, y[:, 0], _scale(m) * np.sinh(y[:, 1]))
+    p0 = ex.prob[0].sum()
+    assert abs(H[0].sum() - p0) < 4.5 * math.sqrt(p0 * (1 - p0) / n)
+    r = compare_exact(np.round(_coarse(H) * n).ravel(), _coarse(ex.prob).ravel(), n)
+    assert_spectrum_matches(r)
+    dt = np.exp(y[:, 2]) * (m.faces[0][2] - m.faces[0][1])
+    assert abs(dt.mean() - ex.t_mean) < 4.5 * math.sqrt(ex.t_var / n)
+    assert dt.var() == pytest.approx(ex.t_var, rel=0.1)
+
+
 @pytest.fixture(scope="module")
 def trained():
     t0 = time.time()
