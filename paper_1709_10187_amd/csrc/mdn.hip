@@ -7,14 +7,21 @@
 // at o[80+k] / o[96+k], correlation 0.95 tanh(o[112+k]); log-sigmas clamped to [-6, 4]).
 // The loss is the mean negative log-likelihood of the targets.
 //
-// Every matrix product is one launch of `gemm`: a wave computes a 32x32 FP32 tile with
-// 32x32x16 MFMA steps; A and B operands are read as BF16 with arbitrary strides (so
-// transposed operands cost strided loads, never a copy), and an epilogue adds the bias,
-// applies GELU or its derivative, and stores FP32 and / or BF16.
+// Every matrix product is one launch of `gemm`: a block of four waves computes a 64x64 FP32
+// tile, 32x32 per wave with 32x32x16 MFMA steps, from 64x32 slices of A and B staged in LDS.
+// The slices are read from global memory with 16-byte loads along whichever dimension of the
+// operand is contiguous (K for activations and transposed weights, M or N for the operands of
+// the weight gradients, which are transposed on their way into LDS), so no operand is copied
+// or read element by element.  An epilogue adds the bias, applies GELU or its derivative, and
+// stores FP32 and / or BF16.  The weight-gradient products contract over the batch (4096 rows
+// for 16 output tiles): they split K over blocks, write FP32 partials, and a second kernel
+// adds the partials to the gradient in a fixed order (the result does not depend on timing).
 #include <hip/hip_runtime.h>
 
 #include <math.h>
 #include <stdint.h>
+
+#include <algorithm>
 
 #include "rddmc_internal.h"
 
@@ -45,6 +52,7 @@ enum Epilogue : int {
     EP_GELU = 1,           // Z = AB + bias -> f32 Z, bf16 gelu(Z)
     EP_GELU_BACK = 2,      // dH = AB -> bf16 dH * gelu'(Z)   (Z given, f32)
     EP_ACCUM_F32 = 3,      // C += AB
+    EP_PARTIAL = 4,        // P[split] = A[., ks] B[ks, .] (K split over blocks; summed by splitk_add)
 };
 
 struct GemmArgs {
@@ -56,57 +64,107 @@ struct GemmArgs {
     float *C;              // f32 [M, N] row-major (ldc = N)
     uint16_t *Cb;          // bf16 [M, N] row-major
     const float *Z;        // f32 [M, N] for the GELU derivative
+    float *P;              // f32 [splits, M, N] partial products (EP_PARTIAL)
     int mode;
+    int splits;            // K ranges (multiples of 32) per output tile; 1 unless EP_PARTIAL
 };
 
-__device__ __forceinline__ bf16x8 load8(const uint16_t *p, int64_t stride)
+constexpr int kTile = 64, kKs = 32, kLdsRow = 40;   // block tile, K slice, padded LDS row (bf16)
+
+// Stage the K slice [k0, k0 + 32) of rows [r0, r0 + 64) of an operand into L[row][k] (bf16,
+// rows padded to 40): element (r, k) lives at X[r * sr + k * sk].  K-contiguous operands
+// (sk == 1) are read 8 k at a time along a row, row-contiguous ones (sr == 1) 8 rows at a
+// time along a k, anything else element by element; out-of-range elements read as zero.
+__device__ __forceinline__ void stage(uint16_t *__restrict__ L, const uint16_t *__restrict__ X, int64_t sr,
+                                      int64_t sk, int rows, int K, int r0, int k0, int t)
 {
-    union {
-        uint16_t h[8];
-        bf16x8 v;
-        uint4 q;
-    } u;
-    if (stride == 1) {
-        u.q = *reinterpret_cast<const uint4 *>(p);
-    } else {
+    if (sk == 1) {
+        const int r = t >> 2, c = (t & 3) << 3;
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        const int gr = r0 + r, gk = k0 + c;
+        if (gr < rows && gk + 8 <= K) {
+            v = *reinterpret_cast<const uint4 *>(X + (int64_t)gr * sr + gk);
+        } else if (gr < rows) {
+            uint16_t h[8];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) u.h[i] = p[i * stride];
+            for (int e = 0; e < 8; ++e) h[e] = gk + e < K ? X[(int64_t)gr * sr + gk + e] : (uint16_t)0;
+            v = make_uint4(h[0] | ((uint32_t)h[1] << 16), h[2] | ((uint32_t)h[3] << 16), h[4] | ((uint32_t)h[5] << 16),
+                           h[6] | ((uint32_t)h[7] << 16));
+        }
+        *reinterpret_cast<uint4 *>(L + r * kLdsRow + c) = v;
+    } else if (sr == 1) {
+        const int kk = t >> 3, c = (t & 7) << 3;
+        const int gk = k0 + kk, gr = r0 + c;
+        uint16_t h[8];
+        if (gk < K && gr + 8 <= rows) {
+            const uint4 v = *reinterpret_cast<const uint4 *>(X + (int64_t)gk * sk + gr);
+            h[0] = (uint16_t)v.x; h[1] = (uint16_t)(v.x >> 16); h[2] = (uint16_t)v.y; h[3] = (uint16_t)(v.y >> 16);
+            h[4] = (uint16_t)v.z; h[5] = (uint16_t)(v.z >> 16); h[6] = (uint16_t)v.w; h[7] = (uint16_t)(v.w >> 16);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) h[e] = (gk < K && gr + e < rows) ? X[(int64_t)gk * sk + gr + e] : (uint16_t)0;
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) L[(c + e) * kLdsRow + kk] = h[e];
+    } else {
+        for (int q = t; q < kTile * kKs; q += 256) {
+            const int r = q / kKs, kk = q % kKs;
+            const int gr = r0 + r, gk = k0 + kk;
+            L[r * kLdsRow + kk] = (gr < rows && gk < K) ? X[(int64_t)gr * sr + (int64_t)gk * sk] : (uint16_t)0;
+        }
     }
-    return u.v;
 }
 
-// One wave per 32x32 output tile.  Lane l supplies A rows m0 + (l % 32), k-slice
-// [(l / 32) * 8, +8) of each 16-deep step, B columns n0 + (l % 32) with the same k-slice;
-// its 16 accumulators hold C rows m0 + 8 (r / 4) + 4 (l / 32) + (r % 4), column n0 + l % 32.
+// Block (tile_m, tile_n, split) of 256 lanes: wave w owns rows m0 + 32 (w >> 1), columns
+// n0 + 32 (w & 1).  Lane l supplies A row (l % 32), k-slice [(l / 32) * 8, +8) of each 16-deep
+// step from LDS, likewise B column (l % 32); its 16 accumulators hold rows
+// 8 (r / 4) + 4 (l / 32) + (r % 4) of the wave's sub-tile, column l % 32.
 __global__ __launch_bounds__(256) void gemm(GemmArgs g)
 {
-    const int lane = threadIdx.x & 63;
-    const int wave = (blockIdx.x * (blockDim.x >> 6)) + (threadIdx.x >> 6);
-    const int tiles_n = (g.N + 31) >> 5;
-    const int tiles = ((g.M + 31) >> 5) * tiles_n;
-    if (wave >= tiles) return;
-    const int m0 = (wave / tiles_n) << 5, n0 = (wave % tiles_n) << 5;
+    __shared__ __attribute__((aligned(16))) uint16_t As[kTile * kLdsRow];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[kTile * kLdsRow];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int tiles_n = (g.N + kTile - 1) / kTile, tiles_m = (g.M + kTile - 1) / kTile;
+    const int tile = blockIdx.x % (tiles_m * tiles_n), split = blockIdx.x / (tiles_m * tiles_n);
+    const int m0 = (tile / tiles_n) * kTile, n0 = (tile % tiles_n) * kTile;
+    // this block's K range: whole slices, the last split takes the remainder
+    const int nks = (g.K + kKs - 1) / kKs;
+    const int per = (nks + g.splits - 1) / g.splits;
+    const int ks_lo = split * per, ks_hi = min(nks, ks_lo + per);
     const int r32 = lane & 31, kh = (lane >> 5) << 3;
+    const int wm = (w >> 1) << 5, wn = (w & 1) << 5;
     f32x16 acc;
 #pragma unroll
     for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
-    const bool arow = m0 + r32 < g.M, bcol = n0 + r32 < g.N;
-    const uint16_t *pa = g.A + (int64_t)(arow ? m0 + r32 : 0) * g.sam + (int64_t)kh * g.sak;
-    const uint16_t *pb = g.B + (int64_t)kh * g.sbk + (int64_t)(bcol ? n0 + r32 : 0) * g.sbn;
-    bf16x8 zero;
+    for (int ks = ks_lo; ks < ks_hi; ++ks) {
+        const int k0 = ks * kKs;
+        // A rows are M, B "rows" are N with element (n, k) at B[n * sbn + k * sbk]
+        stage(As, g.A, g.sam, g.sak, g.M, g.K, m0, k0, t);
+        stage(Bs, g.B, g.sbn, g.sbk, g.N, g.K, n0, k0, t);
+        __syncthreads();
 #pragma unroll
-    for (int i = 0; i < 8; ++i) zero[i] = (__bf16)0.0f;
-    for (int k = 0; k < g.K; k += 16) {
-        const bf16x8 a = arow ? load8(pa + (int64_t)k * g.sak, g.sak) : zero;
-        const bf16x8 b = bcol ? load8(pb + (int64_t)k * g.sbk, g.sbk) : zero;
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+        for (int h = 0; h < kKs; h += 16) {
+            const bf16x8 a = *reinterpret_cast<const bf16x8 *>(As + (wm + r32) * kLdsRow + h + kh);
+            const bf16x8 b = *reinterpret_cast<const bf16x8 *>(Bs + (wn + r32) * kLdsRow + h + kh);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+        }
+        __syncthreads();
     }
-    const int col = n0 + r32;
+    const int col = n0 + wn + r32;
     if (col >= g.N) return;
+    if (g.mode == EP_PARTIAL) {
+        float *P = g.P + (int64_t)split * g.M * g.N;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int row = m0 + wm + ((r >> 2) << 3) + ((lane >> 5) << 2) + (r & 3);
+            if (row < g.M) P[(int64_t)row * g.N + col] = acc[r];
+        }
+        return;
+    }
     const float bv = g.bias ? g.bias[col] : 0.0f;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-        const int row = m0 + ((r >> 2) << 3) + ((lane >> 5) << 2) + (r & 3);
+        const int row = m0 + wm + ((r >> 2) << 3) + ((lane >> 5) << 2) + (r & 3);
         if (row >= g.M) continue;
         const int64_t o = (int64_t)row * g.N + col;
         const float v = acc[r] + bv;
@@ -124,8 +182,19 @@ __global__ __launch_bounds__(256) void gemm(GemmArgs g)
     }
 }
 
+// C[i] += sum over splits of P[split][i], splits in order.
+__global__ void splitk_add(const float *__restrict__ P, int splits, int64_t n, float *__restrict__ C)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float v = 0.0f;
+    for (int q = 0; q < splits; ++q) v += P[(int64_t)q * n + i];
+    C[i] += v;
+}
+
 // ---- parameter layout ---------------------------------------------------------------
 constexpr int kIn = 16, kHid = 256, kOut = 128, kComp = 16;
+constexpr int kMaxSplits = 16;     // K splits of a weight-gradient product
 constexpr int64_t kW1 = 0, kB1 = kW1 + kIn * kHid, kW2 = kB1 + kHid, kB2 = kW2 + kHid * kHid, kW3 = kB2 + kHid,
                   kB3 = kW3 + kHid * kHid, kW4 = kB3 + kHid, kB4 = kW4 + kHid * kOut, kNParams = kB4 + kOut;
 constexpr int64_t kLayerW[4] = {kW1, kW2, kW3, kW4};
@@ -162,6 +231,7 @@ struct WorkView {
     float *o;                      // [cap, 128]
     uint16_t *dout;                // [cap, 128]
     uint16_t *dz[2];               // [cap, 256] ping-pong
+    float *part;                   // [kMaxSplits, 256, 256] split-K partials of a weight gradient
     float *loss;                   // [1]
 };
 
@@ -180,6 +250,7 @@ __host__ __device__ inline WorkView work_view(void *base, int64_t cap)
     w.o = reinterpret_cast<float *>(take(4ull * cap * kOut));
     w.dout = reinterpret_cast<uint16_t *>(take(2ull * cap * kOut));
     for (int l = 0; l < 2; ++l) w.dz[l] = reinterpret_cast<uint16_t *>(take(2ull * cap * kHid));
+    w.part = reinterpret_cast<float *>(take(4ull * kMaxSplits * kHid * kHid));
     w.loss = reinterpret_cast<float *>(take(256));
     return w;
 }
@@ -339,8 +410,12 @@ __global__ void adam_kernel(ParamView p, float lr, float b1, float b2, float eps
 // ---- host orchestration -----------------------------------------------------------------
 hipError_t launch_gemm(const GemmArgs &g, hipStream_t s)
 {
-    const int tiles = ((g.M + 31) / 32) * ((g.N + 31) / 32);
-    gemm<<<(tiles + 3) / 4, 256, 0, s>>>(g);
+    const int tiles = ((g.M + kTile - 1) / kTile) * ((g.N + kTile - 1) / kTile);
+    gemm<<<(unsigned)(tiles * g.splits), 256, 0, s>>>(g);
+    if (g.mode == EP_PARTIAL) {
+        const int64_t n = (int64_t)g.M * g.N;
+        splitk_add<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(g.P, g.splits, n, g.C);
+    }
     return hipGetLastError();
 }
 
@@ -357,6 +432,7 @@ GemmArgs gemm_args(const uint16_t *A, int64_t sam, int64_t sak, const uint16_t *
     g.M = M;
     g.N = N;
     g.K = K;
+    g.splits = 1;
     return g;
 }
 
@@ -404,7 +480,9 @@ hipError_t loss_grad(const ParamView &p, const WorkView &w, const float *d_x, co
         const uint16_t *hin = l > 0 ? w.h[l - 1] : w.xb;
         // dW[K, N] += hin^T (K x mp) * dcur (mp x N)
         GemmArgs gw = gemm_args(hin, 1, K, dcur, dn, 1, K, N, mp);
-        gw.mode = EP_ACCUM_F32;
+        gw.mode = EP_PARTIAL;
+        gw.splits = std::max(1, std::min(kMaxSplits, mp / 256));
+        gw.P = w.part;
         gw.C = p.grad + kLayerW[l];
         if ((e = launch_gemm(gw, s)) != hipSuccess) return e;
         colsum_add<<<(N + 127) / 128, 128, 0, s>>>(dcur, mp, N, p.grad + kLayerB[l]);
