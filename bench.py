@@ -393,11 +393,11 @@ def bench_surrogate(args):
     import torch
     from paper_1709_10187_amd import media, rddmc
     from paper_1709_10187_amd import surrogate as sg
-    dom = sg.Domain(tau_min=1.0e5, tau_max=1.0e6, dx_min=0.5, dx_max=4.5)
+    dom, use = sg.train_domain(), sg.use_domain()
     t0 = time.perf_counter()
     probes = sg.sample_probes(sg.TRAIN_PROBES, dom, seed=11)
-    log(f"surrogate: {sg.TRAIN_PROBES} x {sg.TRAIN_PER_PROBE} sub-walks")
-    data = sg.generate(probes, sg.TRAIN_PER_PROBE, dom, seed=12, max_steps=1 << 30)
+    log(f"surrogate: {sg.TRAIN_PROBES} x {sg.TRAIN_PER_PROBE} samples (sub-walks and exact in-cell laws)")
+    data = sg.generate_mixed(probes, sg.TRAIN_PER_PROBE, dom, seed=12, step_budget=sg.TRAIN_STEP_BUDGET)
     torch.cuda.synchronize()
     t_data = time.perf_counter() - t0
     net = rddmc.Mdn(max_batch=4096, seed=0)
@@ -407,10 +407,10 @@ def bench_surrogate(args):
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t1
     clouds = [media.sweep_cloud_medium(c) for c in media.sweep_parameters()]
-    ids = [i for i in SURROGATE_CLOUDS if sg.window(clouds[i], dom)[1] >= sg.window(clouds[i], dom)[0]]
+    ids = [i for i in SURROGATE_CLOUDS if sg.window(clouds[i], use)[1] >= sg.window(clouds[i], use)[0]]
     meds = [clouds[i].with_packets(args.surrogate_packets) for i in ids]
     surr = rddmc.Problem(meds, streams=ids)
-    att = sg.Attached(surr, net, dom)
+    att = sg.Attached(surr, net, use)
     log(f"surrogate: {len(ids)} clouds, {att.n_states} window states")
     args.steps, args.warmup = 1, 0
     ts, _ = timed_steps(surr, 1, 0, surrogate=att.buffer)
@@ -423,8 +423,9 @@ def bench_surrogate(args):
     v_s, v_p = ns / ts, npl / tp
     out = base_line(
         args, v_s, ts, "bf16 network (f32 accumulate), f32 walk",
-        {"workload": f"{len(ids)} sweep clouds with cells in the trained domain (tau_c {dom.tau_min:g}-"
-                     f"{dom.tau_max:g}, dx {dom.dx_min}-{dom.dx_max}), one batch, {args.surrogate_packets} "
+        {"workload": f"{len(ids)} sweep clouds with cells in the surrogate's domain (used at tau_c {use.tau_min:g}-"
+                     f"{use.tau_max:g}, trained at {dom.tau_min:g}-{dom.tau_max:g}, dx {dom.dx_min}-{dom.dx_max}), "
+                     f"one batch, {args.surrogate_packets} "
                      "packets per cloud, surrogate and plain on the same packet ids",
          "clouds": ids, "window_states": int(att.n_states),
          "surrogate_calls_per_packet": sum(r.surrogate_calls for r in rs) / ns,

@@ -386,12 +386,31 @@ __global__ void nll_kernel(const float *__restrict__ o, const float *__restrict_
 }
 
 // column sums of a bf16 [M, N] matrix, added into out[N]
-__global__ void colsum_add(const uint16_t *__restrict__ d, int M, int N, float *__restrict__ out)
+// Column sums of a bf16 [M, N] matrix in two passes: block (column chunk of 64, row chunk of
+// `rows`) has 4 lanes per column each summing a quarter of the chunk's rows, reduced in LDS
+// to partial[row chunk][column]; colsum_finish adds the row chunks' partials to out in order.
+// At most kMaxSplits * kHid * kHid / N row chunks (the partial buffer), of at least 256 rows.
+__global__ __launch_bounds__(256) void colsum_partial(const uint16_t *__restrict__ d, int M, int N, int rows,
+                                                     float *__restrict__ part)
+{
+    __shared__ float red[4][64];
+    const int cl = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int c = blockIdx.x * 64 + cl;
+    const int r0 = blockIdx.y * rows;
+    float s = 0.0f;
+    if (c < N)
+        for (int r = r0 + g; r < min(M, r0 + rows); r += 4) s += bf2f(d[(int64_t)r * N + c]);
+    red[g][cl] = s;
+    __syncthreads();
+    if (g == 0 && c < N) part[(int64_t)blockIdx.y * N + c] = ((red[0][cl] + red[1][cl]) + red[2][cl]) + red[3][cl];
+}
+
+__global__ void colsum_finish(const float *__restrict__ part, int chunks, int N, float *__restrict__ out)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= N) return;
     float s = 0.0f;
-    for (int r = 0; r < M; ++r) s += bf2f(d[(int64_t)r * N + c]);
+    for (int q = 0; q < chunks; ++q) s += part[(int64_t)q * N + c];
     out[c] += s;
 }
 
@@ -485,7 +504,13 @@ hipError_t loss_grad(const ParamView &p, const WorkView &w, const float *d_x, co
         gw.P = w.part;
         gw.C = p.grad + kLayerW[l];
         if ((e = launch_gemm(gw, s)) != hipSuccess) return e;
-        colsum_add<<<(N + 127) / 128, 128, 0, s>>>(dcur, mp, N, p.grad + kLayerB[l]);
+        {
+            const int max_chunks = (int)(kMaxSplits * kHid * kHid / N);
+            const int rows = std::max(256, (mp + max_chunks - 1) / max_chunks);
+            const int chunks = (mp + rows - 1) / rows;
+            colsum_partial<<<dim3((N + 63) / 64, chunks), 256, 0, s>>>(dcur, mp, N, rows, w.part);
+            colsum_finish<<<(N + 127) / 128, 128, 0, s>>>(w.part, chunks, N, p.grad + kLayerB[l]);
+        }
         if (l == 0) break;
         // dz_{l-1}[mp, K] = (dcur [mp, N] * W^T [N, K]) * gelu'(z_{l-1}); B element (o, i) = W[i, o]
         GemmArgs gd = gemm_args(dcur, dn, 1, p.w + kLayerW[l], 1, N, mp, K, N);

@@ -27,10 +27,13 @@ from . import media, rddmc
 _A_1E4 = 4.702e-4
 _VTH_1E4 = 12.85
 
-# Training recipe: probe media, sub-walks per probe, epochs (Adam, cosine-decayed rate).
+# Training recipe: probe media, samples per probe, epochs (Adam, cosine-decayed rate), the step
+# budget above which a probe's samples come from the exact in-cell law instead of run
+# sub-walks.
 TRAIN_PROBES = 8192
 TRAIN_PER_PROBE = 128
 TRAIN_EPOCHS = 40
+TRAIN_STEP_BUDGET = 2.0e6
 
 
 @dataclasses.dataclass
@@ -50,6 +53,16 @@ class Domain:
     def cfg(self) -> rddmc.SurrogateCfg_t:
         return rddmc.SurrogateCfg_t(self.tau_min, self.tau_max, self.a_min, self.a_max, self.dx_min, self.dx_max,
                                     self.shift_max, self.g_min, self.g_max, self.x_core)
+
+
+def train_domain() -> "Domain":
+    """The trained domain: cell optical widths 1e4 .. 1e9, bins 0.5 .. 4.5 Doppler widths."""
+    return Domain(tau_min=1.0e4, tau_max=1.0e9, dx_min=0.5, dx_max=4.5)
+
+
+def use_domain() -> "Domain":
+    """Where the walk uses the network: the trained domain above tau_c = 1e5."""
+    return Domain(tau_min=1.0e5, tau_max=1.0e9, dx_min=0.5, dx_max=4.5)
 
 
 def probe_medium(tau_c, a, dx, shift, shell, odd_bins, f_mu=0.5, lam=0.7104) -> media.Medium:

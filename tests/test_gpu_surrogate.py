@@ -22,7 +22,8 @@ from tests._stats import assert_spectrum_matches, compare_exact
 
 pytestmark = pytest.mark.gpu
 
-DOM = sg.Domain(tau_min=1.0e5, tau_max=1.0e6, dx_min=0.5, dx_max=4.5)
+DOM = sg.train_domain()      # trained: tau_c 1e4 .. 1e9
+USE = sg.use_domain()        # used by the walk: tau_c > 1e5
 
 
 def _coarse(P, n_groups=40):
@@ -102,9 +103,10 @@ def test_exact_law_samples_match_exact_exit_law(args):
 def trained():
     t0 = time.time()
     probes = sg.sample_probes(sg.TRAIN_PROBES, DOM, seed=11)
-    print(f"[surrogate] generating {sg.TRAIN_PROBES} x {sg.TRAIN_PER_PROBE} sub-walks (tau {DOM.tau_min:g}.."
-          f"{DOM.tau_max:g}, dx {DOM.dx_min}..{DOM.dx_max})", flush=True)
-    data = sg.generate(probes, sg.TRAIN_PER_PROBE, DOM, seed=12, max_steps=1 << 30)
+    print(f"[surrogate] generating {sg.TRAIN_PROBES} x {sg.TRAIN_PER_PROBE} samples (tau {DOM.tau_min:g}.."
+          f"{DOM.tau_max:g}, dx {DOM.dx_min}..{DOM.dx_max}; sub-walks up to {sg.TRAIN_STEP_BUDGET:g} expected steps, "
+          "the exact in-cell law above)", flush=True)
+    data = sg.generate_mixed(probes, sg.TRAIN_PER_PROBE, DOM, seed=12, step_budget=sg.TRAIN_STEP_BUDGET)
     print(f"[surrogate]   {data.n} samples in {time.time() - t0:.1f} s", flush=True)
     net = rddmc.Mdn(max_batch=4096, seed=0)
     loss0 = float(net.loss_grad(data.x[:4096].contiguous(), data.y[:4096].contiguous()).cpu()[0])
@@ -156,7 +158,7 @@ def test_trained_network_against_exact_exit_law(trained):
         js = sg.core_bins(m, DOM.x_core)
         j = int(js[len(js) // 2])
         ex = exitlaw.exit_law(t, 1, j)
-        d = sg.generate([m], 32, DOM, seed=7, bins=[j])
+        d = sg.generate_exact([m], 4, DOM, seed=7, bins=[j])   # the state's features
         o = net.forward(d.x[:1]).cpu().numpy()[0]
         face, y1, y2 = _mixture_sample(o, 400000, rng)
         H = _exit_hist(m, face, _scale(m) * np.sinh(y1))
@@ -183,12 +185,12 @@ def test_surrogate_transport_matches_exact_chain_on_the_tally_grid_and_beats_pla
     net, _ = trained
     idx = 176
     m = media.sweep_cloud_medium(media.sweep_parameters()[idx]).with_packets(1 << 20)
-    win = sg.window(m, DOM)
+    win = sg.window(m, USE)
     assert win[1] >= win[0], "the target cloud must have cells in the trained domain"
     ref = chain.solve(m)
     n = int(m.n_packets)
     prob = rddmc.Problem(m)
-    att = sg.Attached(prob, net, DOM)
+    att = sg.Attached(prob, net, USE)
     print(f"[surrogate] cloud {idx}: window {win}, {att.n_states} states, {n} packets", flush=True)
     prob.run(seed=1, surrogate=att.buffer)
     r = prob.results()[0]
@@ -203,7 +205,7 @@ def test_surrogate_transport_matches_exact_chain_on_the_tally_grid_and_beats_pla
     rates = {}
     for leg in ("surrogate", "plain"):
         q = rddmc.Problem(m)
-        kw = dict(surrogate=sg.Attached(q, net, DOM).buffer) if leg == "surrogate" else {}
+        kw = dict(surrogate=sg.Attached(q, net, USE).buffer) if leg == "surrogate" else {}
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         q.run(seed=1, count=sub, **kw)
@@ -227,7 +229,7 @@ def test_surrogate_transport_matches_exact_chain(trained, idx):
     m = media.sweep_cloud_medium(media.sweep_parameters()[idx]).with_packets(1 << 17)
     ref = chain.solve(m)
     prob = rddmc.Problem(m)
-    att = sg.Attached(prob, net, DOM)
+    att = sg.Attached(prob, net, USE)
     n = int(m.n_packets)
     print(f"[surrogate] cloud {idx}: {att.n_states} states, {n} packets", flush=True)
     prob.run(seed=1, surrogate=att.buffer)
@@ -247,10 +249,10 @@ def test_surrogate_batch_every_cloud_against_exact_chain(trained):
     import bench
     net, _ = trained
     clouds = [media.sweep_cloud_medium(c) for c in media.sweep_parameters()]
-    ids = [i for i in bench.SURROGATE_CLOUDS if sg.window(clouds[i], DOM)[1] >= sg.window(clouds[i], DOM)[0]]
+    ids = [i for i in bench.SURROGATE_CLOUDS if sg.window(clouds[i], USE)[1] >= sg.window(clouds[i], USE)[0]]
     meds = [clouds[i].with_packets(2048) for i in ids]
     prob = rddmc.Problem(meds, streams=ids)
-    att = sg.Attached(prob, net, DOM)
+    att = sg.Attached(prob, net, USE)
     print(f"[surrogate] batch of {len(ids)} clouds, 2048 packets each", flush=True)
     prob.run(seed=1, surrogate=att.buffer)
     for i, m, r in zip(ids, meds, prob.results()):
@@ -273,7 +275,7 @@ def test_surrogate_runs_bit_identical_across_tail_modes(trained, moving):
         c = dataclasses.replace(c, v_max=0.0)
     m = media.sweep_cloud_medium(c)
     prob = rddmc.Problem(m)
-    att = sg.Attached(prob, net, DOM)
+    att = sg.Attached(prob, net, USE)
     out = []
     for tl in (-1, 0, 64):
         print(f"[surrogate] moving={moving} tail_lanes={tl}: 4096 packets", flush=True)
