@@ -40,6 +40,13 @@
  *    states have one more exponential distance, to absorption at rate k_a, and an absorbed
  *    packet is removed after that residence; MC flights meet Lya, dust scattering (k_s:
  *    isotropic, coherent in the comoving frame) and dust absorption (k_a) in proportion.
+ *  - Frequency groups (Sec. 5.3, static isothermal clouds): with P->group the thin states
+ *    carry a bin j instead of a continuous x; a flight meets the bin-averaged opacity k_ij
+ *    (eq. 14), and a scattering takes its outgoing bin from the flat-in-bin law of eq. 42 by
+ *    simulation: an x uniform in bin j, one scattering of the continuous law above (its own
+ *    throwaway direction), and the bin of the outgoing x (bins 0 and nb-1 take everything
+ *    below and above the grid); the packet's new direction is isotropic and independent of
+ *    that frequency change.  Crossings keep j; escapes are tallied in bin j.
  *  - Time-dependent estimators (eq. 17), unnormalised: at every census time t_e the packet's
  *    state is counted ('bin'), and its residence time in each state is summed per census
  *    interval ('path'); an MC packet's state is (cell, bin of its comoving x at the start of
@@ -88,6 +95,7 @@ typedef struct {
     const double *src_t;           /* [n_src*2] emission windows, or NULL (flash at t = 0) */
     int32_t n_census;              /* census intervals (0 = none) */
     const double *census;          /* [n_census+1] increasing census times */
+    int32_t group;                 /* 1: thin states use frequency groups (Sec. 5.3) */
 } oh_problem;
 
 typedef struct {
@@ -364,13 +372,13 @@ static void walk_packet(const oh_problem *P, uint64_t id, uint64_t seed, uint64_
         ++mcsteps;
         int fexit;
         double dwall = wall_distance(P, c, pos, n, left_inner, &fexit);
-        double kl = P->k0[c] * mc_voigt(P->a[c], x);
+        double kl = P->group ? P->k[c * nb + j] : P->k0[c] * mc_voigt(P->a[c], x);
         double ka = P->k_abs ? P->k_abs[c] : 0.0, ks = P->k_sca ? P->k_sca[c] : 0.0;
         double kx = kl + ks + ka;
         double ds = -log(ru(&r)) / kx;
         double p0[3] = {pos[0], pos[1], pos[2]};
         double u0 = n_dot_u(P, c, p0, n);
-        census_add(P, R, mc_state(P, c, x), t, t + fmin(ds, dwall));
+        census_add(P, R, P->group ? c * nb + j : mc_state(P, c, x), t, t + fmin(ds, dwall));
         if (ds < dwall) {
             for (int d = 0; d < 3; ++d) pos[d] += ds * n[d];
             t += ds;
@@ -379,6 +387,16 @@ static void walk_packet(const oh_problem *P, uint64_t id, uint64_t seed, uint64_
                 double uu2 = ru(&r) * kx;
                 if (uu2 < ka) { R->absorbed++; break; }
                 if (uu2 < ka + ks) { iso_dir(&r, n); left_inner = 0; continue; }   /* dust: coherent, isotropic */
+            }
+            if (P->group) {   /* eq. 42: the outgoing bin of a scattering of a bin-j packet */
+                double xg = P->edges[j] + (P->edges[j + 1] - P->edges[j]) * ru(&r);
+                double nd[3] = {n[0], n[1], n[2]};
+                int jg = locate(P->edges, nb, scatter(P->a[c], xg, nd, &r, 0.0));
+                j = jg < 0 ? 0 : (jg > nb - 1 ? nb - 1 : jg);
+                iso_dir(&r, n);
+                left_inner = 0;
+                if (P->thick[c * nb + j]) { mc = 0; R->to_ddmc++; }
+                continue;
             }
             x = scatter(P->a[c], x, n, &r, P->x_crit);
             left_inner = 0;
@@ -400,9 +418,12 @@ static void walk_packet(const oh_problem *P, uint64_t id, uint64_t seed, uint64_
         x += u0 - nu;                                   /* comoving x at the wall */
         int64_t nc = P->nbr[c * 2 + f];
         if (nc == -2) continue;                         /* no face (r = 0): cannot occur */
-        if (nc < 0) { tally_escape(R, P, f, x + nu, t); break; }
+        if (nc < 0) {
+            tally_escape(R, P, f, P->group ? 0.5 * (P->edges[j] + P->edges[j + 1]) : x + nu, t);
+            break;
+        }
         double xn = (x + nu) * sqrt(P->T[c] / P->T[nc]) - n_dot_u(P, nc, pos, n);
-        int jn = locate(P->edges, nb, xn);
+        int jn = P->group ? j : locate(P->edges, nb, xn);
         if (jn >= 0 && jn < nb && P->thick[nc * nb + jn]) {
             double N[3];
             face_normal(P, f, pos, N);

@@ -16,6 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "libo1walk1dh.so")
 TIME_BINS = 128
 STEP_BINS = 64
+GROUP_FLAG = 1 << 2     # a cloud's flag bit: thin states use frequency groups (Sec. 5.3)
 
 
 def build_lib():
@@ -32,7 +33,7 @@ class _Problem(C.Structure):
                 ("T", C.c_void_p), ("u", C.c_void_p), ("lambda_", C.c_double), ("x_crit", C.c_double),
                 ("n_src", C.c_int32), ("src_state", C.c_void_p), ("src_pos", C.c_void_p), ("src_x", C.c_void_p),
                 ("src_cdf", C.c_void_p), ("k_abs", C.c_void_p), ("k_sca", C.c_void_p), ("src_t", C.c_void_p),
-                ("n_census", C.c_int32), ("census", C.c_void_p)]
+                ("n_census", C.c_int32), ("census", C.c_void_p), ("group", C.c_int32)]
 
 
 class _Result(C.Structure):
@@ -105,6 +106,9 @@ def run(m, n_packets=None, seed=0, first_id=0, max_steps=(1 << 62), n_threads=No
     assert m.geometry in (tb.SLAB, tb.SPHERE)
     t = tabs if tabs is not None else tb.build(m)
     n = int(m.n_packets if n_packets is None else n_packets)
+    group = bool(int(m.flags) & GROUP_FLAG)
+    if group:   # frequency groups (Sec. 5.3): static, isothermal clouds
+        assert m.vel is None and np.all(np.asarray(m.temp) == np.asarray(m.temp).flat[0])
     keep = []
 
     def arr(a, dt):
@@ -139,7 +143,7 @@ def run(m, n_packets=None, seed=0, first_id=0, max_steps=(1 << 62), n_threads=No
                  arr(m.dust_sca, np.float64) if m.dust_sca is not None else None,
                  arr(tw, np.float64) if m.src_t is not None else None,
                  0 if m.census is None else len(m.census) - 1,
-                 arr(m.census, np.float64) if m.census is not None else None)
+                 arr(m.census, np.float64) if m.census is not None else None, int(group))
     rows = 2 if m.geometry == tb.SLAB else 1
     spec = np.zeros((rows, t.nb + 2), dtype=np.int64)
     th = np.zeros(TIME_BINS + 2, dtype=np.int64)

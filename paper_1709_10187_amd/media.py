@@ -87,6 +87,10 @@ class Medium:
         return dataclasses.replace(self, **kw)
 
 
+GROUP_MC = 1 << 2      # Medium.flags bit: thin states use frequency groups (Sec. 5.3 eq. 42)
+ALL_THIN = 1.0e300     # a tau_threshold above every state's optical width: no DDMC states
+
+
 def uniform_edges(x_max: float, n_bins: int) -> np.ndarray:
     """n_bins+1 edges over [-x_max, x_max], exactly antisymmetric, with an exact 0 edge
     whenever n_bins is even."""
