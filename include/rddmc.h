@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define RDDMC_ABI_VERSION 6
+#define RDDMC_ABI_VERSION 7
 
 typedef enum {
     RDDMC_OK = 0,
@@ -58,6 +58,8 @@ enum { RDDMC_SLAB = 0, RDDMC_SPHERE = 1, RDDMC_CART3D = 2 };
 /* rddmc_medium.flags */
 #define RDDMC_FLAG_DIRICHLET  (1u << 0)  /* vacuum faces: 2/(3 k dz^2) instead of eq. 10 with 2 lambda */
 #define RDDMC_FLAG_KEEP_RATES (1u << 1)  /* also store the FP64 rates (for table parity checks) */
+#define RDDMC_FLAG_GROUPS     (1u << 2)  /* continuous-MC states use frequency groups (Sec. 5.3) */
+#define RDDMC_MAX_GROUP_BINS  2048       /* largest n_bins of a cloud with RDDMC_FLAG_GROUPS */
 
 #define RDDMC_TIME_BINS 128              /* log10-uniform escape-time bins over [1e-3, 1e6] */
 #define RDDMC_STEP_BINS 64               /* floor(log2(steps per packet)) buckets */
@@ -119,6 +121,19 @@ enum { RDDMC_SLAB = 0, RDDMC_SPHERE = 1, RDDMC_CART3D = 2 };
  *                1D clouds only; n_census = 0 and census = NULL for none.
  * A 1D batch in which any cloud uses x_crit, dust, emission windows or a census is walked by
  * the hybrid 1D walk.
+ *
+ * Frequency groups (flags & RDDMC_FLAG_GROUPS; Sec. 5.3, eq. 42): the cloud's continuous-MC
+ * states carry a frequency bin instead of a continuous frequency.  A flight meets the bin's
+ * averaged opacity k_ij (eq. 14); a scattering draws the outgoing bin from the discrete
+ * redistribution P(j | j') = dx_j R_{j'->j} of eq. 42, built from R_II-A of Appendix A (isotropic
+ * scattering, coherent in the atom's frame, no recoil) with the incoming frequency uniform over
+ * its bin, and bins 0 and n_bins-1 taking every outgoing frequency below and above the grid; the
+ * new direction is isotropic, independent of the frequency change.  Crossings keep the bin;
+ * escapes are tallied in it.  Needs a 1D geometry, a static medium (vel NULL or zero), one
+ * temperature for all cells (one table per cloud), tau_threshold > 0 (thin states exist; a value
+ * above every k_ij w_i makes the cloud pure frequency-group Monte Carlo), x_crit = 0 and
+ * n_bins <= RDDMC_MAX_GROUP_BINS.  DDMC states, dust, emission windows and census estimators
+ * work as for continuous-MC states.
  */
 typedef struct {
     int32_t geometry;
@@ -283,8 +298,15 @@ rddmc_status rddmc_work_bytes(const rddmc_batch *batch, size_t *bytes);
  *   batch        host description, read during the call.
  *   d_tables     device buffer of >= rddmc_table_bytes bytes, 256-byte aligned.
  *   stream       hipStream_t (NULL = default stream); the call synchronises it.
+ * For clouds with RDDMC_FLAG_GROUPS it also builds, in FP64 (Sec. 5.3 eq. 42, Appendix A),
+ * the discrete redistribution P(j | j') of every pair of bins -- the u-integral of R_II-A over
+ * the outgoing bin, exchanged with the x-integration into elementary functions, normalised by
+ * the same integral over all x (pi H(a, x')) and averaged over x' in bin j', by Gauss-Legendre
+ * rules on segments between the integrands' breakpoints -- and, per incoming bin, a Walker
+ * alias table over the row normalised by its sum (rddmc_read_redistribution returns both).
  * Errors: EINVAL (bad grid or inputs), ESIZE (buffer), ENUMERIC (non-finite table entry),
- * EUNSUPPORTED (mixed geometries in one batch), EHIP.
+ * EUNSUPPORTED (mixed geometries in one batch; frequency groups in a 3D, moving or
+ * non-isothermal cloud), EHIP.
  */
 rddmc_status rddmc_build_leakage(const rddmc_batch *batch, void *d_tables, size_t table_bytes,
                                  void *stream);
@@ -368,6 +390,19 @@ rddmc_status rddmc_tally(const rddmc_batch *batch, const void *d_tally, size_t t
  */
 rddmc_status rddmc_read_tables(const rddmc_batch *batch, const void *d_tables, int32_t cloud,
                                double *k, double *rates, void *hot, void *lo_words, void *stream);
+
+/*
+ * Frequency-group tables of cloud `cloud` (RDDMC_FLAG_GROUPS; else EINVAL):
+ *   prob   [n_bins * n_bins] FP64 P(j | j') = dx_j R_{j'->j} (eq. 42) at prob[j' * n_bins + j], as
+ *          computed (each row sums to 1 within the quadrature's error; pairs of bins more than 13
+ *          apart are 0, below e^-42);
+ *   alias  [n_bins * n_bins * 2] u32 {threshold, alias bin} per row j' and column: a draw picks
+ *          column c = (w1 * n_bins) >> 32 from a 32-bit word w1 and keeps c when a second word is
+ *          below the threshold, else takes the alias bin.
+ * Either pointer may be NULL.  Synchronises the stream.
+ */
+rddmc_status rddmc_read_redistribution(const rddmc_batch *batch, const void *d_tables, int32_t cloud, double *prob,
+                                       uint32_t *alias, void *stream);
 
 /*
  * Fill d_out[4*n] with Philox4x32-10 blocks for counters (c0 + i, c1, c2, c3), i < n, under

@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "librddmc.so")
 SOURCES = ["capi.hip", "build.hip", "transport.hip", "transport3d.hip", "transport1dh.hip", "mdn.hip", "surrogate.hip",
-           "exitkernel.hip"]
+           "exitkernel.hip", "redist.hip"]
 ARCH = os.environ.get("RDDMC_OFFLOAD_ARCH", "gfx950")
 
 

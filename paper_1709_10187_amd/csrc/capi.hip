@@ -150,6 +150,21 @@ rddmc_status validate_cloud(const rddmc_medium &m, int idx)
     const bool extras = m.dust_abs || m.dust_sca || m.src_t || m.n_census > 0;
     if (extras && m.geometry == RDDMC_CART3D)
         return fail(RDDMC_EUNSUPPORTED, "cloud %d: dust, emission windows and census tallies are for 1D clouds", idx);
+    if (m.flags & RDDMC_FLAG_GROUPS) {   // frequency groups (Sec. 5.3): one table per cloud
+        if (m.geometry == RDDMC_CART3D)
+            return fail(RDDMC_EUNSUPPORTED, "cloud %d: frequency groups are for 1D clouds", idx);
+        if (m.vel)
+            for (int64_t c = 0; c < nc; ++c)
+                if (m.vel[c] != 0.0) return fail(RDDMC_EUNSUPPORTED, "cloud %d: frequency groups need a static medium", idx);
+        for (int64_t c = 1; c < nc; ++c)
+            if (m.temp[c] != m.temp[0])
+                return fail(RDDMC_EUNSUPPORTED, "cloud %d: frequency groups need one temperature for all cells", idx);
+        if (!(m.tau_threshold > 0.0))
+            return fail(RDDMC_EINVAL, "cloud %d: frequency groups need continuous-MC states (tau_threshold > 0)", idx);
+        if (m.x_crit != 0.0) return fail(RDDMC_EINVAL, "cloud %d: core-skipping does not apply to frequency groups", idx);
+        if (m.n_bins > RDDMC_MAX_GROUP_BINS)
+            return fail(RDDMC_EINVAL, "cloud %d: frequency groups take at most %d bins", idx, RDDMC_MAX_GROUP_BINS);
+    }
     return RDDMC_OK;
 }
 
@@ -318,6 +333,9 @@ rddmc_status make_layout(const rddmc_batch *b, Layout &L)
         c.off_dust = c.dusty ? take(16ull * c.nc) : 0;
         c.off_src_t = hybrid1d ? take(16ull * c.n_src) : 0;
         c.off_census = c.n_census > 0 ? take(8ull * (c.n_census + 1)) : 0;
+        c.groups = (m.flags & RDDMC_FLAG_GROUPS) ? 1 : 0;
+        c.off_grp_prob = c.groups ? take(8ull * c.nb * c.nb) : 0;
+        c.off_grp_alias = c.groups ? take(8ull * c.nb * c.nb) : 0;
         c.n_pix = m.geometry == RDDMC_CART3D
                       ? 2ull * ((uint64_t)c.n[1] * c.n[2] + (uint64_t)c.n[0] * c.n[2] + (uint64_t)c.n[0] * c.n[1])
                       : 0;
@@ -494,9 +512,12 @@ rddmc_status rddmc_build_leakage(const rddmc_batch *batch, void *d_tables, size_
                 return hip_fail(e, "hipMemcpyAsync(census)");
         }
     }
-    for (int ci = 0; ci < L.h.n_clouds; ++ci)
+    for (int ci = 0; ci < L.h.n_clouds; ++ci) {
         if ((e = launch_build(L.clouds[ci], ci, static_cast<uint8_t *>(d_tables), s)) != hipSuccess)
             return hip_fail(e, "build kernels");
+        if ((e = launch_build_redistribution(L.clouds[ci], static_cast<uint8_t *>(d_tables), s)) != hipSuccess)
+            return hip_fail(e, "redistribution kernels");
+    }
     if ((e = launch_build_line_tables(L.h, static_cast<uint8_t *>(d_tables), s)) != hipSuccess)
         return hip_fail(e, "line-table kernels");
     uint32_t flags = 0;
@@ -646,6 +667,28 @@ rddmc_status rddmc_read_tables(const rddmc_batch *batch, const void *d_tables, i
     if (lo_words && (e = hipMemcpyAsync(lo_words, base + c.off_lo_words, 16 * c.n_states, hipMemcpyDeviceToHost,
                                         s)) != hipSuccess)
         return hip_fail(e, "read lo words");
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    return RDDMC_OK;
+}
+
+rddmc_status rddmc_read_redistribution(const rddmc_batch *batch, const void *d_tables, int32_t cloud, double *prob,
+                                       uint32_t *alias, void *stream)
+{
+    Layout L;
+    rddmc_status st = make_layout(batch, L);
+    if (st != RDDMC_OK) return st;
+    if (!d_tables) return fail(RDDMC_EINVAL, "d_tables is NULL");
+    if (cloud < 0 || cloud >= L.h.n_clouds) return fail(RDDMC_EINVAL, "cloud index out of range");
+    const DevCloud &c = L.clouds[cloud];
+    if (!c.groups) return fail(RDDMC_EINVAL, "cloud %d has no frequency groups (RDDMC_FLAG_GROUPS)", cloud);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const uint8_t *base = static_cast<const uint8_t *>(d_tables);
+    const uint64_t n = (uint64_t)c.nb * c.nb;
+    hipError_t e;
+    if (prob && (e = hipMemcpyAsync(prob, base + c.off_grp_prob, 8 * n, hipMemcpyDeviceToHost, s)) != hipSuccess)
+        return hip_fail(e, "read redistribution probabilities");
+    if (alias && (e = hipMemcpyAsync(alias, base + c.off_grp_alias, 8 * n, hipMemcpyDeviceToHost, s)) != hipSuccess)
+        return hip_fail(e, "read alias tables");
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
     return RDDMC_OK;
 }

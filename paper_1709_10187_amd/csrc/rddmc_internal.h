@@ -104,6 +104,10 @@ struct alignas(16) DevCloud {
     uint64_t census_bin_off;     // int64 word offsets (in the cloud's tally block) of the 'bin'
     uint64_t census_path_off;    //   counts [(n_census+1) n_states], 'path' times [n_census n_states]
     uint64_t census_accel_off;   //   and eq. 18 sums [n_census nc]
+    uint64_t off_grp_prob;       // frequency groups: f64 [nb * nb] P(j | j') of eq. 42, row j'
+    uint64_t off_grp_alias;      //   u32x2 [nb * nb] Walker alias table per row {threshold, alias}
+    int32_t groups;              // thin states carry a frequency group (Sec. 5.3)
+    int32_t pad1;
 };
 
 constexpr double kPathFix = RDDMC_CENSUS_PATH_FIX;   // residence-time fixed point (2^24 per length/c)
@@ -151,6 +155,7 @@ hipError_t mdn_loss_grad(void *d_params, void *d_work, int64_t cap, const float 
                          float *d_loss, hipStream_t s);
 hipError_t mdn_adam(void *d_params, int64_t step, float lr, hipStream_t s);
 const float *mdn_outputs(void *d_work, int64_t cap);
+hipError_t launch_build_redistribution(const DevCloud &c, uint8_t *d_tables, hipStream_t s);
 hipError_t launch_build_line_tables(const DevHeader &h, uint8_t *d_tables, hipStream_t s);
 hipError_t launch_walk3d(const uint8_t *d_tables, const DevHeader &h, const rddmc_run &run, uint64_t first,
                          uint64_t count, unsigned long long *d_tally, unsigned long long *d_work, hipStream_t s);

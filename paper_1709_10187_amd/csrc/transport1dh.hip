@@ -31,6 +31,9 @@
 // its overlap with each census interval to that state's residence time (2^-24 units) and
 // counts the packet in that state at every census time it spans.  Packets start at t = 0 or
 // uniformly inside their source's emission window.
+// Frequency groups (Sec. 5.3): in a cloud built with them, thin states carry a bin instead of
+// a continuous frequency; flights meet the bin-averaged opacity and scatterings draw the
+// outgoing bin from the eq. 42 alias table of the packet's bin.
 // Escapes add face row (slab: face; sphere: one row), lab bin and time to the int64 tallies.
 #include <hip/hip_runtime.h>
 
@@ -472,6 +475,101 @@ __device__ void mc_step1(Pk1 &p, const DevCloud &c, const uint8_t *__restrict__ 
     p.x = xn;
 }
 
+// One frequency-group Monte Carlo event (Sec. 5.3) of a packet in a thin state of a static,
+// isothermal cloud: the packet carries bin j; a flight meets the bin-averaged opacity k_ij
+// (eq. 14) plus any dust; a scattering takes the outgoing bin from row j of the cloud's alias
+// table of eq. 42 (two 32-bit words) and an isotropic direction.  Boundaries as in mc_step1,
+// with the bin unchanged across faces (no velocities, one temperature).
+template <bool SPH>
+__device__ void grp_step1(Pk1 &p, const DevCloud &c, const uint8_t *__restrict__ tb, const McArgs &a,
+                          unsigned long long *__restrict__ tally)
+{
+    ++p.mcs;
+    const double *fz = faces_of(c, tb, 0);
+    const double *kt = reinterpret_cast<const double *>(tb + c.off_k);
+    const int64_t s = (int64_t)p.cell * c.nb + p.j;
+    int fexit = 1;
+    const float dwall = wall_distance<SPH>(fz, p.cell, p.pos, p.n, p.left_inner, fexit);
+    const float kl = (float)kt[s];
+    float ka = 0.0f, ks = 0.0f;
+    if (c.dusty) {
+        const float4 m1c = reinterpret_cast<const float4 *>(tb + c.off_mcell)[2 * p.cell + 1];
+        ks = m1c.y;
+        ka = m1c.z;
+    }
+    const float kx = kl + ks + ka;
+    const float ds = -__logf(uf(draw(p.r, a))) / kx;
+    if (c.n_census > 0) census_add(c, tb, tally, s, p.t, p.t + (double)fminf(ds, dwall));
+    if (ds < dwall) {   // an interaction
+        p.pos.x = fmaf(ds, p.n.x, p.pos.x);
+        p.pos.y = fmaf(ds, p.n.y, p.pos.y);
+        p.pos.z = fmaf(ds, p.n.z, p.pos.z);
+        p.t += (double)ds;
+        p.left_inner = false;
+        if (c.dusty) {
+            const float v = uf(draw(p.r, a)) * kx;
+            if (v < ka) {
+                finish1(p, c, tally, false, 0, 0, true);
+                return;
+            }
+            if (v < ka + ks) {   // dust: isotropic, the bin unchanged
+                p.n = iso_dir(p.r, a);
+                return;
+            }
+        }
+        // eq. 42: the outgoing bin from the row's alias table
+        const uint32_t w1 = draw(p.r, a), w2 = draw(p.r, a);
+        const int col = (int)(((uint64_t)w1 * (uint32_t)c.nb) >> 32);
+        const uint2 ent = reinterpret_cast<const uint2 *>(tb + c.off_grp_alias)[(int64_t)p.j * c.nb + col];
+        const int jj = w2 < ent.x ? col : (int)ent.y;
+        p.n = iso_dir(p.r, a);
+        p.j = jj;
+        if (reinterpret_cast<const uint4 *>(tb + c.off_hot)[(int64_t)p.cell * c.nb + jj].w & kFlagThick) {
+            p.mc = false;
+            ++p.toddmc;
+        }
+        return;
+    }
+    // boundary crossing: put the point exactly on its plane or sphere
+    p.pos.x = fmaf(dwall, p.n.x, p.pos.x);
+    p.pos.y = fmaf(dwall, p.n.y, p.pos.y);
+    p.pos.z = fmaf(dwall, p.n.z, p.pos.z);
+    const float rf = (float)fz[p.cell + fexit];
+    if (SPH) {
+        const float3 e = radial(p.pos);
+        p.pos = make_float3(rf * e.x, rf * e.y, rf * e.z);
+    } else {
+        p.pos.z = rf;
+    }
+    p.t += (double)dwall;
+    const int nbc = neighbour1(c, p.cell, fexit);
+    if (nbc < 0) {
+        finish1(p, c, tally, true, SPH ? 0 : fexit, p.j + 1);
+        return;
+    }
+    if (reinterpret_cast<const uint4 *>(tb + c.off_hot)[(int64_t)nbc * c.nb + p.j].w & kFlagThick) {
+        const float4 m1 = reinterpret_cast<const float4 *>(tb + c.off_mcell)[2 * nbc];
+        const float kn = (float)kt[(int64_t)nbc * c.nb + p.j];
+        const float mu = fabsf(dot3f(p.n, face_normal<SPH>(fexit, p.pos)));
+        const float P = 2.0f / fmaf(kn, m1.w, 2.0f * (float)c.lambda) * (0.666666667f + mu);   // eq. 39
+        if (uf(draw(p.r, a)) < P) {
+            p.cell = nbc;
+            p.mc = false;
+            ++p.toddmc;
+            return;
+        }
+        // reflected: uniform point of the interface, isotropic direction back into the cell
+        p.pos = face_point<SPH>(fz, p.cell, fexit, p.r, a);
+        const float3 N = face_normal<SPH>(fexit, p.pos);
+        p.n = hemi_about(p.r, a, make_float3(-N.x, -N.y, -N.z));
+        p.left_inner = fexit == 0;
+        ++p.refl;
+        return;
+    }
+    p.cell = nbc;
+    p.left_inner = fexit == 1;
+}
+
 __device__ __forceinline__ uint64_t shfl64(uint64_t v, int src)
 {
     const uint32_t lo = __shfl((int)(uint32_t)v, src);
@@ -583,7 +681,10 @@ __global__ __launch_bounds__(256) void walk1dh(const uint8_t *__restrict__ tb, M
                 prefetch(p.r, a);
                 ++p.steps;
                 if (mc_pass) {
-                    mc_step1<SPH>(p, c, tb, a, tally, vtab, u0tab);
+                    if (c.groups)
+                        grp_step1<SPH>(p, c, tb, a, tally);
+                    else
+                        mc_step1<SPH>(p, c, tb, a, tally, vtab, u0tab);
                 } else {
                     ddmc_step1<SPH>(p, c, tb, a, tally);
                     if (p.active && !p.mc && p.steps < a.max_steps) {

@@ -24,6 +24,7 @@ STEP_BINS = 64
 STATUS = {0: "OK", -1: "EINVAL", -2: "ESIZE", -3: "EUNSUPPORTED", -4: "ENUMERIC", -5: "EHIP"}
 FLAG_DIRICHLET = 1 << 0
 FLAG_KEEP_RATES = 1 << 1
+FLAG_GROUPS = 1 << 2          # thin states use frequency groups (Sec. 5.3 eq. 42)
 
 
 class RddmcError(RuntimeError):
@@ -79,7 +80,7 @@ class TallyOut_t(C.Structure):
                 ("census_path", C.POINTER(C.c_void_p)), ("census_accel", C.POINTER(C.c_void_p))]
 
 
-ABI_VERSION = 6
+ABI_VERSION = 7
 CENSUS_PATH_FIX = float(1 << 24)   # residence-time units per length/c
 CENSUS_ACCEL_FIX = float(1 << 24)  # eq. 18 optical-depth units
 
@@ -90,7 +91,7 @@ EXPORTS = ["rddmc_abi_version", "rddmc_last_error", "rddmc_table_bytes", "rddmc_
            "rddmc_mdn_set", "rddmc_mdn_get", "rddmc_mdn_forward", "rddmc_mdn_loss_grad", "rddmc_mdn_adam",
            "rddmc_surrogate_samples", "rddmc_surrogate_bytes", "rddmc_surrogate_window", "rddmc_surrogate_attach",
            "rddmc_exitkernel_scratch_bytes", "rddmc_exitkernel_bytes", "rddmc_exitkernel_build",
-           "rddmc_exitlaw_samples"]
+           "rddmc_exitlaw_samples", "rddmc_read_redistribution"]
 
 _lib = None
 
@@ -117,6 +118,7 @@ def load(path: str = LIB_PATH):
     lib.rddmc_tally_reset.argtypes = [C.POINTER(Batch_t), vp, sz, vp]
     lib.rddmc_tally.argtypes = [C.POINTER(Batch_t), vp, sz, C.POINTER(TallyOut_t), vp]
     lib.rddmc_read_tables.argtypes = [C.POINTER(Batch_t), vp, C.c_int32, vp, vp, vp, vp, vp]
+    lib.rddmc_read_redistribution.argtypes = [C.POINTER(Batch_t), vp, C.c_int32, vp, vp, vp]
     lib.rddmc_philox_fill.argtypes = [C.c_uint32] * 6 + [C.c_uint64, vp, vp]
     lib.rddmc_mdn_bytes.argtypes = [C.c_int64, C.POINTER(sz), C.POINTER(sz), C.POINTER(C.c_int64)]
     lib.rddmc_mdn_init.argtypes = [vp, C.c_uint64, vp]
@@ -144,7 +146,8 @@ def load(path: str = LIB_PATH):
                  "rddmc_mdn_set", "rddmc_mdn_get", "rddmc_mdn_forward", "rddmc_mdn_loss_grad",
                  "rddmc_mdn_adam", "rddmc_surrogate_samples", "rddmc_surrogate_bytes",
                  "rddmc_surrogate_window", "rddmc_surrogate_attach", "rddmc_exitkernel_scratch_bytes",
-                 "rddmc_exitkernel_bytes", "rddmc_exitkernel_build", "rddmc_exitlaw_samples"):
+                 "rddmc_exitkernel_bytes", "rddmc_exitkernel_build", "rddmc_exitlaw_samples",
+                 "rddmc_read_redistribution"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -361,6 +364,18 @@ def read_tables(b: Batch, d_tables, cloud=0, want_rates=True, stream=None):
     return k, rates, hot, D, S, F
 
 
+def read_redistribution(b: Batch, d_tables, cloud=0, stream=None):
+    """Frequency-group tables of a cloud: P(j | j') [nb, nb] (row j') and the alias tables
+    [nb, nb] of (threshold, alias bin)."""
+    lib = load()
+    nb = b.meds[cloud].n_bins
+    prob = np.zeros((nb, nb))
+    alias = np.zeros((nb, nb, 2), dtype=np.uint32)
+    _check(lib.rddmc_read_redistribution(b.ref(), C.c_void_p(d_tables.data_ptr()), cloud, prob.ctypes.data,
+                                         alias.ctypes.data, _stream(stream)))
+    return prob, alias
+
+
 def philox_fill(k0, k1, c0, c1, c2, c3, n, d_out, stream=None):
     lib = load()
     _check(lib.rddmc_philox_fill(k0, k1, c0, c1, c2, c3, n, C.c_void_p(d_out.data_ptr()), _stream(stream)))
@@ -431,6 +446,9 @@ class Problem:
 
     def read_tables(self, cloud=0, want_rates=True):
         return read_tables(self.batch, self.tables, cloud, want_rates, self.stream)
+
+    def read_redistribution(self, cloud=0):
+        return read_redistribution(self.batch, self.tables, cloud, self.stream)
 
 
 def mdn_bytes(max_batch):

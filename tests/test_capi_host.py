@@ -26,7 +26,7 @@ def test_library_exports_every_declared_symbol():
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) == set(rddmc.EXPORTS)
-    assert lib.rddmc_abi_version() == rddmc.ABI_VERSION == 6
+    assert lib.rddmc_abi_version() == rddmc.ABI_VERSION == 7
 
 
 def test_cart3d_size_queries():
@@ -80,6 +80,24 @@ def test_validation_errors(mutation, status):
 def test_unsupported_combinations():
     with pytest.raises(rddmc.RddmcError) as ei:
         rddmc.table_bytes(rddmc.Batch([media.config_slab(), media.config_sphere()]))
+    assert ei.value.status == -3
+
+
+def test_frequency_group_clouds():
+    """Frequency groups (Sec. 5.3) add the eq. 42 table and its alias table (16 bytes per pair of
+    bins) and are refused for moving, non-isothermal or all-DDMC clouds, core-skipping and grids
+    beyond the table's bin limit."""
+    m = media.slab(1e3, 1e4, 8, 16, tau_threshold=media.ALL_THIN)
+    g = m.replace(flags=media.GROUP_MC)
+    assert rddmc.table_bytes(rddmc.Batch([g])) >= rddmc.table_bytes(rddmc.Batch([m])) + 16 * 16 * 16
+    for bad, status in ((dict(vel=np.linspace(-5.0, 5.0, 8)), -3), (dict(temp=np.linspace(1e4, 2e4, 8)), -3),
+                        (dict(tau_threshold=0.0), -1), (dict(x_crit=2.0), -1),
+                        (dict(bin_edges=media.uniform_edges(30.0, 2049)), -1)):
+        with pytest.raises(rddmc.RddmcError) as ei:
+            rddmc.table_bytes(rddmc.Batch([g.replace(**bad)]))
+        assert ei.value.status == status, bad
+    with pytest.raises(rddmc.RddmcError) as ei:
+        rddmc.table_bytes(rddmc.Batch([media.cube(n=4, n_bins=16, n_sources=2).replace(flags=media.GROUP_MC)]))
     assert ei.value.status == -3
 
 
