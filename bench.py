@@ -18,7 +18,12 @@ Other workloads (``--workload``):
   sweep      batched sweep clouds in one hipGraph-captured launch with the autotuned schedule;
   sweep-full all 256 sweep clouds at their stated packet counts (2^14..2^18 each) in one launch
              with the exact per-cell exit kernel, clouds ordered longest first by a pilot walk;
-  surrogate  the learned escape surrogate against plain rDDMC on the same clouds and packets.
+  surrogate  the learned escape surrogate against plain rDDMC on the same clouds and packets;
+  methods    static uniform slabs (tau0 = 1e3 .. 1e6, 64 cells x 128 bins over |x| <= 6 (a tau0)^(1/3),
+             T = 1e4 K, central source at x = 0), each walked whole on the same packet ids by
+             rDDMC, rDDMC on the efficient frequency grid, frequency-group Monte Carlo (Sec. 5.3,
+             eq. 42) and continuous-frequency Monte Carlo (the scattering-by-scattering reference);
+             the value is rDDMC's packets/s on the tau0 = 1e5 slab.
 
 Prints one JSON line.  ``--gpus`` must be 1 (the path runs on one GPU).
 """
@@ -87,7 +92,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["cube", "sphere", "sphere-efficient", "surrogate", "sweep", "sweep-full"], default="cube")
+    ap.add_argument("--workload", choices=["cube", "sphere", "sphere-efficient", "surrogate", "sweep", "sweep-full",
+                                           "methods"], default="cube")
     ap.add_argument("--block-packets", type=int, default=0,
                     help="sphere: packets per step (0 = the whole 2^22-packet job)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -437,6 +443,91 @@ def bench_surrogate(args):
     return out
 
 
+def bench_methods(args):
+    """rDDMC against frequency-group and continuous-frequency Monte Carlo on static slabs: each
+    method walks the same 2^16 packet ids of each slab whole in one launch (tables built
+    untimed).  Events are DDMC leaks for rDDMC, scatterings and cell-face crossings for the
+    Monte Carlo methods."""
+    import numpy as np
+    import torch
+    from paper_1709_10187_amd import media, rddmc
+    n = 1 << 16
+    rows, headline = [], None
+    for tau0 in (1e3, 1e4, 1e5, 1e6):
+        base = media.slab(tau0, 1e4, 64, 128, n_packets=n, name=f"slab_tau{tau0:.0e}")
+        legs = {"rddmc": base}
+        try:   # the efficient grid needs the spectrum to reach beyond the core (a tau0 >~ 2.5)
+            eff = media.efficient_edges(media._a_of_T(1e4), tau0, 1.0 / 32)
+            legs["rddmc_efficient"] = base.replace(bin_edges=eff)
+        except ValueError:
+            eff = None
+        legs["groups"] = base.replace(tau_threshold=media.ALL_THIN, flags=media.GROUP_MC)
+        legs["mcrt"] = base.replace(tau_threshold=media.ALL_THIN)
+        row = {"tau0": tau0, "dx": float(base.bin_edges[1] - base.bin_edges[0])}
+        spectra = {}
+        for leg, m in legs.items():
+            prob = rddmc.Problem(m)
+            torch.cuda.synchronize()
+            start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            start.record()
+            prob.run(seed=0)
+            stop.record()
+            torch.cuda.synchronize()
+            sec = start.elapsed_time(stop) / 1e3
+            r = prob.results()[0]
+            events = r.steps_total
+            spectra[leg] = r.spectrum.sum(axis=0)[1:-1].astype(np.float64) / max(r.escaped, 1)
+            row[leg] = {"packets_per_s": n / sec, "events_per_packet": events / n, "events_per_s": events / sec,
+                        "seconds": sec, "t_mean": r.t_mean}
+            log(f"tau0 {tau0:.0e} {leg}: {sec:.3f} s, {n / sec:.4g} packets/s, {events / n:.4g} events/packet")
+            del prob
+        row["speedup_rddmc_vs_mcrt"] = row["rddmc"]["packets_per_s"] / row["mcrt"]["packets_per_s"]
+        if eff is not None:
+            row["efficient_bins"] = len(eff) - 1
+            row["speedup_rddmc_efficient_vs_mcrt"] = (row["rddmc_efficient"]["packets_per_s"] /
+                                                      row["mcrt"]["packets_per_s"])
+        row["speedup_groups_vs_mcrt"] = row["groups"]["packets_per_s"] / row["mcrt"]["packets_per_s"]
+        row["L1_rddmc_vs_mcrt"] = float(np.abs(spectra["rddmc"] - spectra["mcrt"]).sum())
+        row["L1_groups_vs_mcrt"] = float(np.abs(spectra["groups"] - spectra["mcrt"]).sum())
+        rows.append(row)
+        if tau0 == 1e5:
+            headline = row
+    out = base_line(
+        args, headline["rddmc"]["packets_per_s"], n / headline["rddmc"]["packets_per_s"], "f32",
+        {"workload": "static uniform slabs tau0 = 1e3..1e6, T = 1e4 K, 64 cells x 128 bins over "
+                     "|x| <= 6 (a tau0)^(1/3), central source x = 0, 2^16 packets each, walked whole by rDDMC, "
+                     "rDDMC on the efficient frequency grid (central bin 2 x_cw, unit wings), frequency-group "
+                     "Monte Carlo (eq. 42) and continuous-frequency Monte Carlo on the same packet ids; "
+                     "value = rDDMC on the tau0 = 1e5 slab",
+         "methods": rows,
+         "precision": "f32 walk, f64 tables (eq. 42 tables in f64), f64 clock, i64 tallies, Philox4x32-10"},
+        packet_steps_per_s=headline["rddmc"]["events_per_s"])
+    out["roofline"] = None   # a comparison of methods; the kernels' own rooflines are the other workloads'
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_1d(media.config_slab(), args.cpu_packets or 4096, args)
+        out["config"]["cpu_mcrt"] = cpu_mcrt_slabs(args)
+    return out
+
+
+def cpu_mcrt_slabs(args):
+    """The oracle's continuous-frequency Monte Carlo (the 1D hybrid walker with every state thin)
+    on the host's cores: 4096 packets of the tau0 = 1e3 slab and 1024 of the 1e4 slab of the
+    methods workload."""
+    from paper_1709_10187_amd import media
+    from oracle import walk1dh as ow1h
+    threads = _threads(args)
+    out = []
+    for tau0, n in ((1e3, 4096), (1e4, 1024)):
+        m = media.slab(tau0, 1e4, 64, 128, tau_threshold=media.ALL_THIN)
+        t0 = time.perf_counter()
+        w = ow1h.run(m, n_packets=n, seed=0, n_threads=threads)
+        dt = time.perf_counter() - t0
+        out.append({"tau0": tau0, "packets": n, "packets_per_s": n / dt, "events_per_packet": w.mc_steps_sum / n,
+                    "cores": threads})
+        log(f"cpu mcrt tau0 {tau0:.0e}: {n / dt:.4g} packets/s")
+    return out
+
+
 def _threads(args):
     return args.cpu_threads or min(16, os.cpu_count() or 1)
 
@@ -489,7 +580,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     fn = {"cube": bench_cube, "sphere": bench_sphere, "sphere-efficient": lambda a: bench_sphere(a, efficient=True),
-          "surrogate": bench_surrogate, "sweep": bench_sweep, "sweep-full": bench_sweep_full}
+          "surrogate": bench_surrogate, "sweep": bench_sweep, "sweep-full": bench_sweep_full,
+          "methods": bench_methods}
     print(json.dumps(fn[args.workload](args)), flush=True)
 
 
