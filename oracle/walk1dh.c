@@ -47,6 +47,12 @@
  *    throwaway direction), and the bin of the outgoing x (bins 0 and nb-1 take everything
  *    below and above the grid); the packet's new direction is isotropic and independent of
  *    that frequency change.  Crossings keep j; escapes are tallied in bin j.
+ *  - Dust by continuous weights (Sec. 2.4's second method, P->dust_weight): absorption is no
+ *    event; the packet's weight w = exp(-L) decays with L += k_a dl over every stretch dl it
+ *    travels (a DDMC step's interaction distance, an MC flight), the packet is dropped (counted
+ *    as absorbed) once w < 1e-10, and escapes add w (and w^2) to the weighted spectra.  The
+ *    census estimators take the weight along the path: w(t_e) at a census time and the
+ *    integral of w over a residence, (w(a) - w(b)) / k_a; eq. 18 likewise.
  *  - Time-dependent estimators (eq. 17), unnormalised: at every census time t_e the packet's
  *    state is counted ('bin'), and its residence time in each state is summed per census
  *    interval ('path'); an MC packet's state is (cell, bin of its comoving x at the start of
@@ -96,6 +102,7 @@ typedef struct {
     int32_t n_census;              /* census intervals (0 = none) */
     const double *census;          /* [n_census+1] increasing census times */
     int32_t group;                 /* 1: thin states use frequency groups (Sec. 5.3) */
+    int32_t dust_weight;           /* 1: dust absorption by continuous weights (Sec. 2.4) */
 } oh_problem;
 
 typedef struct {
@@ -107,6 +114,8 @@ typedef struct {
     double *e_bin;         /* [(n_census+1)*nc*nb] counts of packets in each state at each census time */
     double *e_path;        /* [n_census*nc*nb] residence time in each state per census interval */
     double *e_accel;       /* [n_census*nc] eq. 18 optical-depth sums (z or r component) */
+    double *wspec, *wspec2;    /* [rows*(nb+2)] escaped weight and squared weight (dust_weight) */
+    double wt_sum, wt2_sum, w_sum;
 } oh_result;
 
 static int locate(const double *e, int nb, double x)
@@ -226,26 +235,38 @@ static double wall_distance(const oh_problem *P, int64_t c, const double p[3], c
 }
 
 /* the packet stays in state s over [t0, t1): census counts and residence times */
-static void census_add(const oh_problem *P, oh_result *R, int64_t s, double t0, double t1)
+/* weight at time t of a packet with L = L0 at t0 decaying at rate ka (c = 1) */
+static double weight_at(double t, double t0, double L0, double ka) { return exp(-(L0 + ka * (t - t0))); }
+
+/* integral of that weight over [a, b) (the residence without weights: ka = 0, L0 = 0) */
+static double weight_int(double a, double b, double t0, double L0, double ka)
+{
+    if (ka > 0.0) return (weight_at(a, t0, L0, ka) - weight_at(b, t0, L0, ka)) / ka;
+    return exp(-L0) * (b - a);
+}
+
+static void census_add(const oh_problem *P, oh_result *R, int64_t s, double t0, double t1, double L0, double ka)
 {
     if (P->n_census <= 0) return;
     const int64_t ns = (int64_t)P->nc * P->nb;
     for (int e = 0; e <= P->n_census; ++e)
-        if (P->census[e] >= t0 && P->census[e] < t1) R->e_bin[(int64_t)e * ns + s] += 1.0;
+        if (P->census[e] >= t0 && P->census[e] < t1)
+            R->e_bin[(int64_t)e * ns + s] += P->dust_weight ? weight_at(P->census[e], t0, L0, ka) : 1.0;
     for (int n = 0; n < P->n_census; ++n) {
         double a = fmax(t0, P->census[n]), b = fmin(t1, P->census[n + 1]);
-        if (b > a) R->e_path[(int64_t)n * ns + s] += b - a;
+        if (b > a) R->e_path[(int64_t)n * ns + s] += P->dust_weight ? weight_int(a, b, t0, L0, ka) : b - a;
     }
 }
 
 /* eq. 18: a leak of a step that stayed over [t0, t1) adds v times its residence in each census
  * interval to cell c */
-static void accel_add(const oh_problem *P, oh_result *R, int64_t c, double t0, double t1, double v)
+static void accel_add(const oh_problem *P, oh_result *R, int64_t c, double t0, double t1, double v, double L0,
+                      double ka)
 {
     if (P->n_census <= 0) return;
     for (int n = 0; n < P->n_census; ++n) {
         double a = fmax(t0, P->census[n]), b = fmin(t1, P->census[n + 1]);
-        if (b > a) R->e_accel[(int64_t)n * P->nc + c] += v * (b - a);
+        if (b > a) R->e_accel[(int64_t)n * P->nc + c] += v * (P->dust_weight ? weight_int(a, b, t0, L0, ka) : b - a);
     }
 }
 
@@ -256,12 +277,20 @@ static int64_t mc_state(const oh_problem *P, int64_t c, double x)
     return c * P->nb + j;
 }
 
-static void tally_escape(oh_result *R, const oh_problem *P, int f, double xlab, double t)
+static void tally_escape(oh_result *R, const oh_problem *P, int f, double xlab, double t, double L)
 {
     int nb = P->nb;
     int row = P->geometry == 0 ? f : 0;
     int slot = locate(P->edges, nb, xlab) + 1;
     R->spectrum[(int64_t)row * (nb + 2) + slot]++;
+    if (P->dust_weight) {
+        const double w = exp(-L);
+        R->wspec[(int64_t)row * (nb + 2) + slot] += w;
+        R->wspec2[(int64_t)row * (nb + 2) + slot] += w * w;
+        R->w_sum += w;
+        R->wt_sum += w * t;
+        R->wt2_sum += w * t * t;
+    }
     R->escaped++;
     R->t_sum += t;
     R->t2_sum += t * t;
@@ -297,6 +326,7 @@ static void walk_packet(const oh_problem *P, uint64_t id, uint64_t seed, uint64_
     int left_inner = 0;
     if (mc) iso_dir(&r, n);
     uint64_t steps = 0, mcsteps = 0;
+    double L = 0.0;                 /* -ln(weight) with continuous dust weights */
     for (;;) {
         if (steps >= max_steps) { R->capped++; break; }
         ++steps;
@@ -310,14 +340,20 @@ static void walk_packet(const oh_problem *P, uint64_t id, uint64_t seed, uint64_
             }
             if (P->rate_dn[s] > 0.0) { double l = -log(ru(&r)) / P->rate_dn[s]; if (l < best) { best = l; ev = 2; } }
             if (P->rate_up[s] > 0.0) { double l = -log(ru(&r)) / P->rate_up[s]; if (l < best) { best = l; ev = 3; } }
-            if (P->k_abs && P->k_abs[c] > 0.0) {
-                double l = -log(ru(&r)) / P->k_abs[c];
+            const double ka = P->k_abs ? P->k_abs[c] : 0.0;
+            if (ka > 0.0 && !P->dust_weight) {
+                double l = -log(ru(&r)) / ka;
                 if (l < best) { best = l; ev = 4; }
             }
-            census_add(P, R, s, t, t + best);
+            const double L_prev = L;
+            census_add(P, R, s, t, t + best, L, ka);
             const double t_prev = t;
             t += best;
             if (ev == 4) { R->absorbed++; break; }   /* removed by dust after that residence */
+            if (P->dust_weight) {
+                L += ka * best;
+                if (L > -log(1e-10)) { R->absorbed++; break; }   /* negligible weight: dropped */
+            }
             if (ev >= 2) {
                 j += (ev == 2) ? -1 : 1;
                 if (!P->thick[c * nb + j]) {   /* frequency leak into a thin bin */
@@ -333,7 +369,7 @@ static void walk_packet(const oh_problem *P, uint64_t id, uint64_t seed, uint64_
             int f = ev;
             int64_t nc = P->nbr[c * 2 + f];
             const double dir = f ? 1.0 : -1.0;
-            accel_add(P, R, c, t_prev, t, dir * P->k[s]);      /* outward leakage from c */
+            accel_add(P, R, c, t_prev, t, dir * P->k[s], L_prev, ka);   /* outward leakage from c */
             double xin = P->edges[j] + (P->edges[j + 1] - P->edges[j]) * ru(&r);
             if (P->face_mc[s * 2 + f] || nc < 0) {
                 /* interface leak: MC at a uniform point of the face, isotropic outward */
@@ -342,7 +378,7 @@ static void walk_packet(const oh_problem *P, uint64_t id, uint64_t seed, uint64_
                 face_normal(P, f, pos, N);
                 hemi_about(&r, N, n);
                 double nu = n_dot_u(P, c, pos, n);
-                if (nc < 0) { tally_escape(R, P, f, xin + nu, t); break; }
+                if (nc < 0) { tally_escape(R, P, f, xin + nu, t, L); break; }
                 x = (xin + nu) * sqrt(P->T[c] / P->T[nc]) - n_dot_u(P, nc, pos, n);
                 c = nc;
                 left_inner = f == 1;
@@ -357,7 +393,7 @@ static void walk_packet(const oh_problem *P, uint64_t id, uint64_t seed, uint64_
                 j = jn < 0 ? 0 : (jn > nb - 1 ? nb - 1 : jn);
             }
             c = nc;
-            if (P->thick[c * nb + j]) accel_add(P, R, c, t_prev, t, dir * P->k[c * nb + j]);   /* inward */
+            if (P->thick[c * nb + j]) accel_add(P, R, c, t_prev, t, dir * P->k[c * nb + j], L_prev, ka);   /* inward */
             if (!P->thick[c * nb + j]) {   /* re-binned into a thin state */
                 cell_point(P, c, &r, pos);
                 iso_dir(&r, n);
@@ -374,19 +410,24 @@ static void walk_packet(const oh_problem *P, uint64_t id, uint64_t seed, uint64_
         double dwall = wall_distance(P, c, pos, n, left_inner, &fexit);
         double kl = P->group ? P->k[c * nb + j] : P->k0[c] * mc_voigt(P->a[c], x);
         double ka = P->k_abs ? P->k_abs[c] : 0.0, ks = P->k_sca ? P->k_sca[c] : 0.0;
-        double kx = kl + ks + ka;
+        double ka_ev = P->dust_weight ? 0.0 : ka;     /* absorption as an interaction, or as weight decay */
+        double kx = kl + ks + ka_ev;
         double ds = -log(ru(&r)) / kx;
         double p0[3] = {pos[0], pos[1], pos[2]};
         double u0 = n_dot_u(P, c, p0, n);
-        census_add(P, R, P->group ? c * nb + j : mc_state(P, c, x), t, t + fmin(ds, dwall));
+        census_add(P, R, P->group ? c * nb + j : mc_state(P, c, x), t, t + fmin(ds, dwall), L, ka);
+        if (P->dust_weight) {
+            L += ka * fmin(ds, dwall);
+            if (L > -log(1e-10)) { R->absorbed++; break; }
+        }
         if (ds < dwall) {
             for (int d = 0; d < 3; ++d) pos[d] += ds * n[d];
             t += ds;
             x += u0 - n_dot_u(P, c, pos, n);
-            if (ka > 0.0 || ks > 0.0) {   /* which opacity interacted */
+            if (ka_ev > 0.0 || ks > 0.0) {   /* which opacity interacted */
                 double uu2 = ru(&r) * kx;
-                if (uu2 < ka) { R->absorbed++; break; }
-                if (uu2 < ka + ks) { iso_dir(&r, n); left_inner = 0; continue; }   /* dust: coherent, isotropic */
+                if (uu2 < ka_ev) { R->absorbed++; break; }
+                if (uu2 < ka_ev + ks) { iso_dir(&r, n); left_inner = 0; continue; }   /* dust: coherent, isotropic */
             }
             if (P->group) {   /* eq. 42: the outgoing bin of a scattering of a bin-j packet */
                 double xg = P->edges[j] + (P->edges[j + 1] - P->edges[j]) * ru(&r);
@@ -419,7 +460,7 @@ static void walk_packet(const oh_problem *P, uint64_t id, uint64_t seed, uint64_
         int64_t nc = P->nbr[c * 2 + f];
         if (nc == -2) continue;                         /* no face (r = 0): cannot occur */
         if (nc < 0) {
-            tally_escape(R, P, f, P->group ? 0.5 * (P->edges[j] + P->edges[j + 1]) : x + nu, t);
+            tally_escape(R, P, f, P->group ? 0.5 * (P->edges[j] + P->edges[j + 1]) : x + nu, t, L);
             break;
         }
         double xn = (x + nu) * sqrt(P->T[c] / P->T[nc]) - n_dot_u(P, nc, pos, n);
@@ -470,6 +511,8 @@ static void *worker(void *arg)
     L.e_path = npath ? calloc(npath, 8) : NULL;
     size_t nacc = P->n_census > 0 ? (size_t)P->n_census * P->nc : 0;
     L.e_accel = nacc ? calloc(nacc, 8) : NULL;
+    L.wspec = P->dust_weight ? calloc(ns, 8) : NULL;
+    L.wspec2 = P->dust_weight ? calloc(ns, 8) : NULL;
     for (;;) {
         uint64_t b = __sync_fetch_and_add(jb->next, 8);
         if (b >= jb->n) break;
@@ -489,8 +532,13 @@ static void *worker(void *arg)
     for (size_t i = 0; i < nbin; ++i) R->e_bin[i] += L.e_bin[i];
     for (size_t i = 0; i < npath; ++i) R->e_path[i] += L.e_path[i];
     for (size_t i = 0; i < nacc; ++i) R->e_accel[i] += L.e_accel[i];
+    if (P->dust_weight) {
+        for (size_t i = 0; i < ns; ++i) { R->wspec[i] += L.wspec[i]; R->wspec2[i] += L.wspec2[i]; }
+        R->w_sum += L.w_sum; R->wt_sum += L.wt_sum; R->wt2_sum += L.wt2_sum;
+    }
     pthread_mutex_unlock(jb->lock);
     free(L.spectrum); free(L.time_hist); free(L.step_hist); free(L.e_bin); free(L.e_path); free(L.e_accel);
+    free(L.wspec); free(L.wspec2);
     return NULL;
 }
 

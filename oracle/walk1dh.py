@@ -17,6 +17,7 @@ LIB = os.path.join(HERE, "libo1walk1dh.so")
 TIME_BINS = 128
 STEP_BINS = 64
 GROUP_FLAG = 1 << 2     # a cloud's flag bit: thin states use frequency groups (Sec. 5.3)
+DUST_WEIGHT_FLAG = 1 << 3   # a cloud's flag bit: dust absorption by continuous weights (Sec. 2.4)
 
 
 def build_lib():
@@ -33,7 +34,7 @@ class _Problem(C.Structure):
                 ("T", C.c_void_p), ("u", C.c_void_p), ("lambda_", C.c_double), ("x_crit", C.c_double),
                 ("n_src", C.c_int32), ("src_state", C.c_void_p), ("src_pos", C.c_void_p), ("src_x", C.c_void_p),
                 ("src_cdf", C.c_void_p), ("k_abs", C.c_void_p), ("k_sca", C.c_void_p), ("src_t", C.c_void_p),
-                ("n_census", C.c_int32), ("census", C.c_void_p), ("group", C.c_int32)]
+                ("n_census", C.c_int32), ("census", C.c_void_p), ("group", C.c_int32), ("dust_weight", C.c_int32)]
 
 
 class _Result(C.Structure):
@@ -41,7 +42,9 @@ class _Result(C.Structure):
                 ("t_sum", C.c_double), ("t2_sum", C.c_double), ("steps_sum", C.c_double),
                 ("mc_steps_sum", C.c_double), ("steps2_sum", C.c_double), ("escaped", C.c_int64),
                 ("capped", C.c_int64), ("to_mc", C.c_int64), ("to_ddmc", C.c_int64), ("reflected", C.c_int64),
-                ("absorbed", C.c_int64), ("e_bin", C.c_void_p), ("e_path", C.c_void_p), ("e_accel", C.c_void_p)]
+                ("absorbed", C.c_int64), ("e_bin", C.c_void_p), ("e_path", C.c_void_p), ("e_accel", C.c_void_p),
+                ("wspec", C.c_void_p), ("wspec2", C.c_void_p), ("wt_sum", C.c_double), ("wt2_sum", C.c_double),
+                ("w_sum", C.c_double)]
 
 
 _lib = None
@@ -79,6 +82,19 @@ class Walk1DHResult:
     e_bin: np.ndarray = None   # (n_census+1, nc, nb) packets in each state at each census time
     e_path: np.ndarray = None  # (n_census, nc, nb) residence time per census interval
     e_accel: np.ndarray = None  # (n_census, nc) eq. 18 optical-depth sums (z or r component)
+    wspec: np.ndarray = None   # (rows, nb+2) escaped weight (continuous dust weights)
+    wspec2: np.ndarray = None  # (rows, nb+2) escaped squared weight
+    w_sum: float = 0.0
+    wt_sum: float = 0.0
+    wt2_sum: float = 0.0
+
+    @property
+    def t_mean_w(self):
+        return self.wt_sum / self.w_sum if self.w_sum > 0 else 0.0
+
+    @property
+    def t_var_w(self):
+        return self.wt2_sum / self.w_sum - self.t_mean_w ** 2 if self.w_sum > 0 else 0.0
 
     @property
     def t_mean(self):
@@ -107,6 +123,9 @@ def run(m, n_packets=None, seed=0, first_id=0, max_steps=(1 << 62), n_threads=No
     t = tabs if tabs is not None else tb.build(m)
     n = int(m.n_packets if n_packets is None else n_packets)
     group = bool(int(m.flags) & GROUP_FLAG)
+    weighted = bool(int(m.flags) & DUST_WEIGHT_FLAG)
+    if weighted:
+        assert m.dust_abs is not None
     if group:   # frequency groups (Sec. 5.3): static, isothermal clouds
         assert m.vel is None and np.all(np.asarray(m.temp) == np.asarray(m.temp).flat[0])
     keep = []
@@ -143,7 +162,7 @@ def run(m, n_packets=None, seed=0, first_id=0, max_steps=(1 << 62), n_threads=No
                  arr(m.dust_sca, np.float64) if m.dust_sca is not None else None,
                  arr(tw, np.float64) if m.src_t is not None else None,
                  0 if m.census is None else len(m.census) - 1,
-                 arr(m.census, np.float64) if m.census is not None else None, int(group))
+                 arr(m.census, np.float64) if m.census is not None else None, int(group), int(weighted))
     rows = 2 if m.geometry == tb.SLAB else 1
     spec = np.zeros((rows, t.nb + 2), dtype=np.int64)
     th = np.zeros(TIME_BINS + 2, dtype=np.int64)
@@ -152,11 +171,15 @@ def run(m, n_packets=None, seed=0, first_id=0, max_steps=(1 << 62), n_threads=No
     e_bin = np.zeros((nce + 1, t.nc, t.nb)) if nce else None
     e_path = np.zeros((nce, t.nc, t.nb)) if nce else None
     e_accel = np.zeros((nce, t.nc)) if nce else None
+    wspec = np.zeros((rows, t.nb + 2)) if weighted else None
+    wspec2 = np.zeros((rows, t.nb + 2)) if weighted else None
     R = _Result(spec.ctypes.data, th.ctypes.data, sh.ctypes.data, 0.0, 0.0, 0.0, 0.0, 0.0, 0, 0, 0, 0, 0, 0,
                 e_bin.ctypes.data if nce else None, e_path.ctypes.data if nce else None,
-                e_accel.ctypes.data if nce else None)
+                e_accel.ctypes.data if nce else None, wspec.ctypes.data if weighted else None,
+                wspec2.ctypes.data if weighted else None, 0.0, 0.0, 0.0)
     rc = lib.oh_run(C.byref(P), first_id, n, seed, max_steps, n_threads or os.cpu_count() or 1, C.byref(R))
     if rc != 0:
         raise RuntimeError("oh_run failed")
     return Walk1DHResult(spec, th, sh, R.t_sum, R.t2_sum, R.steps_sum, R.mc_steps_sum, R.steps2_sum, R.escaped,
-                         R.capped, R.to_mc, R.to_ddmc, R.reflected, n, R.absorbed, e_bin, e_path, e_accel)
+                         R.capped, R.to_mc, R.to_ddmc, R.reflected, n, R.absorbed, e_bin, e_path, e_accel,
+                         wspec, wspec2, R.w_sum, R.wt_sum, R.wt2_sum)

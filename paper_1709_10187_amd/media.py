@@ -89,6 +89,7 @@ class Medium:
 
 GROUP_MC = 1 << 2      # Medium.flags bit: thin states use frequency groups (Sec. 5.3 eq. 42)
 ALL_THIN = 1.0e300     # a tau_threshold above every state's optical width: no DDMC states
+DUST_WEIGHT = 1 << 3   # Medium.flags bit: dust absorption by continuous packet weights (Sec. 2.4)
 
 
 def uniform_edges(x_max: float, n_bins: int) -> np.ndarray:

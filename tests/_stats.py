@@ -65,6 +65,40 @@ def compare_two_samples(c1, c2):
             "L1": float(np.abs(c1 / n1 - c2 / n2).sum())}
 
 
+def compare_weighted_exact(w, w2, n, p):
+    """Weighted escapes (continuous dust weights) against an exact expectation: w, w2 the escaped
+    weight and squared weight per slot over n packets, p the exact escape probability per slot
+    (the expected weight).  Bins expecting < 10 packets' weight are merged; the per-bin sigma is
+    the sample's own, sqrt((w2 / n - (w / n)^2) / n)."""
+    w = np.asarray(w, dtype=np.float64).ravel()
+    w2 = np.asarray(w2, dtype=np.float64).ravel()
+    p = np.maximum(np.asarray(p, dtype=np.float64).ravel(), 0.0)
+    a, b, q = _merge(p * n, w, w2, p)
+    var = np.maximum(b / n - (a / n) ** 2, 1e-300) / n
+    z = (a / n - q) / np.sqrt(var)
+    chi2 = float(np.sum(z ** 2))
+    dof = max(len(a), 1)
+    return {"z": z, "frac_within_3sigma": float(np.mean(np.abs(z) <= 3)), "max_abs_z": float(np.abs(z).max()),
+            "chi2": chi2, "dof": dof, "p_value": float(stats.chi2.sf(chi2, dof)),
+            "L1": float(np.abs(w / n - p).sum())}
+
+
+def compare_weighted_two(w_a, w2_a, n_a, w_b, w2_b, n_b):
+    """Two samples of weighted escapes (either may be unweighted: then w2 = w, the counts):
+    per-bin differences of the mean weight per packet over their joint sigma."""
+    wa, w2a, wb, w2b = (np.asarray(v, dtype=np.float64).ravel() for v in (w_a, w2_a, w_b, w2_b))
+    pooled = (wa + wb) / (n_a + n_b)
+    a1, a2, b1, b2 = _merge(pooled * min(n_a, n_b), wa, w2a, wb, w2b)
+    va = np.maximum(a2 / n_a - (a1 / n_a) ** 2, 0.0) / n_a
+    vb = np.maximum(b2 / n_b - (b1 / n_b) ** 2, 0.0) / n_b
+    z = (a1 / n_a - b1 / n_b) / np.sqrt(np.maximum(va + vb, 1e-300))
+    chi2 = float(np.sum(z ** 2))
+    dof = max(len(a1), 1)
+    return {"z": z, "frac_within_3sigma": float(np.mean(np.abs(z) <= 3)), "max_abs_z": float(np.abs(z).max()),
+            "chi2": chi2, "dof": dof, "p_value": float(stats.chi2.sf(chi2, dof)),
+            "L1": float(np.abs(wa / n_a - wb / n_b).sum())}
+
+
 def allowed_3sigma_exceedances(n_bins, p_fail=1e-3):
     k = 0
     while stats.binom.sf(k, n_bins, 0.0027) >= p_fail:
