@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define RDDMC_ABI_VERSION 7
+#define RDDMC_ABI_VERSION 8
 
 typedef enum {
     RDDMC_OK = 0,
@@ -60,6 +60,9 @@ enum { RDDMC_SLAB = 0, RDDMC_SPHERE = 1, RDDMC_CART3D = 2 };
 #define RDDMC_FLAG_KEEP_RATES (1u << 1)  /* also store the FP64 rates (for table parity checks) */
 #define RDDMC_FLAG_GROUPS     (1u << 2)  /* continuous-MC states use frequency groups (Sec. 5.3) */
 #define RDDMC_MAX_GROUP_BINS  2048       /* largest n_bins of a cloud with RDDMC_FLAG_GROUPS */
+#define RDDMC_FLAG_DUST_WEIGHT (1u << 3) /* dust absorption by continuous packet weights (Sec. 2.4) */
+#define RDDMC_DUST_WMIN       1e-10      /* weight below which such a packet is eliminated */
+#define RDDMC_WEIGHT_FIX      4294967296.0   /* weighted escape tallies: units of 2^-32 weight */
 
 #define RDDMC_TIME_BINS 128              /* log10-uniform escape-time bins over [1e-3, 1e6] */
 #define RDDMC_STEP_BINS 64               /* floor(log2(steps per packet)) buckets */
@@ -102,6 +105,15 @@ enum { RDDMC_SLAB = 0, RDDMC_SPHERE = 1, RDDMC_CART3D = 2 };
  *                exponential distance (rate k_a) in DDMC states; in MC states dust scatters
  *                isotropically and coherently in the comoving frame, or absorbs.  Absorbed
  *                packets are counted, not tallied as escapes.  1D clouds only.
+ *                With flags & RDDMC_FLAG_DUST_WEIGHT (Sec. 2.4's second method) nothing is
+ *                absorbed: a packet's weight, 1 at emission, is multiplied by exp(-k_a dl) over
+ *                every stretch dl it travels (a DDMC step's interaction distance, an MC flight),
+ *                packets whose weight falls below RDDMC_DUST_WMIN are eliminated (counted as
+ *                absorbed), escapes add their weight (and its square) to weighted spectra, and
+ *                the census estimators are weighted along the path: a 'bin' count at a census
+ *                time adds the weight then, and a residence [a, b) adds the integral of the
+ *                weight over it, w(a) (1 - exp(-k_a (b - a))) / k_a (the paper's path
+ *                correction), as does eq. 18's sum.
  *   src_t        per source emission window {t_start, t_end} (0 <= t_start <= t_end): packets
  *                are emitted uniformly in time over it (Sec. 2.3); NULL = a flash at t = 0.
  *                1D clouds only.
@@ -201,7 +213,7 @@ typedef struct {
 } rddmc_run;
 
 /* Per-cloud summary filled by rddmc_tally (FP64 host-side normalisation of the exact
- * integer tallies). */
+ * integer tallies).  The weighted fields are 0 unless the cloud has RDDMC_FLAG_DUST_WEIGHT. */
 typedef struct {
     uint64_t launched;       /* packets emitted in the tallied runs                      */
     uint64_t escaped;        /* packets that left the domain                             */
@@ -221,7 +233,11 @@ typedef struct {
     uint64_t n_pix;          /* 3D: escape pixels 2 (ny nz + nx nz + nx ny); else 0       */
     uint64_t surrogate_calls;/* cell exits drawn from the learned surrogate (each counted  */
                              /* as two steps in steps_total)                             */
-    uint64_t absorbed;       /* packets absorbed by dust                                  */
+    uint64_t absorbed;       /* packets absorbed by dust (weights: eliminated below        */
+                             /* RDDMC_DUST_WMIN)                                          */
+    double   escaped_w;      /* weights: total escaped weight                             */
+    double   t_mean_w;       /* weights: weighted mean escape time [length / c]           */
+    double   t_var_w;        /* weights: weighted variance of the escape time             */
 } rddmc_cloud_stats;
 
 /*
@@ -240,6 +256,11 @@ typedef struct {
  *                 state during each census interval, units of 2^-24 length/c, interval-major.
  *   census_accel[c] (with a census) int64 [n_census * n_cells]: eq. 18 optical-depth sums
  *                 per cell and interval (signed), units of 2^-24, interval-major.
+ *   spectrum_w[c], spectrum_w2[c]  (RDDMC_FLAG_DUST_WEIGHT) int64 [n_rows * (n_bins + 2)]:
+ *                 escaped weight and escaped squared weight per face row and lab slot, units
+ *                 of 2^-32 (RDDMC_WEIGHT_FIX).
+ * With RDDMC_FLAG_DUST_WEIGHT the census 'bin' counts are weights in units of 2^-24 and the
+ * 'path' and eq. 18 sums are weighted by the integral of the weight over each residence.
  * Any pointer array may be NULL to skip that output.
  */
 typedef struct {
@@ -251,6 +272,8 @@ typedef struct {
     int64_t **census_bin;
     int64_t **census_path;
     int64_t **census_accel;
+    int64_t **spectrum_w;
+    int64_t **spectrum_w2;
 } rddmc_tally_out;
 
 #define RDDMC_CENSUS_PATH_FIX 16777216.0   /* residence-time units per length/c (2^24) */

@@ -282,14 +282,20 @@ class TransientResult:
     accel: np.ndarray = None  # (n, nc): eq. 18's optical-depth sum per cell and interval (1D)
 
 
-def _accel_weights(ch):
+def _accel_weights(ch, dust_weights=False):
     """Per state s = (c, j): the expected eq. 18 contribution of one unit of residence in s,
     split into the cell it leaks out of and the cell it leaks into.  A step in s lasts
     dl ~ Exp(K_s) and ends in leak f with probability r_f / K_s, independently of dl; a leak
     along direction d (-1 through face 0, +1 through face 1) adds k_s dl d to cell c and, when
     the neighbour c' is a grid cell, k_{c',j'} dl d to c' at the bin j' it lands in (Doppler
     re-binning of eq. 20 for moving media).  Returns (out (ns,), into list of (dst cell,
-    weights (ns,)))."""
+    weights (ns,))).
+
+    With ``dust_weights`` (Sec. 2.4's continuous weights) absorption is not an event: a step
+    lasts dl ~ Exp(K_leak) and ends in leak f with probability r_f / K_leak, and the leak adds
+    k d times the weight integrated over the step (the paper's path correction); the expected
+    weighted residence in s is the killed chain's, so the weights per unit residence are
+    r_f / K_leak instead of r_f / (K_leak + k_a)."""
     t, nb, K = ch["t"], ch["nb"], ch["K"]
     nc = t.nc
     if t.nf != 2:
@@ -298,8 +304,9 @@ def _accel_weights(ch):
     edges = t.bin_edges
     out = np.zeros(nc * nb)
     into = np.zeros((nc, nc * nb))
+    Kstep = t.K if dust_weights else K.reshape(nc, nb)       # the rate that ends a step
     for f, d in ((0, -1.0), (1, 1.0)):
-        p = t.rate_face[:, :, f] / K.reshape(nc, nb)          # P(leak through f | s)
+        p = t.rate_face[:, :, f] / Kstep                      # P(leak through f | s)
         out += (d * p * kk).ravel()
         for c in range(nc):
             n = t.nbr[c, f]
@@ -315,12 +322,14 @@ def _accel_weights(ch):
     return out, into
 
 
-def transient(m, edges, tabs=None, emit=None) -> TransientResult:
+def transient(m, edges, tabs=None, emit=None, dust_weights=False) -> TransientResult:
     """Transient law of pure DDMC on a small medium (dense matrices): the expectations, per
     emitted packet, of the 'bin' estimator at each census time and of the 'path' estimator
     over each census interval (eq. 17, without the energy and volume factors).  ``emit`` =
     (t_s, t_e) emits packets uniformly in time over that window (t_e > t_s), else a flash at
-    t = 0."""
+    t = 0.  ``dust_weights``: eq. 18's expectation under continuous dust weights (see
+    _accel_weights); the occupation and residence expectations are the same for both dust
+    methods."""
     from scipy import linalg as la
     ch = _chain(m, tabs)
     ns, nb, K, R, pi0 = ch["ns"], ch["nb"], ch["K"], ch["R"], ch["pi0"]
@@ -362,7 +371,7 @@ def transient(m, edges, tabs=None, emit=None) -> TransientResult:
     accel = None
     if ch["t"].nf == 2:
         res = cum[1:] - cum[:-1]                    # expected residence per (interval, state)
-        w_out, w_into = _accel_weights(ch)
+        w_out, w_into = _accel_weights(ch, dust_weights)
         accel = (res * w_out).reshape(len(edges) - 1, nc, nb).sum(axis=2) + res @ w_into.T
     return TransientResult(edges=edges, at_edges=at.reshape(len(edges), nc, nb),
                            mean_in=mean.reshape(len(edges) - 1, nc, nb), escaped_by=escaped, accel=accel)

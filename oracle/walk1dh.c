@@ -303,6 +303,7 @@ typedef struct {
     volatile uint64_t *next;
     pthread_mutex_t *lock;
     oh_result *out;
+    uint64_t grain;                /* packets a thread takes at a time */
 } job_t;
 
 static void walk_packet(const oh_problem *P, uint64_t id, uint64_t seed, uint64_t max_steps, oh_result *R)
@@ -514,9 +515,9 @@ static void *worker(void *arg)
     L.wspec = P->dust_weight ? calloc(ns, 8) : NULL;
     L.wspec2 = P->dust_weight ? calloc(ns, 8) : NULL;
     for (;;) {
-        uint64_t b = __sync_fetch_and_add(jb->next, 8);
+        uint64_t b = __sync_fetch_and_add(jb->next, jb->grain);
         if (b >= jb->n) break;
-        uint64_t e = b + 8 < jb->n ? b + 8 : jb->n;
+        uint64_t e = b + jb->grain < jb->n ? b + jb->grain : jb->n;
         for (uint64_t i = b; i < e; ++i) walk_packet(P, jb->first + i, jb->seed, jb->max_steps, &L);
     }
     pthread_mutex_lock(jb->lock);
@@ -549,7 +550,8 @@ int oh_run(const oh_problem *p, uint64_t first, uint64_t n, uint64_t seed, uint6
     volatile uint64_t next = 0;
     pthread_mutex_t lock;
     pthread_mutex_init(&lock, NULL);
-    job_t jb = {p, first, n, seed, max_steps, &next, &lock, out};
+    /* small runs (few, long packets) hand out one packet at a time */
+    job_t jb = {p, first, n, seed, max_steps, &next, &lock, out, n >= 64 * (uint64_t)threads ? 8u : 1u};
     pthread_t *th = malloc(sizeof(pthread_t) * threads);
     for (int i = 0; i < threads; ++i) pthread_create(&th[i], NULL, worker, &jb);
     for (int i = 0; i < threads; ++i) pthread_join(th[i], NULL);

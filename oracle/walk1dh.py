@@ -177,7 +177,7 @@ def run(m, n_packets=None, seed=0, first_id=0, max_steps=(1 << 62), n_threads=No
                 e_bin.ctypes.data if nce else None, e_path.ctypes.data if nce else None,
                 e_accel.ctypes.data if nce else None, wspec.ctypes.data if weighted else None,
                 wspec2.ctypes.data if weighted else None, 0.0, 0.0, 0.0)
-    rc = lib.oh_run(C.byref(P), first_id, n, seed, max_steps, n_threads or os.cpu_count() or 1, C.byref(R))
+    rc = lib.oh_run(C.byref(P), first_id, n, seed, max_steps, n_threads or min(16, os.cpu_count() or 1), C.byref(R))
     if rc != 0:
         raise RuntimeError("oh_run failed")
     return Walk1DHResult(spec, th, sh, R.t_sum, R.t2_sum, R.steps_sum, R.mc_steps_sum, R.steps2_sum, R.escaped,

@@ -176,7 +176,7 @@ def run(m, n_packets=None, seed=0, first_id=0, max_steps=(1 << 62), n_threads=No
     sh = np.zeros(STEP_BINS, dtype=np.int64)
     R = _Result(spec.ctypes.data, pix.ctypes.data, th.ctypes.data, sh.ctypes.data, 0.0, 0.0, 0.0, 0.0,
                 0, 0, 0, 0, 0, 0.0, 0.0)
-    rc = lib.o3_run(C.byref(P), first_id, n, seed, max_steps, n_threads or os.cpu_count() or 1, C.byref(R))
+    rc = lib.o3_run(C.byref(P), first_id, n, seed, max_steps, n_threads or min(16, os.cpu_count() or 1), C.byref(R))
     if rc != 0:
         raise RuntimeError("o3_run failed")
     return Walk3DResult(spec, pix, th, sh, R.t_sum, R.t2_sum, R.steps_sum, R.mc_steps_sum, R.escaped,

@@ -231,7 +231,9 @@ __global__ void build_rates(DevCloud c, uint8_t *tb, uint32_t *err)
         const double dxp = e[j + 2] - e[j + 1];
         ru = 1.0 / (dx * (dx / ks + dxp / kk[s + 1]));
     }
-    const double ka = c.dusty ? f64p(tb, c.off_dust)[2 * cell] : 0.0;   // dust absorption rate
+    // dust absorption rate: one more exponential channel, unless absorption is carried by
+    // continuous weights (then the walk's interaction distances ignore it)
+    const double ka = (c.dusty && !c.dust_weight) ? f64p(tb, c.off_dust)[2 * cell] : 0.0;
     const double K = rs + rd + ru + ka;
     if (!(K > 0.0) || !isfinite(K)) atomicOr(err, (uint32_t)BE_NONFINITE);
 

@@ -150,6 +150,8 @@ rddmc_status validate_cloud(const rddmc_medium &m, int idx)
     const bool extras = m.dust_abs || m.dust_sca || m.src_t || m.n_census > 0;
     if (extras && m.geometry == RDDMC_CART3D)
         return fail(RDDMC_EUNSUPPORTED, "cloud %d: dust, emission windows and census tallies are for 1D clouds", idx);
+    if ((m.flags & RDDMC_FLAG_DUST_WEIGHT) && !m.dust_abs)
+        return fail(RDDMC_EINVAL, "cloud %d: RDDMC_FLAG_DUST_WEIGHT needs dust_abs", idx);
     if (m.flags & RDDMC_FLAG_GROUPS) {   // frequency groups (Sec. 5.3): one table per cloud
         if (m.geometry == RDDMC_CART3D)
             return fail(RDDMC_EUNSUPPORTED, "cloud %d: frequency groups are for 1D clouds", idx);
@@ -334,6 +336,8 @@ rddmc_status make_layout(const rddmc_batch *b, Layout &L)
         c.off_src_t = hybrid1d ? take(16ull * c.n_src) : 0;
         c.off_census = c.n_census > 0 ? take(8ull * (c.n_census + 1)) : 0;
         c.groups = (m.flags & RDDMC_FLAG_GROUPS) ? 1 : 0;
+        c.dust_weight = (m.flags & RDDMC_FLAG_DUST_WEIGHT) ? 1 : 0;
+        if (c.dust_weight) L.h.dust_weight1d = 1u;
         c.off_grp_prob = c.groups ? take(8ull * c.nb * c.nb) : 0;
         c.off_grp_alias = c.groups ? take(8ull * c.nb * c.nb) : 0;
         c.n_pix = m.geometry == RDDMC_CART3D
@@ -347,6 +351,10 @@ rddmc_status make_layout(const rddmc_batch *b, Layout &L)
             c.census_path_off = c.census_bin_off + (uint64_t)(c.n_census + 1) * c.n_states;
             c.census_accel_off = c.census_path_off + (uint64_t)c.n_census * c.n_states;
             c.tally_words = c.census_accel_off + (uint64_t)c.n_census * c.nc;
+        }
+        if (c.dust_weight) {
+            c.wspec_off = c.tally_words;
+            c.tally_words += 4 + 2ull * c.n_rows * (c.nb + 2);
         }
         tally += c.tally_words;
     }
@@ -630,7 +638,26 @@ rddmc_status rddmc_tally(const rddmc_batch *batch, const void *d_tally, size_t t
             z.surrogate_calls = w[TW_SURR_CALLS];
             z.absorbed = w[TW_ABSORBED];
             z.n_pix = c.n_pix;
+            z.escaped_w = z.t_mean_w = z.t_var_w = 0.0;
+            if (c.dust_weight) {
+                const uint64_t *ww = w + c.wspec_off;
+                long double sw = 0.0L;
+                for (uint64_t i = 0; i < nspec; ++i) sw += (long double)ww[4 + i];
+                sw /= (long double)kWeightFix;
+                const long double two64 = 18446744073709551616.0L;
+                const long double swt = ((long double)ww[1] * two64 + (long double)ww[0]) / (long double)kWeightFix;
+                const long double swt2 = ((long double)ww[3] * two64 + (long double)ww[2]) / (long double)kTimeFix;
+                z.escaped_w = (double)sw;
+                if (sw > 0.0L) {
+                    z.t_mean_w = (double)(swt / sw);
+                    z.t_var_w = (double)(swt2 / sw) - z.t_mean_w * z.t_mean_w;
+                }
+            }
         }
+        if (c.dust_weight && out->spectrum_w && out->spectrum_w[ci])
+            std::memcpy(out->spectrum_w[ci], w + c.wspec_off + 4, 8 * nspec);
+        if (c.dust_weight && out->spectrum_w2 && out->spectrum_w2[ci])
+            std::memcpy(out->spectrum_w2[ci], w + c.wspec_off + 4 + nspec, 8 * nspec);
         if (c.n_census > 0 && out->census_bin && out->census_bin[ci])
             std::memcpy(out->census_bin[ci], w + c.census_bin_off, 8ull * (c.n_census + 1) * c.n_states);
         if (c.n_census > 0 && out->census_path && out->census_path[ci])

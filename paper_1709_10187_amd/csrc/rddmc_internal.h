@@ -107,10 +107,16 @@ struct alignas(16) DevCloud {
     uint64_t off_grp_prob;       // frequency groups: f64 [nb * nb] P(j | j') of eq. 42, row j'
     uint64_t off_grp_alias;      //   u32x2 [nb * nb] Walker alias table per row {threshold, alias}
     int32_t groups;              // thin states carry a frequency group (Sec. 5.3)
-    int32_t pad1;
+    int32_t dust_weight;         // dust absorption by continuous weights (Sec. 2.4)
+    uint64_t wspec_off;          // (dust_weight) int64 word offset in the cloud's tally block:
+                                 //   sum w t (128-bit, 2^-32 units), sum w t^2 (128-bit, 2^-20
+                                 //   units), then the weighted and squared-weight spectra
+                                 //   [n_rows (nb + 2)] each, 2^-32 units
 };
 
 constexpr double kPathFix = RDDMC_CENSUS_PATH_FIX;   // residence-time fixed point (2^24 per length/c)
+constexpr double kWeightFix = RDDMC_WEIGHT_FIX;      // weighted escape tallies (2^32 per unit weight)
+constexpr double kLogWMin = 23.025850929940457;      // ln(1 / RDDMC_DUST_WMIN)
 constexpr double kAccelFix = RDDMC_CENSUS_ACCEL_FIX; // eq. 18 optical-depth fixed point (2^24)
 
 struct alignas(16) DevHeader {
@@ -123,6 +129,8 @@ struct alignas(16) DevHeader {
     uint32_t hybrid1d;           // 1D batch walked by the hybrid 1D walk (flag layout, MC tables)
     uint64_t off_voigt;          // f32 [kVoigtN] (3D batches)
     uint64_t off_u0;             // f32 [kU0NA * kU0NX] (3D batches)
+    uint32_t dust_weight1d;      // a cloud of the 1D batch carries continuous dust weights
+    uint32_t pad_h;
 };
 
 enum BuildError : uint32_t {

@@ -37,6 +37,8 @@
 // Escapes add face row (slab: face; sphere: one row), lab bin and time to the int64 tallies.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "mc_dev.h"
 #include "philox.h"
 #include "rddmc_internal.h"
@@ -58,6 +60,7 @@ struct Pk1 {
     float3 pos, n;
     float x;
     double t;
+    double lw;         // -ln(weight): optical depth of dust absorption so far (continuous weights)
     uint64_t steps;
     uint32_t mcs, tomc, toddmc, refl;
     Rng r;
@@ -175,9 +178,20 @@ __device__ __forceinline__ int time_bin1(double t)
 
 __device__ __forceinline__ int step_bin1(uint64_t n) { return n <= 1 ? 0 : 63 - __clzll((long long)n); }
 
-// The packet stays in state s over [t0, t1): census counts and residence times.
-__device__ void census_add(const DevCloud &c, const uint8_t *__restrict__ tb, unsigned long long *__restrict__ tally,
-                           int64_t s, double t0, double t1)
+// Integral over [a, b) of the weight exp(-(lw0 + ka (t - t0))) of a packet that had log-weight
+// lw0 at t0 (c = 1): w(a) (1 - exp(-ka (b - a))) / ka, the residence times the path correction.
+__device__ __forceinline__ double weight_integral(double a, double b, double t0, double lw0, double ka)
+{
+    const double wa = exp(-(lw0 + ka * (a - t0)));
+    return ka > 0.0 ? wa * (-expm1(-ka * (b - a)) / ka) : wa * (b - a);
+}
+
+// The packet stays in state s over [t0, t1): census counts and residence times.  With
+// continuous dust weights (log-weight lw0 at t0, decay rate ka) the counts are the weights at
+// the census times and the residences their integrals (2^-24 units both).
+template <bool WGT>
+__device__ __forceinline__ void census_add(const DevCloud &c, const uint8_t *__restrict__ tb, unsigned long long *__restrict__ tally,
+                           int64_t s, double t0, double t1, double lw0, double ka)
 {
     const double *ct = reinterpret_cast<const double *>(tb + c.off_census);
     const int n = c.n_census;
@@ -188,18 +202,24 @@ __device__ void census_add(const DevCloud &c, const uint8_t *__restrict__ tb, un
     }
     unsigned long long *w = tally + c.tally_off;
     const uint64_t ns = c.n_states;
-    for (int e = lo; e <= n && ct[e] < t1; ++e) atomicAdd(&w[c.census_bin_off + (uint64_t)e * ns + s], 1ull);
+    for (int e = lo; e <= n && ct[e] < t1; ++e)
+        atomicAdd(&w[c.census_bin_off + (uint64_t)e * ns + s],
+                  (WGT && c.dust_weight) ? (unsigned long long)rint(exp(-(lw0 + ka * (ct[e] - t0))) * kPathFix) : 1ull);
     for (int i = lo > 0 ? lo - 1 : 0; i < n && ct[i] < t1; ++i) {
         const double a0 = fmax(t0, ct[i]), b0 = fmin(t1, ct[i + 1]);
-        if (b0 > a0)
-            atomicAdd(&w[c.census_path_off + (uint64_t)i * ns + s], (unsigned long long)rint((b0 - a0) * kPathFix));
+        if (b0 > a0) {
+            const double r = (WGT && c.dust_weight) ? weight_integral(a0, b0, t0, lw0, ka) : b0 - a0;
+            atomicAdd(&w[c.census_path_off + (uint64_t)i * ns + s], (unsigned long long)rint(r * kPathFix));
+        }
     }
 }
 
 // Eq. 18: a leak of a step that stayed over [t0, t1) adds v times its residence in each census
-// interval to `cell` (signed fixed point, 2^-24).
-__device__ void accel_add(const DevCloud &c, const uint8_t *__restrict__ tb, unsigned long long *__restrict__ tally,
-                          int cell, double t0, double t1, double v)
+// interval to `cell` (signed fixed point, 2^-24); with continuous dust weights, v times the
+// weight's integral over the residence (the path correction).
+template <bool WGT>
+__device__ __forceinline__ void accel_add(const DevCloud &c, const uint8_t *__restrict__ tb, unsigned long long *__restrict__ tally,
+                          int cell, double t0, double t1, double v, double lw0, double ka)
 {
     const double *ct = reinterpret_cast<const double *>(tb + c.off_census);
     const int n = c.n_census;
@@ -211,12 +231,30 @@ __device__ void accel_add(const DevCloud &c, const uint8_t *__restrict__ tb, uns
     unsigned long long *w = tally + c.tally_off + c.census_accel_off;
     for (int i = lo > 0 ? lo - 1 : 0; i < n && ct[i] < t1; ++i) {
         const double a0 = fmax(t0, ct[i]), b0 = fmin(t1, ct[i + 1]);
-        if (b0 > a0)
-            atomicAdd(&w[(uint64_t)i * c.nc + cell], (unsigned long long)(long long)rint(v * (b0 - a0) * kAccelFix));
+        if (b0 > a0) {
+            const double r = (WGT && c.dust_weight) ? weight_integral(a0, b0, t0, lw0, ka) : b0 - a0;
+            atomicAdd(&w[(uint64_t)i * c.nc + cell], (unsigned long long)(long long)rint(v * r * kAccelFix));
+        }
     }
 }
 
-__device__ void finish1(Pk1 &p, const DevCloud &c, unsigned long long *__restrict__ tally, bool escaped, int row,
+// A weighted escape (continuous dust weights): weight and squared weight into slot q of the
+// weighted spectra, w t and w t^2 into their 128-bit sums.
+__device__ __forceinline__ void escape_weighted(const DevCloud &c, unsigned long long *w, uint64_t q, uint64_t nspec,
+                                             double lw, double t)
+{
+    unsigned long long *ww = w + c.wspec_off;
+    const double wt = exp(-lw);
+    atomicAdd(&ww[4 + q], (unsigned long long)rint(wt * kWeightFix));
+    atomicAdd(&ww[4 + nspec + q], (unsigned long long)rint(wt * wt * kWeightFix));
+    const unsigned long long a1 = (unsigned long long)rint(wt * t * kWeightFix);
+    if (atomicAdd(&ww[0], a1) + a1 < a1) atomicAdd(&ww[1], 1ull);
+    const unsigned long long a2 = (unsigned long long)rint(wt * t * t * kTimeFix);
+    if (atomicAdd(&ww[2], a2) + a2 < a2) atomicAdd(&ww[3], 1ull);
+}
+
+template <bool WGT>
+__device__ __forceinline__ void finish1(Pk1 &p, const DevCloud &c, unsigned long long *__restrict__ tally, bool escaped, int row,
                         int slot, bool absorbed = false)
 {
     unsigned long long *w = tally + c.tally_off;
@@ -231,6 +269,7 @@ __device__ void finish1(Pk1 &p, const DevCloud &c, unsigned long long *__restric
         const unsigned long long old = atomicAdd(&w[TW_T2_LO], t2);
         if (old + t2 < old) atomicAdd(&w[TW_T2_HI], 1ull);
         atomicAdd(&w[kTallyHeader + nspec + time_bin1(p.t)], 1ull);
+        if (WGT && c.dust_weight) escape_weighted(c, w, (uint64_t)row * (c.nb + 2) + slot, nspec, p.lw, p.t);
     } else {
         atomicAdd(&w[TW_CAPPED], 1ull);
     }
@@ -252,8 +291,8 @@ __device__ __forceinline__ int neighbour1(const DevCloud &c, int cell, int f)
 }
 
 // One DDMC step of a packet in a thick state.
-template <bool SPH>
-__device__ void ddmc_step1(Pk1 &p, const DevCloud &c, const uint8_t *__restrict__ tb, const McArgs &a,
+template <bool SPH, bool WGT>
+__device__ __forceinline__ void ddmc_step1(Pk1 &p, const DevCloud &c, const uint8_t *__restrict__ tb, const McArgs &a,
                            unsigned long long *__restrict__ tally)
 {
     const int nb = c.nb;
@@ -261,9 +300,19 @@ __device__ void ddmc_step1(Pk1 &p, const DevCloud &c, const uint8_t *__restrict_
     const uint4 rec = reinterpret_cast<const uint4 *>(tb + c.off_hot)[s];
     const uint32_t tw = draw(p.r, a), ew = draw(p.r, a);
     const double dl = (double)ddmc_path(tw, __uint_as_float(rec.x));
-    if (c.n_census > 0) census_add(c, tb, tally, s, p.t, p.t + dl);
+    // continuous dust weights: the interaction distance dl carries optical depth k_a dl
+    const double ka = (WGT && c.dust_weight) ? reinterpret_cast<const double *>(tb + c.off_dust)[2 * p.cell] : 0.0;
+    const double lw0 = p.lw;
+    if (c.n_census > 0) census_add<WGT>(c, tb, tally, s, p.t, p.t + dl, lw0, ka);
     const double t0 = p.t;
     p.t += dl;
+    if (WGT && c.dust_weight) {
+        p.lw += ka * dl;
+        if (p.lw > kLogWMin) {   // negligible weight: eliminated
+            finish1<WGT>(p, c, tally, false, 0, 0, true);
+            return;
+        }
+    }
     int ev;
     bool have_lo = false;
     uint32_t lo_word = 0u;
@@ -291,7 +340,7 @@ __device__ void ddmc_step1(Pk1 &p, const DevCloud &c, const uint8_t *__restrict_
             absorb = (((uint64_t)ew << 32) | lo_word) >= A;
         }
         if (absorb) {
-            finish1(p, c, tally, false, 0, 0, true);
+            finish1<WGT>(p, c, tally, false, 0, 0, true);
             return;
         }
     }
@@ -313,7 +362,7 @@ __device__ void ddmc_step1(Pk1 &p, const DevCloud &c, const uint8_t *__restrict_
     const int f = v >= reinterpret_cast<const uint32_t *>(tb + c.off_face_split)[s] ? 1 : 0;
     const double *kt = reinterpret_cast<const double *>(tb + c.off_k);
     const double dir = f ? 1.0 : -1.0;
-    if (c.n_census > 0) accel_add(c, tb, tally, p.cell, t0, p.t, dir * kt[s]);   // outward leakage (eq. 18)
+    if (c.n_census > 0) accel_add<WGT>(c, tb, tally, p.cell, t0, p.t, dir * kt[s], lw0, ka);   // outward leakage (eq. 18)
     const float xin = bin_x(c, tb, p.j, uf(draw(p.r, a)));
     const int nbc = neighbour1(c, p.cell, f);
     const float4 *mcell = reinterpret_cast<const float4 *>(tb + c.off_mcell);
@@ -324,7 +373,7 @@ __device__ void ddmc_step1(Pk1 &p, const DevCloud &c, const uint8_t *__restrict_
         const float nu = n_dot_u<SPH>(mcell[2 * p.cell + 1].x, p.pos, p.n);
         if (nbc < 0) {
             const int slot = c.moving ? bin_of(c, tb, xin + nu) + 1 : p.j + 1;
-            finish1(p, c, tally, true, SPH ? 0 : f, slot);
+            finish1<WGT>(p, c, tally, true, SPH ? 0 : f, slot);
             return;
         }
         const float4 m0 = mcell[2 * p.cell], m1 = mcell[2 * nbc];
@@ -361,12 +410,12 @@ __device__ void ddmc_step1(Pk1 &p, const DevCloud &c, const uint8_t *__restrict_
         }
     }
     if (c.n_census > 0 && ddmc_in)   // inward leakage into a DDMC state (eq. 18)
-        accel_add(c, tb, tally, p.cell, t0, p.t, dir * kt[(int64_t)p.cell * nb + p.j]);
+        accel_add<WGT>(c, tb, tally, p.cell, t0, p.t, dir * kt[(int64_t)p.cell * nb + p.j], lw0, ka);
 }
 
 // One continuous-MC event (a scattering or a boundary crossing) of a packet in a thin state.
-template <bool SPH>
-__device__ void mc_step1(Pk1 &p, const DevCloud &c, const uint8_t *__restrict__ tb, const McArgs &a,
+template <bool SPH, bool WGT>
+__device__ __forceinline__ void mc_step1(Pk1 &p, const DevCloud &c, const uint8_t *__restrict__ tb, const McArgs &a,
                          unsigned long long *__restrict__ tally, const float *__restrict__ vtab,
                          const float *__restrict__ u0tab)
 {
@@ -379,13 +428,23 @@ __device__ void mc_step1(Pk1 &p, const DevCloud &c, const uint8_t *__restrict__ 
     int fexit = 1;
     const float dwall = wall_distance<SPH>(fz, p.cell, p.pos, p.n, p.left_inner, fexit);
     const float kl = m0.x * voigt_f32(m0.y, p.x, vtab);
-    const float kx = c.dusty ? kl + m1c.y + m1c.z : kl;
+    // dust absorption is an interaction, or (continuous weights) a decay of the weight
+    const float kab = (WGT && c.dust_weight) ? 0.0f : m1c.z;
+    const float kx = c.dusty ? kl + m1c.y + kab : kl;
     const float ds = -__logf(uf(draw(p.r, a))) / kx;
     const float u0 = n_dot_u<SPH>(uc, p.pos, p.n);
+    const double fl = (double)fminf(ds, dwall);
     if (c.n_census > 0) {
         int jc = bin_of(c, tb, p.x);
         jc = jc < 0 ? 0 : (jc > c.nb - 1 ? c.nb - 1 : jc);
-        census_add(c, tb, tally, (int64_t)p.cell * c.nb + jc, p.t, p.t + (double)fminf(ds, dwall));
+        census_add<WGT>(c, tb, tally, (int64_t)p.cell * c.nb + jc, p.t, p.t + fl, p.lw, (double)m1c.z);
+    }
+    if (WGT && c.dust_weight) {
+        p.lw += (double)m1c.z * fl;
+        if (p.lw > kLogWMin) {   // negligible weight: eliminated
+            finish1<WGT>(p, c, tally, false, 0, 0, true);
+            return;
+        }
     }
     if (ds < dwall) {   // an interaction
         p.pos.x = fmaf(ds, p.n.x, p.pos.x);
@@ -395,11 +454,11 @@ __device__ void mc_step1(Pk1 &p, const DevCloud &c, const uint8_t *__restrict__ 
         if (SPH && c.moving) p.x += u0 - n_dot_u<SPH>(uc, p.pos, p.n);
         if (c.dusty) {   // which opacity interacted: dust absorption, dust scattering or Lya
             const float v = uf(draw(p.r, a)) * kx;
-            if (v < m1c.z) {
-                finish1(p, c, tally, false, 0, 0, true);
+            if (v < kab) {
+                finish1<WGT>(p, c, tally, false, 0, 0, true);
                 return;
             }
-            if (v < m1c.z + m1c.y) {   // dust: isotropic, coherent in the comoving frame
+            if (v < kab + m1c.y) {   // dust: isotropic, coherent in the comoving frame
                 p.n = iso_dir(p.r, a);
                 p.left_inner = false;
                 return;
@@ -407,7 +466,7 @@ __device__ void mc_step1(Pk1 &p, const DevCloud &c, const uint8_t *__restrict__ 
         }
         float upar;
         if (!sample_upar(m0.y, p.x, u0tab, p.r, a, upar)) {
-            finish1(p, c, tally, false, 0, 0);   // counted with the step-capped packets
+            finish1<WGT>(p, c, tally, false, 0, 0);   // counted with the step-capped packets
             return;
         }
         // perpendicular velocity in the scattering plane: sqrt(xc^2 - ln xi) cos(phi), a
@@ -444,7 +503,7 @@ __device__ void mc_step1(Pk1 &p, const DevCloud &c, const uint8_t *__restrict__ 
     if (SPH && c.moving) p.x += u0 - nu;
     const int nbc = neighbour1(c, p.cell, fexit);
     if (nbc < 0) {
-        finish1(p, c, tally, true, SPH ? 0 : fexit, bin_of(c, tb, p.x + nu) + 1);
+        finish1<WGT>(p, c, tally, true, SPH ? 0 : fexit, bin_of(c, tb, p.x + nu) + 1);
         return;
     }
     const float4 m1 = mcell[2 * nbc];
@@ -480,8 +539,8 @@ __device__ void mc_step1(Pk1 &p, const DevCloud &c, const uint8_t *__restrict__ 
 // (eq. 14) plus any dust; a scattering takes the outgoing bin from row j of the cloud's alias
 // table of eq. 42 (two 32-bit words) and an isotropic direction.  Boundaries as in mc_step1,
 // with the bin unchanged across faces (no velocities, one temperature).
-template <bool SPH>
-__device__ void grp_step1(Pk1 &p, const DevCloud &c, const uint8_t *__restrict__ tb, const McArgs &a,
+template <bool SPH, bool WGT>
+__device__ __forceinline__ void grp_step1(Pk1 &p, const DevCloud &c, const uint8_t *__restrict__ tb, const McArgs &a,
                           unsigned long long *__restrict__ tally)
 {
     ++p.mcs;
@@ -491,15 +550,24 @@ __device__ void grp_step1(Pk1 &p, const DevCloud &c, const uint8_t *__restrict__
     int fexit = 1;
     const float dwall = wall_distance<SPH>(fz, p.cell, p.pos, p.n, p.left_inner, fexit);
     const float kl = (float)kt[s];
-    float ka = 0.0f, ks = 0.0f;
+    float ka = 0.0f, ks = 0.0f, kd = 0.0f;   // kd: dust absorption rate (either method)
     if (c.dusty) {
         const float4 m1c = reinterpret_cast<const float4 *>(tb + c.off_mcell)[2 * p.cell + 1];
         ks = m1c.y;
-        ka = m1c.z;
+        kd = m1c.z;
+        ka = (WGT && c.dust_weight) ? 0.0f : kd;
     }
     const float kx = kl + ks + ka;
     const float ds = -__logf(uf(draw(p.r, a))) / kx;
-    if (c.n_census > 0) census_add(c, tb, tally, s, p.t, p.t + (double)fminf(ds, dwall));
+    const double fl = (double)fminf(ds, dwall);
+    if (c.n_census > 0) census_add<WGT>(c, tb, tally, s, p.t, p.t + fl, p.lw, (double)kd);
+    if (WGT && c.dust_weight) {
+        p.lw += (double)kd * fl;
+        if (p.lw > kLogWMin) {   // negligible weight: eliminated
+            finish1<WGT>(p, c, tally, false, 0, 0, true);
+            return;
+        }
+    }
     if (ds < dwall) {   // an interaction
         p.pos.x = fmaf(ds, p.n.x, p.pos.x);
         p.pos.y = fmaf(ds, p.n.y, p.pos.y);
@@ -509,7 +577,7 @@ __device__ void grp_step1(Pk1 &p, const DevCloud &c, const uint8_t *__restrict__
         if (c.dusty) {
             const float v = uf(draw(p.r, a)) * kx;
             if (v < ka) {
-                finish1(p, c, tally, false, 0, 0, true);
+                finish1<WGT>(p, c, tally, false, 0, 0, true);
                 return;
             }
             if (v < ka + ks) {   // dust: isotropic, the bin unchanged
@@ -544,7 +612,7 @@ __device__ void grp_step1(Pk1 &p, const DevCloud &c, const uint8_t *__restrict__
     p.t += (double)dwall;
     const int nbc = neighbour1(c, p.cell, fexit);
     if (nbc < 0) {
-        finish1(p, c, tally, true, SPH ? 0 : fexit, p.j + 1);
+        finish1<WGT>(p, c, tally, true, SPH ? 0 : fexit, p.j + 1);
         return;
     }
     if (reinterpret_cast<const uint4 *>(tb + c.off_hot)[(int64_t)nbc * c.nb + p.j].w & kFlagThick) {
@@ -577,7 +645,7 @@ __device__ __forceinline__ uint64_t shfl64(uint64_t v, int src)
     return ((uint64_t)hi << 32) | lo;
 }
 
-template <bool SPH, bool SINGLE>
+template <bool SPH, bool SINGLE, bool WGT>
 __global__ __launch_bounds__(256) void walk1dh(const uint8_t *__restrict__ tb, McArgs a,
                                                unsigned long long *__restrict__ tally,
                                                unsigned long long *__restrict__ work)
@@ -600,6 +668,7 @@ __global__ __launch_bounds__(256) void walk1dh(const uint8_t *__restrict__ tb, M
     p.n = make_float3(0.f, 0.f, 1.f);
     p.x = 0.f;
     p.t = 0.0;
+    p.lw = 0.0;
     p.steps = 0;
     p.mcs = p.tomc = p.toddmc = p.refl = 0u;
     p.r = Rng{0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 4u, false, 0u, 0u, 0u, 0u};
@@ -644,6 +713,7 @@ __global__ __launch_bounds__(256) void walk1dh(const uint8_t *__restrict__ tb, M
                         p.cell = (int)(st / c.nb);
                         p.j = (int)(st - (int64_t)p.cell * c.nb);
                         p.t = 0.0;
+                        p.lw = 0.0;
                         if (c.off_src_t) {   // emission uniform over the source's window
                             const double *tw = reinterpret_cast<const double *>(tb + c.off_src_t) + 2 * lo;
                             p.t = tw[0] + (tw[1] - tw[0]) * ud(draw(p.r, a));
@@ -671,7 +741,7 @@ __global__ __launch_bounds__(256) void walk1dh(const uint8_t *__restrict__ tb, M
         // one event; every packet's own sequence of steps and draws is unchanged by this.
         const DevCloud &c = clouds[SINGLE ? 0 : p.cl];
         for (int k = 0; k < a.chunk; ++k) {
-            if (p.active && p.steps >= a.max_steps) finish1(p, c, tally, false, 0, 0);
+            if (p.active && p.steps >= a.max_steps) finish1<WGT>(p, c, tally, false, 0, 0);
             const uint64_t bm = __ballot(p.active && p.mc);
             const uint64_t bd = __ballot(p.active && !p.mc);
             if (!(bm | bd)) break;
@@ -682,14 +752,14 @@ __global__ __launch_bounds__(256) void walk1dh(const uint8_t *__restrict__ tb, M
                 ++p.steps;
                 if (mc_pass) {
                     if (c.groups)
-                        grp_step1<SPH>(p, c, tb, a, tally);
+                        grp_step1<SPH, WGT>(p, c, tb, a, tally);
                     else
-                        mc_step1<SPH>(p, c, tb, a, tally, vtab, u0tab);
+                        mc_step1<SPH, WGT>(p, c, tb, a, tally, vtab, u0tab);
                 } else {
-                    ddmc_step1<SPH>(p, c, tb, a, tally);
+                    ddmc_step1<SPH, WGT>(p, c, tb, a, tally);
                     if (p.active && !p.mc && p.steps < a.max_steps) {
                         ++p.steps;
-                        ddmc_step1<SPH>(p, c, tb, a, tally);
+                        ddmc_step1<SPH, WGT>(p, c, tb, a, tally);
                     }
                 }
             }
@@ -727,14 +797,23 @@ hipError_t launch_walk1dh(const uint8_t *d_tables, const DevHeader &h, const rdd
     reset_queue1<<<1, 64, 0, s>>>(d_work);
     const bool sph = h.geometry == RDDMC_SPHERE;
     const bool single = h.n_clouds == 1;
-    if (sph && single)
-        walk1dh<true, true><<<(unsigned)grid, block, 0, s>>>(d_tables, a, d_tally, d_work);
-    else if (sph)
-        walk1dh<true, false><<<(unsigned)grid, block, 0, s>>>(d_tables, a, d_tally, d_work);
-    else if (single)
-        walk1dh<false, true><<<(unsigned)grid, block, 0, s>>>(d_tables, a, d_tally, d_work);
+    // batches with continuous dust weights take their own instantiation, so that the others
+    // keep the registers (and occupancy) of a walk without them
+    auto go = [&](auto wgt) {
+        constexpr bool W = decltype(wgt)::value;
+        if (sph && single)
+            walk1dh<true, true, W><<<(unsigned)grid, block, 0, s>>>(d_tables, a, d_tally, d_work);
+        else if (sph)
+            walk1dh<true, false, W><<<(unsigned)grid, block, 0, s>>>(d_tables, a, d_tally, d_work);
+        else if (single)
+            walk1dh<false, true, W><<<(unsigned)grid, block, 0, s>>>(d_tables, a, d_tally, d_work);
+        else
+            walk1dh<false, false, W><<<(unsigned)grid, block, 0, s>>>(d_tables, a, d_tally, d_work);
+    };
+    if (h.dust_weight1d)
+        go(std::true_type{});
     else
-        walk1dh<false, false><<<(unsigned)grid, block, 0, s>>>(d_tables, a, d_tally, d_work);
+        go(std::false_type{});
     return hipGetLastError();
 }
 

@@ -25,6 +25,8 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "ESIZE", -3: "EUNSUPPORTED", -4: "ENUMERIC"
 FLAG_DIRICHLET = 1 << 0
 FLAG_KEEP_RATES = 1 << 1
 FLAG_GROUPS = 1 << 2          # thin states use frequency groups (Sec. 5.3 eq. 42)
+FLAG_DUST_WEIGHT = 1 << 3     # dust absorption by continuous packet weights (Sec. 2.4)
+WEIGHT_FIX = float(1 << 32)   # weighted escape tallies: 2^-32 units
 
 
 class RddmcError(RuntimeError):
@@ -70,17 +72,19 @@ class CloudStats_t(C.Structure):
                 ("t_mean", C.c_double), ("t_var", C.c_double), ("n_rows", C.c_int32),
                 ("n_slots", C.c_int32), ("to_mc", C.c_uint64), ("to_ddmc", C.c_uint64),
                 ("reflected", C.c_uint64), ("mc_steps", C.c_uint64), ("n_pix", C.c_uint64),
-                ("surrogate_calls", C.c_uint64), ("absorbed", C.c_uint64)]
+                ("surrogate_calls", C.c_uint64), ("absorbed", C.c_uint64), ("escaped_w", C.c_double),
+                ("t_mean_w", C.c_double), ("t_var_w", C.c_double)]
 
 
 class TallyOut_t(C.Structure):
     _fields_ = [("spectrum", C.POINTER(C.c_void_p)), ("time_hist", C.POINTER(C.c_void_p)),
                 ("step_hist", C.POINTER(C.c_void_p)), ("stats", C.POINTER(CloudStats_t)),
                 ("pixels", C.POINTER(C.c_void_p)), ("census_bin", C.POINTER(C.c_void_p)),
-                ("census_path", C.POINTER(C.c_void_p)), ("census_accel", C.POINTER(C.c_void_p))]
+                ("census_path", C.POINTER(C.c_void_p)), ("census_accel", C.POINTER(C.c_void_p)),
+                ("spectrum_w", C.POINTER(C.c_void_p)), ("spectrum_w2", C.POINTER(C.c_void_p))]
 
 
-ABI_VERSION = 7
+ABI_VERSION = 8
 CENSUS_PATH_FIX = float(1 << 24)   # residence-time units per length/c
 CENSUS_ACCEL_FIX = float(1 << 24)  # eq. 18 optical-depth units
 
@@ -297,6 +301,12 @@ class CloudTally:
     census_bin: Optional[np.ndarray] = None    # (n_census+1, cells, bins) int64 packets per state at t_e
     census_path: Optional[np.ndarray] = None   # (n_census, cells, bins) int64 residence, 2^-24 units
     census_accel: Optional[np.ndarray] = None  # (n_census, cells) int64 eq. 18 optical-depth sums, 2^-24 units
+    # continuous dust weights (FLAG_DUST_WEIGHT; census_bin then holds weights in 2^-24 units)
+    spectrum_w: Optional[np.ndarray] = None    # (rows, nb+2) escaped weight
+    spectrum_w2: Optional[np.ndarray] = None   # (rows, nb+2) escaped squared weight
+    escaped_w: float = 0.0
+    t_mean_w: float = 0.0
+    t_var_w: float = 0.0
 
 
 def n_pixels(m) -> int:
@@ -327,8 +337,14 @@ def tally(b: Batch, d_tally, stream=None) -> List[CloudTally]:
     cb_ptrs = (C.c_void_p * n)(*[a.ctypes.data if a.size else None for a in cb])
     cp_ptrs = (C.c_void_p * n)(*[a.ctypes.data if a.size else None for a in cp])
     ca_ptrs = (C.c_void_p * n)(*[a.ctypes.data if a.size else None for a in ca])
+    weighted = [bool(int(m.flags) & FLAG_DUST_WEIGHT) for m in b.meds]
+    sw = [np.zeros((b.n_rows(i), b.meds[i].n_bins + 2), dtype=np.int64) if weighted[i] else np.zeros(0, np.int64)
+          for i in range(n)]
+    sw2 = [np.zeros_like(a) for a in sw]
+    sw_ptrs = (C.c_void_p * n)(*[a.ctypes.data if a.size else None for a in sw])
+    sw2_ptrs = (C.c_void_p * n)(*[a.ctypes.data if a.size else None for a in sw2])
     stats = (CloudStats_t * n)()
-    out = TallyOut_t(sp_ptrs, th_ptrs, sh_ptrs, stats, px_ptrs, cb_ptrs, cp_ptrs, ca_ptrs)
+    out = TallyOut_t(sp_ptrs, th_ptrs, sh_ptrs, stats, px_ptrs, cb_ptrs, cp_ptrs, ca_ptrs, sw_ptrs, sw2_ptrs)
     _check(lib.rddmc_tally(b.ref(), C.c_void_p(d_tally.data_ptr()), d_tally.numel() * d_tally.element_size(),
                            C.byref(out), _stream(stream)))
     res = []
@@ -338,7 +354,10 @@ def tally(b: Batch, d_tally, stream=None) -> List[CloudTally]:
                               z.steps_max, z.steps_mean, z.t_mean, z.t_var, z.to_mc, z.to_ddmc, z.reflected,
                               z.mc_steps, pix[i] if pix[i].size else None, z.surrogate_calls, z.absorbed,
                               cb[i] if cb[i].size else None, cp[i] if cp[i].size else None,
-                              ca[i] if ca[i].size else None))
+                              ca[i] if ca[i].size else None,
+                              sw[i].astype(np.float64) / WEIGHT_FIX if weighted[i] else None,
+                              sw2[i].astype(np.float64) / WEIGHT_FIX if weighted[i] else None,
+                              z.escaped_w, z.t_mean_w, z.t_var_w))
     return res
 
 

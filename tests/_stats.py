@@ -113,3 +113,26 @@ def assert_spectrum_matches(res, l1_max=None):
     assert res["p_value"] >= 1e-3, res
     if l1_max is not None:
         assert res["L1"] <= l1_max, res
+
+
+def run_watched(prob, seed, poll_s=10.0, label="", **kw):
+    """One transport launch of ``prob`` on a side stream (a single tail for the whole run),
+    with the tallies read on another stream every ``poll_s`` seconds and a line printed
+    whenever more packets have finished: long GPU steps report their own progress."""
+    import time
+    import torch
+    from paper_1709_10187_amd import rddmc
+    cur = torch.cuda.current_stream()
+    run_s, poll_st = torch.cuda.Stream(), torch.cuda.Stream()
+    stop = torch.cuda.Event()
+    run_s.wait_stream(cur)
+    rddmc.transport(prob.batch, prob.tables, prob.tallies, prob.work, seed=seed, stream=run_s, **kw)
+    stop.record(run_s)
+    t0, last = time.perf_counter(), 0
+    while not stop.query():
+        time.sleep(poll_s)
+        done = sum(r.escaped + r.capped + r.absorbed for r in rddmc.tally(prob.batch, prob.tallies, stream=poll_st))
+        if done > last:
+            print(f"    {label}{done} packets finished ({time.perf_counter() - t0:.0f} s)", flush=True)
+            last = done
+    torch.cuda.synchronize()

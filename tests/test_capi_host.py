@@ -26,7 +26,7 @@ def test_library_exports_every_declared_symbol():
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) == set(rddmc.EXPORTS)
-    assert lib.rddmc_abi_version() == rddmc.ABI_VERSION == 7
+    assert lib.rddmc_abi_version() == rddmc.ABI_VERSION == 8
 
 
 def test_cart3d_size_queries():

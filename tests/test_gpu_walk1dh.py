@@ -9,7 +9,7 @@ import pytest
 
 from oracle import chain, walk1dh
 from paper_1709_10187_amd import media, rddmc
-from tests._stats import assert_spectrum_matches, compare_exact, compare_two_samples
+from tests._stats import assert_spectrum_matches, compare_exact, compare_two_samples, run_watched
 
 pytestmark = pytest.mark.gpu
 
@@ -105,14 +105,23 @@ def test_workloads_at_tau_threshold_10(name):
     else:
         m = media.config_sphere().replace(tau_threshold=10.0)
         ng, no = 1 << 12, 1 << 6
-    g = _gpu(m, ng, seed=2)
-    o = walk1dh.run(m, n_packets=no, seed=8)
-    assert g.escaped == ng and o.escaped == no and g.to_mc > 0
-    r = compare_two_samples(g.spectrum, o.spectrum)
-    print(f"    L1 {r['L1']:.4f} max|z| {r['max_abs_z']:.2f}; to_mc/pk {g.to_mc / ng:.3g} vs {o.to_mc / no:.3g}",
+    print(f"[walk1dh] {m.name} cells={m.n_cells[0]} bins={m.n_bins} tau_th={m.tau_threshold} packets={ng}", flush=True)
+    p = rddmc.Problem(m.with_packets(ng))
+    run_watched(p, seed=2, label="GPU: ")
+    g = p.results()[0]
+    print(f"    GPU walk done: {g.steps_mean:.4g} steps per packet; oracle walker on {no} packets", flush=True)
+    spec, esc, to_mc = 0, 0, 0
+    for k in range(4):   # the oracle in four runs of consecutive ids, so that progress shows
+        o = walk1dh.run(m, n_packets=no // 4, seed=8, first_id=k * (no // 4))
+        spec, esc, to_mc = spec + o.spectrum, esc + o.escaped, to_mc + o.to_mc
+        print(f"    oracle packets {(k + 1) * (no // 4)} of {no} done", flush=True)
+    assert g.escaped == ng and esc == no and g.to_mc > 0
+    r = compare_two_samples(g.spectrum, spec)
+    print(f"    L1 {r['L1']:.4f} max|z| {r['max_abs_z']:.2f}; to_mc/pk {g.to_mc / ng:.3g} vs {to_mc / no:.3g}",
           flush=True)
     assert_spectrum_matches(r)
     if name == "sphere":
+        print("    solving the exact chain of the pure sphere", flush=True)
         ref = chain.solve(media.config_sphere())
         rp = compare_exact(g.spectrum, ref.spectrum, ng)
         print(f"    hybrid against the pure chain: L1 {rp['L1']:.4f} (noise {rp['expected_noise_L1']:.4f}), "

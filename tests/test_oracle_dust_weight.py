@@ -1,8 +1,9 @@
 """Pins of the oracle walker's continuous dust weights (Sec. 2.4's second method) against the
 exact chain, whose dust absorption is a killing channel: the expected escaped weight per slot
 is the chain's escape probability, the weighted mean escape time its mean escape time, and the
-weighted 'bin', 'path' and eq. 18 estimators (with the path correction) are the killed chain's
-transient expectations; and the two dust methods of the oracle walker against each other on a
+weighted 'bin' and 'path' estimators (with the path correction) are the killed chain's
+transient expectations, and eq. 18's is the chain's with leak probabilities r_f / K_leak (no
+absorption event ends a weighted step); and the two dust methods of the oracle walker against each other on a
 hybrid slab with continuous-MC wings.  Weights lie in [0, 1], so every weighted estimator's
 variance is at most its mean."""
 import math
@@ -41,7 +42,7 @@ def test_weighted_census_and_acceleration_match_the_killed_transient_law():
                                                         dust_sca=np.full(4, 0.5), flags=W)
     ref = chain.solve(m)
     edges = np.array([0.0, 0.2, 0.5, 1.0, 2.0, 4.0]) * ref.t_mean
-    ex = chain.transient(m, edges)
+    ex = chain.transient(m, edges, dust_weights=True)
     n = 1 << 17
     o = walk1dh.run(m.replace(census=edges), n_packets=n, seed=23)
     p = ex.at_edges.ravel()
@@ -53,12 +54,15 @@ def test_weighted_census_and_acceleration_match_the_killed_transient_law():
     want = ex.mean_in.ravel()
     tol = 5 * np.sqrt(np.maximum(want, 1e-30) / n) + 1e-6
     assert np.all(np.abs(mean - want) <= tol)
-    # eq. 18 with the path correction: |k d| w integrated over a residence; its per-packet
-    # variance is at most max|k| times the residence estimate's
-    kmax = float(np.max(np.abs(m.k0)))
-    acc = o.e_accel / n
-    tol_a = 6 * kmax * np.sqrt(np.maximum(ex.mean_in.sum(axis=2) * dt[:, :, 0], 1e-30) / n) + 1e-9
-    assert np.all(np.abs(acc - ex.accel) <= tol_a), (acc, ex.accel)
+    # eq. 18 with the path correction, against the chain's expectation for weighted walks (its
+    # per-packet spread from eight independent seeds); the probabilistic method's expectation
+    # (r_f / (K_leak + k_a) per unit residence) differs here by about 20 %
+    runs = np.array([walk1dh.run(m.replace(census=edges), n_packets=1 << 15, seed=60 + b).e_accel / (1 << 15)
+                     for b in range(8)])
+    mean, se = runs.mean(axis=0), runs.std(axis=0, ddof=1) / math.sqrt(len(runs))
+    assert np.all(np.abs(mean - ex.accel) <= 5.0 * se + 1e-9), (mean, ex.accel, se)
+    other = chain.transient(m, edges).accel
+    assert np.max(np.abs(other - ex.accel) / np.maximum(se, 1e-12)) > 10   # the test tells the two apart
 
 
 def test_weights_and_probabilistic_absorption_agree_on_a_hybrid_slab():
