@@ -354,18 +354,15 @@ def bench_sweep_full(args):
     per cloud (capped at 2^20 steps, untimed) estimates each cloud's steps per packet, so the
     clouds whose packets take longest start first and the launch does not end on them."""
     import torch
-    from paper_1709_10187_amd import media, rddmc
+    from paper_1709_10187_amd import autotune, media, rddmc
     meds = media.config_sweep(packet_scale=args.sweep_scale)
     n_cl = len(meds)
     t0 = time.perf_counter()
     log(f"sweep-full: pilot of 64 packets per cloud over {n_cl} clouds")
-    pilot = rddmc.Problem([m.with_packets(64) for m in meds], streams=list(range(n_cl)))
-    ekp = rddmc.ExitKernel(pilot, min_steps=args.ek_min_steps)
-    pilot.run(seed=987654321, surrogate=ekp.buffer, max_steps=1 << 20)
-    cost = [r.steps_mean for r in pilot.results()]
-    del pilot, ekp
+    cost = autotune.pilot_costs(meds, streams=list(range(n_cl)),
+                                surrogate_fn=lambda q: rddmc.ExitKernel(q, min_steps=args.ek_min_steps).buffer)
     torch.cuda.empty_cache()
-    order = sorted(range(n_cl), key=lambda i: -cost[i])
+    order = autotune.longest_first(cost)
     t_pilot = time.perf_counter() - t0
     log(f"sweep-full: building tables and exit kernels ({t_pilot:.1f} s of pilot)")
     prob = rddmc.Problem([meds[i] for i in order], streams=order)

@@ -81,13 +81,25 @@ def test_autotuner_picks_a_working_schedule():
     meds = _small_sweep()
     p = rddmc.Problem(meds)
     best = autotune.tune(p, sample_packets=1 << 16, trial_steps=4000, use_cache=False,
-                         candidates=[(64, 512, 32), (256, 1024, 128), (128, 2048, 32)])
+                         candidates=[(64, 512, 32), (256, 1024, 128), (128, 2048, 32)],
+                         tail_candidates=(16, -1, 32), tail_packets_per_cloud=256)
     assert best["steps_per_s"] > 0 and len(best["trials"]) == 3
+    assert len(best["tail_trials"]) == 3 and best["tail_lanes"] in (16, -1, 32)
+    print(f"[batch] autotuned {autotune.schedule(best)}; tail trials "
+          f"{[(t['tail_lanes'], round(t['ms'], 1)) for t in best['tail_trials']]}", flush=True)
     p.run(seed=5, **autotune.schedule(best))
     q = rddmc.Problem(meds)
     q.run(seed=5)
     for a, b in zip(p.results(), q.results()):
         np.testing.assert_array_equal(a.spectrum, b.spectrum)
+
+
+def test_longest_first_order_from_the_pilot():
+    """The pilot's per-cloud cost orders the clouds; a denser cloud of the same grid walks longer."""
+    base = media.slab(200.0, 1e4, 8, 16)
+    meds = [base.replace(k0=np.full(8, tau)) for tau in (50.0, 800.0, 200.0)]
+    cost = autotune.pilot_costs(meds, packets=256)
+    assert autotune.longest_first(cost) == [1, 2, 0]
 
 
 def test_sweep_clouds_at_full_grid():
