@@ -123,3 +123,57 @@ def test_tables_3d_match_oracle(name):
     p_up = (S[thick].astype(np.float64) - D[thick].astype(np.float64)) / two64
     np.testing.assert_allclose(p_dn, t.rate_dn.reshape(ns)[thick] / K, rtol=1e-6, atol=2.0 ** -52)
     np.testing.assert_allclose(p_up, t.rate_up.reshape(ns)[thick] / K, rtol=1e-6, atol=2.0 ** -52)
+
+
+def _sub_block(m, ix, iy, iz):
+    """The 3 x 3 x 3 cells around (ix, iy, iz) of a Cartesian medium as a medium of its own: the
+    centre cell's leakage rates, opacities and flags depend only on it and its six neighbours."""
+    n = m.n_cells[0]
+    idx = [((z * n) + y) * n + x for z in range(iz - 1, iz + 2) for y in range(iy - 1, iy + 2)
+           for x in range(ix - 1, ix + 2)]
+    f = [np.asarray(m.faces[0])[ix - 1:ix + 3], np.asarray(m.faces[1])[iy - 1:iy + 3],
+         np.asarray(m.faces[2])[iz - 1:iz + 3]]
+    return m.replace(n_cells=(3, 3, 3), faces=f, k0=np.asarray(m.k0)[idx], temp=np.asarray(m.temp)[idx],
+                     vel=np.asarray(m.vel)[idx], src_pos=np.array([[ix + 0.5, iy + 0.5, iz + 0.5]]),
+                     src_x=np.zeros(1), n_packets=1)
+
+
+def test_full_size_cube_tables_at_sampled_cells():
+    """The 128^3 x 256 lognormal cube as the bench builds it (tau_th = 10): k, ln2/K, the event
+    thresholds and the flag word of every bin of 48 sampled interior cells (the 8 densest among
+    them) against the oracle's tables of each cell's 3 x 3 x 3 neighbourhood, 1e-6 relative."""
+    m = media.cube()
+    n, nb = m.n_cells[0], m.n_bins
+    prob = rddmc.Problem(m)
+    print(f"[tables] full cube: {prob.tables.numel() / 2**30:.2f} GiB of tables; reading back", flush=True)
+    k, _, hot, D, S, _ = prob.read_tables(0, want_rates=False)
+    del prob
+    rng = np.random.default_rng(12)
+    cells = [tuple(int(v) for v in rng.integers(1, n - 1, size=3)) for _ in range(40)]
+    dense = np.argsort(-np.asarray(m.k0), kind="stable")
+    for c in dense:
+        iz, rem = divmod(int(c), n * n)
+        iy, ix = divmod(rem, n)
+        if 0 < ix < n - 1 and 0 < iy < n - 1 and 0 < iz < n - 1:
+            cells.append((ix, iy, iz))
+        if len(cells) == 48:
+            break
+    two64 = 2.0 ** 64
+    for ix, iy, iz in cells:
+        t = tb.build(_sub_block(m, ix, iy, iz))
+        s0 = (((iz * n) + iy) * n + ix) * nb
+        g = slice(s0, s0 + nb)
+        np.testing.assert_allclose(k[g], t.k[13], rtol=1e-6)
+        thick = t.thick[13]
+        flags = hot["f_hi"][g]
+        np.testing.assert_array_equal((flags & 1) == 1, thick)
+        iface = (flags >> 1) & 63
+        ref_iface = (t.face_is_mc[13] * (1 << np.arange(6))).sum(axis=1)
+        np.testing.assert_array_equal(iface[thick], ref_iface[thick])
+        K = t.K[13][thick]
+        np.testing.assert_allclose(hot["ln2_over_K"][g][thick], LN2 / K, rtol=1e-6)
+        p_dn = D[g][thick].astype(np.float64) / two64
+        p_up = (S[g][thick].astype(np.float64) - D[g][thick].astype(np.float64)) / two64
+        np.testing.assert_allclose(p_dn, t.rate_dn[13][thick] / K, rtol=1e-6, atol=2.0 ** -52)
+        np.testing.assert_allclose(p_up, t.rate_up[13][thick] / K, rtol=1e-6, atol=2.0 ** -52)
+    print(f"    {len(cells)} cells x {nb} bins match", flush=True)
