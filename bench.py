@@ -110,6 +110,10 @@ def parse():
                     help="sphere workloads: walk with the exact per-cell exit kernel (built untimed)")
     ap.add_argument("--ek-min-steps", type=float, default=64.0, help="exit-kernel window: shortest expected sub-walk")
     ap.add_argument("--sweep-scale", type=float, default=1.0, help="sweep-full: fraction of the stated packet counts")
+    ap.add_argument("--methods-tau0", type=float, nargs="*", default=[1e3, 1e4, 1e5, 1e6],
+                    help="methods: the slabs' line-centre depths")
+    ap.add_argument("--methods-legs", nargs="*", default=["rddmc", "rddmc_efficient", "groups", "mcrt"],
+                    help="methods: which methods walk each slab")
     return ap.parse_args()
 
 
@@ -450,7 +454,7 @@ def bench_methods(args):
     from paper_1709_10187_amd import media, rddmc
     n = 1 << 16
     rows, headline = [], None
-    for tau0 in (1e3, 1e4, 1e5, 1e6):
+    for tau0 in args.methods_tau0:
         base = media.slab(tau0, 1e4, 64, 128, n_packets=n, name=f"slab_tau{tau0:.0e}")
         legs = {"rddmc": base}
         try:   # the efficient grid needs the spectrum to reach beyond the core (a tau0 >~ 2.5)
@@ -460,6 +464,7 @@ def bench_methods(args):
             eff = None
         legs["groups"] = base.replace(tau_threshold=media.ALL_THIN, flags=media.GROUP_MC)
         legs["mcrt"] = base.replace(tau_threshold=media.ALL_THIN)
+        legs = {k: v for k, v in legs.items() if k in args.methods_legs}
         row = {"tau0": tau0, "dx": float(base.bin_edges[1] - base.bin_edges[0])}
         spectra = {}
         for leg, m in legs.items():
@@ -478,27 +483,28 @@ def bench_methods(args):
                         "seconds": sec, "t_mean": r.t_mean}
             log(f"tau0 {tau0:.0e} {leg}: {sec:.3f} s, {n / sec:.4g} packets/s, {events / n:.4g} events/packet")
             del prob
-        row["speedup_rddmc_vs_mcrt"] = row["rddmc"]["packets_per_s"] / row["mcrt"]["packets_per_s"]
         if eff is not None:
             row["efficient_bins"] = len(eff) - 1
-            row["speedup_rddmc_efficient_vs_mcrt"] = (row["rddmc_efficient"]["packets_per_s"] /
-                                                      row["mcrt"]["packets_per_s"])
-        row["speedup_groups_vs_mcrt"] = row["groups"]["packets_per_s"] / row["mcrt"]["packets_per_s"]
-        row["L1_rddmc_vs_mcrt"] = float(np.abs(spectra["rddmc"] - spectra["mcrt"]).sum())
-        row["L1_groups_vs_mcrt"] = float(np.abs(spectra["groups"] - spectra["mcrt"]).sum())
+        if "mcrt" in row:
+            for leg in ("rddmc", "rddmc_efficient", "groups"):
+                if leg in row:
+                    row[f"speedup_{leg}_vs_mcrt"] = row[leg]["packets_per_s"] / row["mcrt"]["packets_per_s"]
+                    if leg != "rddmc_efficient":
+                        row[f"L1_{leg}_vs_mcrt"] = float(np.abs(spectra[leg] - spectra["mcrt"]).sum())
         rows.append(row)
-        if tau0 == 1e5:
+        if headline is None or tau0 == 1e5:
             headline = row
+    lead = next(leg for leg in ("rddmc", "rddmc_efficient", "groups", "mcrt") if leg in headline)
     out = base_line(
-        args, headline["rddmc"]["packets_per_s"], n / headline["rddmc"]["packets_per_s"], "f32",
+        args, headline[lead]["packets_per_s"], n / headline[lead]["packets_per_s"], "f32",
         {"workload": "static uniform slabs tau0 = 1e3..1e6, T = 1e4 K, 64 cells x 128 bins over "
                      "|x| <= 6 (a tau0)^(1/3), central source x = 0, 2^16 packets each, walked whole by rDDMC, "
                      "rDDMC on the efficient frequency grid (central bin 2 x_cw, unit wings), frequency-group "
                      "Monte Carlo (eq. 42) and continuous-frequency Monte Carlo on the same packet ids; "
-                     "value = rDDMC on the tau0 = 1e5 slab",
+                     "value = rDDMC on the tau0 = 1e5 slab (or the first method and slab asked for)",
          "methods": rows,
          "precision": "f32 walk, f64 tables (eq. 42 tables in f64), f64 clock, i64 tallies, Philox4x32-10"},
-        packet_steps_per_s=headline["rddmc"]["events_per_s"])
+        packet_steps_per_s=headline[lead]["events_per_s"])
     out["roofline"] = None   # a comparison of methods; the kernels' own rooflines are the other workloads'
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_1d(media.config_slab(), args.cpu_packets or 4096, args)
