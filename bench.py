@@ -23,7 +23,11 @@ Other workloads (``--workload``):
              T = 1e4 K, central source at x = 0), each walked whole on the same packet ids by
              rDDMC, rDDMC on the efficient frequency grid, frequency-group Monte Carlo (Sec. 5.3,
              eq. 42) and continuous-frequency Monte Carlo (the scattering-by-scattering reference);
-             the value is rDDMC's packets/s on the tau0 = 1e5 slab.
+             the value is rDDMC's packets/s on the tau0 = 1e5 slab;
+  census     the time-dependent estimators' cost: the tau0 = 1e5 slab (64 x 128, 2^16 packets)
+             walked whole by the pure 1D walk, by the hybrid 1D walk without estimators, and by
+             the hybrid walk with 16 census intervals (eq. 17's bin and path estimators and
+             eq. 18's sums), on the same packet ids.
 
 Prints one JSON line.  ``--gpus`` must be 1 (the path runs on one GPU).
 """
@@ -93,7 +97,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", choices=["cube", "sphere", "sphere-efficient", "surrogate", "sweep", "sweep-full",
-                                           "methods"], default="cube")
+                                           "methods", "census"], default="cube")
     ap.add_argument("--block-packets", type=int, default=0,
                     help="sphere: packets per step (0 = the whole 2^22-packet job)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -512,6 +516,55 @@ def bench_methods(args):
     return out
 
 
+def bench_census(args):
+    """The cost of the census estimators (eq. 17 bin and path, eq. 18) on the config slab: the
+    same 2^16 packet ids walked whole by the pure walk, by the hybrid walk (forced by a zero
+    emission window, which is the same flash) without estimators, and by the hybrid walk with
+    16 census intervals spanning 0..3 mean escape times.  The two hybrid legs draw the same
+    random words, so their escape tallies are identical."""
+    import numpy as np
+    import torch
+    from paper_1709_10187_amd import media, rddmc
+    m = media.config_slab()
+    n = int(m.n_packets)
+    legs, tmean = {}, None
+    for leg in ("pure", "hybrid", "census"):
+        mm = m
+        if leg != "pure":
+            mm = m.replace(src_t=np.array([[0.0, 0.0]]))
+        if leg == "census":
+            mm = mm.replace(census=np.linspace(0.0, 3.0 * tmean, 17))
+        prob = rddmc.Problem(mm)
+        torch.cuda.synchronize()
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record()
+        prob.run(seed=0)
+        stop.record()
+        torch.cuda.synchronize()
+        sec = start.elapsed_time(stop) / 1e3
+        r = prob.results()[0]
+        tmean = tmean or r.t_mean
+        legs[leg] = {"seconds": sec, "packets_per_s": n / sec, "steps_per_s": r.steps_total / sec,
+                     "steps_per_packet": r.steps_mean, "spectrum": r.spectrum.copy()}
+        log(f"census workload, {leg}: {sec:.3f} s, {n / sec:.4g} packets/s, {r.steps_total / sec:.4g} steps/s")
+        del prob
+    same = np.array_equal(legs["census"]["spectrum"], legs["hybrid"]["spectrum"])
+    for v in legs.values():
+        del v["spectrum"]
+    out = base_line(
+        args, legs["census"]["packets_per_s"], legs["census"]["seconds"], "f32",
+        {"workload": "static slab tau0 = 1e5, T = 1e4 K, 64 cells x 128 bins, 2^16 packets, walked whole by the "
+                     "pure 1D walk, the hybrid 1D walk without estimators and the hybrid walk with 16 census "
+                     "intervals over 0..3 mean escape times (eq. 17 bin and path, eq. 18); value = the census leg",
+         "legs": legs, "hybrid_spectra_identical": bool(same),
+         "census_cost": legs["hybrid"]["packets_per_s"] / legs["census"]["packets_per_s"]},
+        packet_steps_per_s=legs["census"]["steps_per_s"])
+    out["roofline"] = None   # the estimators' cost against the same walk without them
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_1d(media.config_slab(), args.cpu_packets or 4096, args)
+    return out
+
+
 def cpu_mcrt_slabs(args):
     """The oracle's continuous-frequency Monte Carlo (the 1D hybrid walker with every state thin)
     on the host's cores: 4096 packets of the tau0 = 1e3 slab and 1024 of the 1e4 slab of the
@@ -584,7 +637,7 @@ def main():
     torch.cuda.set_device(0)
     fn = {"cube": bench_cube, "sphere": bench_sphere, "sphere-efficient": lambda a: bench_sphere(a, efficient=True),
           "surrogate": bench_surrogate, "sweep": bench_sweep, "sweep-full": bench_sweep_full,
-          "methods": bench_methods}
+          "methods": bench_methods, "census": bench_census}
     print(json.dumps(fn[args.workload](args)), flush=True)
 
 

@@ -338,6 +338,7 @@ rddmc_status make_layout(const rddmc_batch *b, Layout &L)
         c.groups = (m.flags & RDDMC_FLAG_GROUPS) ? 1 : 0;
         c.dust_weight = (m.flags & RDDMC_FLAG_DUST_WEIGHT) ? 1 : 0;
         if (c.dust_weight) L.h.dust_weight1d = 1u;
+        if (m.n_census > 0) L.h.census1d = 1u;
         c.off_grp_prob = c.groups ? take(8ull * c.nb * c.nb) : 0;
         c.off_grp_alias = c.groups ? take(8ull * c.nb * c.nb) : 0;
         c.n_pix = m.geometry == RDDMC_CART3D

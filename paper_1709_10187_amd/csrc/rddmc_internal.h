@@ -130,7 +130,7 @@ struct alignas(16) DevHeader {
     uint64_t off_voigt;          // f32 [kVoigtN] (3D batches)
     uint64_t off_u0;             // f32 [kU0NA * kU0NX] (3D batches)
     uint32_t dust_weight1d;      // a cloud of the 1D batch carries continuous dust weights
-    uint32_t pad_h;
+    uint32_t census1d;           // a cloud of the 1D batch has census estimators
 };
 
 enum BuildError : uint32_t {

@@ -61,6 +61,10 @@ struct Pk1 {
     float x;
     double t;
     double lw;         // -ln(weight): optical depth of dust absorption so far (continuous weights)
+    uint64_t ck[4];    // census 'path' sums held by the packet: (interval, state) keys ...
+    uint64_t ca[4];    // ... and their fixed-point residences, added to the tallies on eviction
+    uint32_t cn;       // next way to evict (round robin)
+    int ci;            // first census time at or after the packet's clock (its clock only grows)
     uint64_t steps;
     uint32_t mcs, tomc, toddmc, refl;
     Rng r;
@@ -186,20 +190,56 @@ __device__ __forceinline__ double weight_integral(double a, double b, double t0,
     return ka > 0.0 ? wa * (-expm1(-ka * (b - a)) / ka) : wa * (b - a);
 }
 
+constexpr uint64_t kNoKey = ~0ull;
+
+// The 'path' estimator's sums go through a four-way cache in the packet: a walk returns to the
+// states it has just left (a frequency move and back), so most of its per-step residences add
+// to a held sum instead of a device atomic.  Integer sums make the tallies identical to adding
+// every residence at once, whatever the evictions.
+__device__ __forceinline__ void path_add(Pk1 &p, unsigned long long *__restrict__ wpath, uint64_t key, uint64_t v)
+{
+    bool hit = false;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        if (p.ck[q] == key) {
+            p.ca[q] += v;
+            hit = true;
+        }
+    if (hit) return;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        if ((uint32_t)q == p.cn) {
+            if (p.ck[q] != kNoKey && p.ca[q]) atomicAdd(&wpath[p.ck[q]], (unsigned long long)p.ca[q]);
+            p.ck[q] = key;
+            p.ca[q] = v;
+        }
+    p.cn = (p.cn + 1) & 3u;
+}
+
+__device__ __forceinline__ void path_flush(Pk1 &p, unsigned long long *__restrict__ wpath)
+{
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (p.ck[q] != kNoKey && p.ca[q]) atomicAdd(&wpath[p.ck[q]], (unsigned long long)p.ca[q]);
+        p.ck[q] = kNoKey;
+        p.ca[q] = 0;
+    }
+    p.cn = 0;
+}
+
 // The packet stays in state s over [t0, t1): census counts and residence times.  With
 // continuous dust weights (log-weight lw0 at t0, decay rate ka) the counts are the weights at
 // the census times and the residences their integrals (2^-24 units both).
 template <bool WGT>
-__device__ __forceinline__ void census_add(const DevCloud &c, const uint8_t *__restrict__ tb, unsigned long long *__restrict__ tally,
-                           int64_t s, double t0, double t1, double lw0, double ka)
+__device__ __forceinline__ void census_add(Pk1 &p, const DevCloud &c, const uint8_t *__restrict__ tb,
+                                           unsigned long long *__restrict__ tally, int64_t s, double t0, double t1,
+                                           double lw0, double ka)
 {
     const double *ct = reinterpret_cast<const double *>(tb + c.off_census);
     const int n = c.n_census;
-    int lo = 0, hi = n + 1;   // first census time >= t0
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (ct[mid] < t0) lo = mid + 1; else hi = mid;
-    }
+    int lo = p.ci;   // first census time >= t0: the packet's clock never goes back
+    while (lo <= n && ct[lo] < t0) ++lo;
+    p.ci = lo;
     unsigned long long *w = tally + c.tally_off;
     const uint64_t ns = c.n_states;
     for (int e = lo; e <= n && ct[e] < t1; ++e)
@@ -209,7 +249,7 @@ __device__ __forceinline__ void census_add(const DevCloud &c, const uint8_t *__r
         const double a0 = fmax(t0, ct[i]), b0 = fmin(t1, ct[i + 1]);
         if (b0 > a0) {
             const double r = (WGT && c.dust_weight) ? weight_integral(a0, b0, t0, lw0, ka) : b0 - a0;
-            atomicAdd(&w[c.census_path_off + (uint64_t)i * ns + s], (unsigned long long)rint(r * kPathFix));
+            path_add(p, w + c.census_path_off, (uint64_t)i * ns + s, (uint64_t)rint(r * kPathFix));
         }
     }
 }
@@ -253,7 +293,7 @@ __device__ __forceinline__ void escape_weighted(const DevCloud &c, unsigned long
     if (atomicAdd(&ww[2], a2) + a2 < a2) atomicAdd(&ww[3], 1ull);
 }
 
-template <bool WGT>
+template <bool WGT, bool CEN>
 __device__ __forceinline__ void finish1(Pk1 &p, const DevCloud &c, unsigned long long *__restrict__ tally, bool escaped, int row,
                         int slot, bool absorbed = false)
 {
@@ -273,6 +313,7 @@ __device__ __forceinline__ void finish1(Pk1 &p, const DevCloud &c, unsigned long
     } else {
         atomicAdd(&w[TW_CAPPED], 1ull);
     }
+    if (CEN && c.n_census > 0) path_flush(p, w + c.census_path_off);
     atomicAdd(&w[kTallyHeader + nspec + RDDMC_TIME_BINS + 2 + step_bin1(p.steps)], 1ull);
     atomicAdd(&w[TW_STEPS], (unsigned long long)p.steps);
     atomicMax(&w[TW_STEPS_MAX], (unsigned long long)p.steps);
@@ -291,7 +332,7 @@ __device__ __forceinline__ int neighbour1(const DevCloud &c, int cell, int f)
 }
 
 // One DDMC step of a packet in a thick state.
-template <bool SPH, bool WGT>
+template <bool SPH, bool WGT, bool CEN>
 __device__ __forceinline__ void ddmc_step1(Pk1 &p, const DevCloud &c, const uint8_t *__restrict__ tb, const McArgs &a,
                            unsigned long long *__restrict__ tally)
 {
@@ -303,13 +344,13 @@ __device__ __forceinline__ void ddmc_step1(Pk1 &p, const DevCloud &c, const uint
     // continuous dust weights: the interaction distance dl carries optical depth k_a dl
     const double ka = (WGT && c.dust_weight) ? reinterpret_cast<const double *>(tb + c.off_dust)[2 * p.cell] : 0.0;
     const double lw0 = p.lw;
-    if (c.n_census > 0) census_add<WGT>(c, tb, tally, s, p.t, p.t + dl, lw0, ka);
+    if (CEN && c.n_census > 0) census_add<WGT>(p, c, tb, tally, s, p.t, p.t + dl, lw0, ka);
     const double t0 = p.t;
     p.t += dl;
     if (WGT && c.dust_weight) {
         p.lw += ka * dl;
         if (p.lw > kLogWMin) {   // negligible weight: eliminated
-            finish1<WGT>(p, c, tally, false, 0, 0, true);
+            finish1<WGT, CEN>(p, c, tally, false, 0, 0, true);
             return;
         }
     }
@@ -340,7 +381,7 @@ __device__ __forceinline__ void ddmc_step1(Pk1 &p, const DevCloud &c, const uint
             absorb = (((uint64_t)ew << 32) | lo_word) >= A;
         }
         if (absorb) {
-            finish1<WGT>(p, c, tally, false, 0, 0, true);
+            finish1<WGT, CEN>(p, c, tally, false, 0, 0, true);
             return;
         }
     }
@@ -362,7 +403,7 @@ __device__ __forceinline__ void ddmc_step1(Pk1 &p, const DevCloud &c, const uint
     const int f = v >= reinterpret_cast<const uint32_t *>(tb + c.off_face_split)[s] ? 1 : 0;
     const double *kt = reinterpret_cast<const double *>(tb + c.off_k);
     const double dir = f ? 1.0 : -1.0;
-    if (c.n_census > 0) accel_add<WGT>(c, tb, tally, p.cell, t0, p.t, dir * kt[s], lw0, ka);   // outward leakage (eq. 18)
+    if (CEN && c.n_census > 0) accel_add<WGT>(c, tb, tally, p.cell, t0, p.t, dir * kt[s], lw0, ka);   // outward leakage (eq. 18)
     const float xin = bin_x(c, tb, p.j, uf(draw(p.r, a)));
     const int nbc = neighbour1(c, p.cell, f);
     const float4 *mcell = reinterpret_cast<const float4 *>(tb + c.off_mcell);
@@ -373,7 +414,7 @@ __device__ __forceinline__ void ddmc_step1(Pk1 &p, const DevCloud &c, const uint
         const float nu = n_dot_u<SPH>(mcell[2 * p.cell + 1].x, p.pos, p.n);
         if (nbc < 0) {
             const int slot = c.moving ? bin_of(c, tb, xin + nu) + 1 : p.j + 1;
-            finish1<WGT>(p, c, tally, true, SPH ? 0 : f, slot);
+            finish1<WGT, CEN>(p, c, tally, true, SPH ? 0 : f, slot);
             return;
         }
         const float4 m0 = mcell[2 * p.cell], m1 = mcell[2 * nbc];
@@ -409,12 +450,12 @@ __device__ __forceinline__ void ddmc_step1(Pk1 &p, const DevCloud &c, const uint
             ddmc_in = false;
         }
     }
-    if (c.n_census > 0 && ddmc_in)   // inward leakage into a DDMC state (eq. 18)
+    if (CEN && c.n_census > 0 && ddmc_in)   // inward leakage into a DDMC state (eq. 18)
         accel_add<WGT>(c, tb, tally, p.cell, t0, p.t, dir * kt[(int64_t)p.cell * nb + p.j], lw0, ka);
 }
 
 // One continuous-MC event (a scattering or a boundary crossing) of a packet in a thin state.
-template <bool SPH, bool WGT>
+template <bool SPH, bool WGT, bool CEN>
 __device__ __forceinline__ void mc_step1(Pk1 &p, const DevCloud &c, const uint8_t *__restrict__ tb, const McArgs &a,
                          unsigned long long *__restrict__ tally, const float *__restrict__ vtab,
                          const float *__restrict__ u0tab)
@@ -434,15 +475,15 @@ __device__ __forceinline__ void mc_step1(Pk1 &p, const DevCloud &c, const uint8_
     const float ds = -__logf(uf(draw(p.r, a))) / kx;
     const float u0 = n_dot_u<SPH>(uc, p.pos, p.n);
     const double fl = (double)fminf(ds, dwall);
-    if (c.n_census > 0) {
+    if (CEN && c.n_census > 0) {
         int jc = bin_of(c, tb, p.x);
         jc = jc < 0 ? 0 : (jc > c.nb - 1 ? c.nb - 1 : jc);
-        census_add<WGT>(c, tb, tally, (int64_t)p.cell * c.nb + jc, p.t, p.t + fl, p.lw, (double)m1c.z);
+        census_add<WGT>(p, c, tb, tally, (int64_t)p.cell * c.nb + jc, p.t, p.t + fl, p.lw, (double)m1c.z);
     }
     if (WGT && c.dust_weight) {
         p.lw += (double)m1c.z * fl;
         if (p.lw > kLogWMin) {   // negligible weight: eliminated
-            finish1<WGT>(p, c, tally, false, 0, 0, true);
+            finish1<WGT, CEN>(p, c, tally, false, 0, 0, true);
             return;
         }
     }
@@ -455,7 +496,7 @@ __device__ __forceinline__ void mc_step1(Pk1 &p, const DevCloud &c, const uint8_
         if (c.dusty) {   // which opacity interacted: dust absorption, dust scattering or Lya
             const float v = uf(draw(p.r, a)) * kx;
             if (v < kab) {
-                finish1<WGT>(p, c, tally, false, 0, 0, true);
+                finish1<WGT, CEN>(p, c, tally, false, 0, 0, true);
                 return;
             }
             if (v < kab + m1c.y) {   // dust: isotropic, coherent in the comoving frame
@@ -466,7 +507,7 @@ __device__ __forceinline__ void mc_step1(Pk1 &p, const DevCloud &c, const uint8_
         }
         float upar;
         if (!sample_upar(m0.y, p.x, u0tab, p.r, a, upar)) {
-            finish1<WGT>(p, c, tally, false, 0, 0);   // counted with the step-capped packets
+            finish1<WGT, CEN>(p, c, tally, false, 0, 0);   // counted with the step-capped packets
             return;
         }
         // perpendicular velocity in the scattering plane: sqrt(xc^2 - ln xi) cos(phi), a
@@ -503,7 +544,7 @@ __device__ __forceinline__ void mc_step1(Pk1 &p, const DevCloud &c, const uint8_
     if (SPH && c.moving) p.x += u0 - nu;
     const int nbc = neighbour1(c, p.cell, fexit);
     if (nbc < 0) {
-        finish1<WGT>(p, c, tally, true, SPH ? 0 : fexit, bin_of(c, tb, p.x + nu) + 1);
+        finish1<WGT, CEN>(p, c, tally, true, SPH ? 0 : fexit, bin_of(c, tb, p.x + nu) + 1);
         return;
     }
     const float4 m1 = mcell[2 * nbc];
@@ -539,7 +580,7 @@ __device__ __forceinline__ void mc_step1(Pk1 &p, const DevCloud &c, const uint8_
 // (eq. 14) plus any dust; a scattering takes the outgoing bin from row j of the cloud's alias
 // table of eq. 42 (two 32-bit words) and an isotropic direction.  Boundaries as in mc_step1,
 // with the bin unchanged across faces (no velocities, one temperature).
-template <bool SPH, bool WGT>
+template <bool SPH, bool WGT, bool CEN>
 __device__ __forceinline__ void grp_step1(Pk1 &p, const DevCloud &c, const uint8_t *__restrict__ tb, const McArgs &a,
                           unsigned long long *__restrict__ tally)
 {
@@ -560,11 +601,11 @@ __device__ __forceinline__ void grp_step1(Pk1 &p, const DevCloud &c, const uint8
     const float kx = kl + ks + ka;
     const float ds = -__logf(uf(draw(p.r, a))) / kx;
     const double fl = (double)fminf(ds, dwall);
-    if (c.n_census > 0) census_add<WGT>(c, tb, tally, s, p.t, p.t + fl, p.lw, (double)kd);
+    if (CEN && c.n_census > 0) census_add<WGT>(p, c, tb, tally, s, p.t, p.t + fl, p.lw, (double)kd);
     if (WGT && c.dust_weight) {
         p.lw += (double)kd * fl;
         if (p.lw > kLogWMin) {   // negligible weight: eliminated
-            finish1<WGT>(p, c, tally, false, 0, 0, true);
+            finish1<WGT, CEN>(p, c, tally, false, 0, 0, true);
             return;
         }
     }
@@ -577,7 +618,7 @@ __device__ __forceinline__ void grp_step1(Pk1 &p, const DevCloud &c, const uint8
         if (c.dusty) {
             const float v = uf(draw(p.r, a)) * kx;
             if (v < ka) {
-                finish1<WGT>(p, c, tally, false, 0, 0, true);
+                finish1<WGT, CEN>(p, c, tally, false, 0, 0, true);
                 return;
             }
             if (v < ka + ks) {   // dust: isotropic, the bin unchanged
@@ -612,7 +653,7 @@ __device__ __forceinline__ void grp_step1(Pk1 &p, const DevCloud &c, const uint8
     p.t += (double)dwall;
     const int nbc = neighbour1(c, p.cell, fexit);
     if (nbc < 0) {
-        finish1<WGT>(p, c, tally, true, SPH ? 0 : fexit, p.j + 1);
+        finish1<WGT, CEN>(p, c, tally, true, SPH ? 0 : fexit, p.j + 1);
         return;
     }
     if (reinterpret_cast<const uint4 *>(tb + c.off_hot)[(int64_t)nbc * c.nb + p.j].w & kFlagThick) {
@@ -645,7 +686,7 @@ __device__ __forceinline__ uint64_t shfl64(uint64_t v, int src)
     return ((uint64_t)hi << 32) | lo;
 }
 
-template <bool SPH, bool SINGLE, bool WGT>
+template <bool SPH, bool SINGLE, bool WGT, bool CEN>
 __global__ __launch_bounds__(256) void walk1dh(const uint8_t *__restrict__ tb, McArgs a,
                                                unsigned long long *__restrict__ tally,
                                                unsigned long long *__restrict__ work)
@@ -669,6 +710,13 @@ __global__ __launch_bounds__(256) void walk1dh(const uint8_t *__restrict__ tb, M
     p.x = 0.f;
     p.t = 0.0;
     p.lw = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        p.ck[q] = kNoKey;
+        p.ca[q] = 0;
+    }
+    p.cn = 0;
+    p.ci = 0;
     p.steps = 0;
     p.mcs = p.tomc = p.toddmc = p.refl = 0u;
     p.r = Rng{0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 4u, false, 0u, 0u, 0u, 0u};
@@ -714,6 +762,7 @@ __global__ __launch_bounds__(256) void walk1dh(const uint8_t *__restrict__ tb, M
                         p.j = (int)(st - (int64_t)p.cell * c.nb);
                         p.t = 0.0;
                         p.lw = 0.0;
+                        p.ci = 0;
                         if (c.off_src_t) {   // emission uniform over the source's window
                             const double *tw = reinterpret_cast<const double *>(tb + c.off_src_t) + 2 * lo;
                             p.t = tw[0] + (tw[1] - tw[0]) * ud(draw(p.r, a));
@@ -741,7 +790,7 @@ __global__ __launch_bounds__(256) void walk1dh(const uint8_t *__restrict__ tb, M
         // one event; every packet's own sequence of steps and draws is unchanged by this.
         const DevCloud &c = clouds[SINGLE ? 0 : p.cl];
         for (int k = 0; k < a.chunk; ++k) {
-            if (p.active && p.steps >= a.max_steps) finish1<WGT>(p, c, tally, false, 0, 0);
+            if (p.active && p.steps >= a.max_steps) finish1<WGT, CEN>(p, c, tally, false, 0, 0);
             const uint64_t bm = __ballot(p.active && p.mc);
             const uint64_t bd = __ballot(p.active && !p.mc);
             if (!(bm | bd)) break;
@@ -752,14 +801,14 @@ __global__ __launch_bounds__(256) void walk1dh(const uint8_t *__restrict__ tb, M
                 ++p.steps;
                 if (mc_pass) {
                     if (c.groups)
-                        grp_step1<SPH, WGT>(p, c, tb, a, tally);
+                        grp_step1<SPH, WGT, CEN>(p, c, tb, a, tally);
                     else
-                        mc_step1<SPH, WGT>(p, c, tb, a, tally, vtab, u0tab);
+                        mc_step1<SPH, WGT, CEN>(p, c, tb, a, tally, vtab, u0tab);
                 } else {
-                    ddmc_step1<SPH, WGT>(p, c, tb, a, tally);
+                    ddmc_step1<SPH, WGT, CEN>(p, c, tb, a, tally);
                     if (p.active && !p.mc && p.steps < a.max_steps) {
                         ++p.steps;
-                        ddmc_step1<SPH, WGT>(p, c, tb, a, tally);
+                        ddmc_step1<SPH, WGT, CEN>(p, c, tb, a, tally);
                     }
                 }
             }
@@ -797,23 +846,27 @@ hipError_t launch_walk1dh(const uint8_t *d_tables, const DevHeader &h, const rdd
     reset_queue1<<<1, 64, 0, s>>>(d_work);
     const bool sph = h.geometry == RDDMC_SPHERE;
     const bool single = h.n_clouds == 1;
-    // batches with continuous dust weights take their own instantiation, so that the others
-    // keep the registers (and occupancy) of a walk without them
-    auto go = [&](auto wgt) {
-        constexpr bool W = decltype(wgt)::value;
+    // batches with continuous dust weights or census estimators take instantiations of their
+    // own, so that the others keep the registers (and occupancy) of a walk without them
+    auto go = [&](auto wgt, auto cen) {
+        constexpr bool W = decltype(wgt)::value, C = decltype(cen)::value;
         if (sph && single)
-            walk1dh<true, true, W><<<(unsigned)grid, block, 0, s>>>(d_tables, a, d_tally, d_work);
+            walk1dh<true, true, W, C><<<(unsigned)grid, block, 0, s>>>(d_tables, a, d_tally, d_work);
         else if (sph)
-            walk1dh<true, false, W><<<(unsigned)grid, block, 0, s>>>(d_tables, a, d_tally, d_work);
+            walk1dh<true, false, W, C><<<(unsigned)grid, block, 0, s>>>(d_tables, a, d_tally, d_work);
         else if (single)
-            walk1dh<false, true, W><<<(unsigned)grid, block, 0, s>>>(d_tables, a, d_tally, d_work);
+            walk1dh<false, true, W, C><<<(unsigned)grid, block, 0, s>>>(d_tables, a, d_tally, d_work);
         else
-            walk1dh<false, false, W><<<(unsigned)grid, block, 0, s>>>(d_tables, a, d_tally, d_work);
+            walk1dh<false, false, W, C><<<(unsigned)grid, block, 0, s>>>(d_tables, a, d_tally, d_work);
     };
-    if (h.dust_weight1d)
-        go(std::true_type{});
+    if (h.dust_weight1d && h.census1d)
+        go(std::true_type{}, std::true_type{});
+    else if (h.dust_weight1d)
+        go(std::true_type{}, std::false_type{});
+    else if (h.census1d)
+        go(std::false_type{}, std::true_type{});
     else
-        go(std::false_type{});
+        go(std::false_type{}, std::false_type{});
     return hipGetLastError();
 }
 
