@@ -545,7 +545,7 @@ def bench_census(args):
         r = prob.results()[0]
         tmean = tmean or r.t_mean
         legs[leg] = {"seconds": sec, "packets_per_s": n / sec, "steps_per_s": r.steps_total / sec,
-                     "steps_per_packet": r.steps_mean, "spectrum": r.spectrum.copy()}
+                     "steps_per_packet": r.steps_mean, "steps_max": int(r.steps_max), "spectrum": r.spectrum.copy()}
         log(f"census workload, {leg}: {sec:.3f} s, {n / sec:.4g} packets/s, {r.steps_total / sec:.4g} steps/s")
         del prob
     same = np.array_equal(legs["census"]["spectrum"], legs["hybrid"]["spectrum"])
