@@ -78,6 +78,36 @@ def test_tables_of_an_efficient_grid():
         assert abs(prob[jp, j] - want) <= 1e-7 * want + 1e-18, (jp, j, prob[jp, j], want)
 
 
+def test_tables_of_a_cold_fine_grid():
+    """T = 100 K (a = 4.7e-3) on 201 bins of width 0.2 over |x| <= 20, finer than the unit
+    width of wing redistribution: rows sum to 1, the mirror symmetry holds, and core, wing and
+    edge elements match O6."""
+    a = media._a_of_T(1e2)
+    m = media.slab(3e2, 1e2, 8, 201, x_max=20.0, tau_threshold=THIN, flags=G)
+    prob, _ = rddmc.Problem(m).read_redistribution(0)
+    np.testing.assert_allclose(prob.sum(axis=1), 1.0, atol=1e-8)
+    np.testing.assert_allclose(prob, prob[::-1, ::-1], rtol=1e-9, atol=1e-20)
+    for jp, j in [(100, 100), (100, 101), (100, 96), (180, 178), (0, 0)]:
+        want = rd.group_probability(m.bin_edges, a, jp, j, epsrel=1e-9)
+        assert abs(prob[jp, j] - want) <= 1e-7 * want + 1e-18, (jp, j, prob[jp, j], want)
+
+
+def test_table_build_of_a_wide_grid():
+    """1024 bins of width 0.078 over |x| <= 40 (the widest grids of the batched sweep): rows sum
+    to 1; the build time is printed (pairs of bins more than 13 apart are skipped)."""
+    import time
+    import torch
+    m = media.slab(3e2, 1e4, 4, 1024, x_max=40.0, tau_threshold=THIN, flags=G)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    p = rddmc.Problem(m)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prob, _ = p.read_redistribution(0)
+    print(f"[groups] 1024-bin tables built in {dt:.2f} s", flush=True)
+    np.testing.assert_allclose(prob.sum(axis=1), 1.0, atol=1e-8)
+
+
 def test_unsupported_clouds_are_refused():
     for bad in (CASES["slab_groups"].replace(vel=np.linspace(-5, 5, 8)),
                 CASES["slab_groups"].replace(temp=np.linspace(1e4, 2e4, 8)),
