@@ -22,7 +22,8 @@ Other workloads (``--workload``):
   methods    static uniform slabs (tau0 = 1e3 .. 1e6, 64 cells x 128 bins over |x| <= 6 (a tau0)^(1/3),
              T = 1e4 K, central source at x = 0), each walked whole on the same packet ids by
              rDDMC, rDDMC on the efficient frequency grid, frequency-group Monte Carlo (Sec. 5.3,
-             eq. 42) and continuous-frequency Monte Carlo (the scattering-by-scattering reference);
+             eq. 42), continuous-frequency Monte Carlo (the scattering-by-scattering reference) and
+             the latter with core-skipping (x_crit = 3, the kind of MCRT the paper compares with);
              the value is rDDMC's packets/s on the tau0 = 1e5 slab;
   census     the time-dependent estimators' cost: the tau0 = 1e5 slab (64 x 128, 2^16 packets)
              walked whole by the pure 1D walk, by the hybrid 1D walk without estimators, and by
@@ -116,7 +117,7 @@ def parse():
     ap.add_argument("--sweep-scale", type=float, default=1.0, help="sweep-full: fraction of the stated packet counts")
     ap.add_argument("--methods-tau0", type=float, nargs="*", default=[1e3, 1e4, 1e5, 1e6],
                     help="methods: the slabs' line-centre depths")
-    ap.add_argument("--methods-legs", nargs="*", default=["rddmc", "rddmc_efficient", "groups", "mcrt"],
+    ap.add_argument("--methods-legs", nargs="*", default=["rddmc", "rddmc_efficient", "groups", "mcrt", "mcrt_cs"],
                     help="methods: which methods walk each slab")
     return ap.parse_args()
 
@@ -468,6 +469,9 @@ def bench_methods(args):
             eff = None
         legs["groups"] = base.replace(tau_threshold=media.ALL_THIN, flags=media.GROUP_MC)
         legs["mcrt"] = base.replace(tau_threshold=media.ALL_THIN)
+        # continuous MC with core-skipping (the kind of MCRT the paper compares with): a photon
+        # scattered at |x| < 3 takes the atom's perpendicular speed from the Maxwellian above 3
+        legs["mcrt_cs"] = base.replace(tau_threshold=media.ALL_THIN, x_crit=3.0)
         legs = {k: v for k, v in legs.items() if k in args.methods_legs}
         row = {"tau0": tau0, "dx": float(base.bin_edges[1] - base.bin_edges[0])}
         spectra = {}
@@ -490,21 +494,26 @@ def bench_methods(args):
         if eff is not None:
             row["efficient_bins"] = len(eff) - 1
         if "mcrt" in row:
-            for leg in ("rddmc", "rddmc_efficient", "groups"):
+            for leg in ("rddmc", "rddmc_efficient", "groups", "mcrt_cs"):
                 if leg in row:
                     row[f"speedup_{leg}_vs_mcrt"] = row[leg]["packets_per_s"] / row["mcrt"]["packets_per_s"]
                     if leg != "rddmc_efficient":
                         row[f"L1_{leg}_vs_mcrt"] = float(np.abs(spectra[leg] - spectra["mcrt"]).sum())
+        if "mcrt_cs" in row:
+            for leg in ("rddmc", "rddmc_efficient", "groups"):
+                if leg in row:
+                    row[f"speedup_{leg}_vs_mcrt_cs"] = row[leg]["packets_per_s"] / row["mcrt_cs"]["packets_per_s"]
         rows.append(row)
         if headline is None or tau0 == 1e5:
             headline = row
-    lead = next(leg for leg in ("rddmc", "rddmc_efficient", "groups", "mcrt") if leg in headline)
+    lead = next(leg for leg in ("rddmc", "rddmc_efficient", "groups", "mcrt", "mcrt_cs") if leg in headline)
     out = base_line(
         args, headline[lead]["packets_per_s"], n / headline[lead]["packets_per_s"], "f32",
         {"workload": "static uniform slabs tau0 = 1e3..1e6, T = 1e4 K, 64 cells x 128 bins over "
                      "|x| <= 6 (a tau0)^(1/3), central source x = 0, 2^16 packets each, walked whole by rDDMC, "
                      "rDDMC on the efficient frequency grid (central bin 2 x_cw, unit wings), frequency-group "
-                     "Monte Carlo (eq. 42) and continuous-frequency Monte Carlo on the same packet ids; "
+                     "Monte Carlo (eq. 42), continuous-frequency Monte Carlo, and the latter with core-skipping "
+                     "(x_crit = 3) on the same packet ids; "
                      "value = rDDMC on the tau0 = 1e5 slab (or the first method and slab asked for)",
          "methods": rows,
          "precision": "f32 walk, f64 tables (eq. 42 tables in f64), f64 clock, i64 tallies, Philox4x32-10"},
