@@ -101,6 +101,18 @@ def test_frequency_group_clouds():
     assert ei.value.status == -3
 
 
+def test_dust_weight_clouds():
+    """Continuous dust weights (Sec. 2.4) add the weighted tally block: w t and w t^2 as 128-bit
+    sums and the weighted and squared-weight spectra; they need the absorption coefficients."""
+    m = media.slab(1e3, 1e4, 8, 16).replace(dust_abs=np.full(8, 0.5), dust_sca=np.full(8, 0.5))
+    w = m.replace(flags=media.DUST_WEIGHT)
+    extra = 8 * (4 + 2 * 2 * (16 + 2))
+    assert rddmc.tally_bytes(rddmc.Batch([w])) == rddmc.tally_bytes(rddmc.Batch([m])) + extra
+    with pytest.raises(rddmc.RddmcError) as ei:
+        rddmc.table_bytes(rddmc.Batch([w.replace(dust_abs=None)]))
+    assert ei.value.status == -1
+
+
 def test_oracle_philox_known_answers():
     g = json.load(open(os.path.join(ROOT, "tests", "golden", "philox4x32_10_kat.json")))
     for v in g["vectors"]:
