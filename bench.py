@@ -111,6 +111,12 @@ def parse():
     ap.add_argument("--tail-lanes", type=int, default=0,
                     help="1D: hand a wave's packets to the cooperative walk at <= this many (0 = default)")
     ap.add_argument("--surrogate-packets", type=int, default=2048, help="packets per cloud, surrogate workload")
+    ap.add_argument("--train-per-probe", type=int, default=0,
+                    help="surrogate: training samples per probe medium (0 = the library's recipe)")
+    ap.add_argument("--train-epochs", type=int, default=0, help="surrogate: training epochs (0 = the recipe)")
+    ap.add_argument("--train-step-budget", type=float, default=0.0,
+                    help="surrogate: longest expected sub-walk run as a walk; longer ones draw from the exact "
+                         "in-cell law (0 = the recipe)")
     ap.add_argument("--exit-kernel", action="store_true",
                     help="sphere workloads: walk with the exact per-cell exit kernel (built untimed)")
     ap.add_argument("--ek-min-steps", type=float, default=64.0, help="exit-kernel window: shortest expected sub-walk")
@@ -400,24 +406,52 @@ def bench_sweep_full(args):
     return out
 
 
+def spectrum_agreement(ra, rb, n_groups=40):
+    """Two escape spectra of the same cloud (surrogate and plain legs) on at most n_groups
+    groups of adjacent bins: their L1 distance and the L1 that Monte Carlo noise alone gives
+    two independent samples of these sizes (half-normal mean of each group's difference)."""
+    import numpy as np
+    a = np.asarray(ra.spectrum, dtype=np.float64).sum(axis=0)
+    b = np.asarray(rb.spectrum, dtype=np.float64).sum(axis=0)
+    k = max(1, a.size // n_groups)
+    a = np.add.reduceat(a, np.arange(0, a.size, k))
+    b = np.add.reduceat(b, np.arange(0, b.size, k))
+    na, nb = a.sum(), b.sum()
+    p = (a + b) / (na + nb)
+    l1 = float(np.abs(a / na - b / nb).sum())
+    noise = float((np.sqrt(2.0 / np.pi) * np.sqrt(p * (1.0 - p) * (1.0 / na + 1.0 / nb))).sum())
+    return l1, noise
+
+
 def bench_surrogate(args):
     """Learned escape surrogate against plain rDDMC: the same clouds, the same packet ids."""
     import torch
     from paper_1709_10187_amd import media, rddmc
     from paper_1709_10187_amd import surrogate as sg
     dom, use = sg.train_domain(), sg.use_domain()
+    per_probe = args.train_per_probe or sg.TRAIN_PER_PROBE
+    epochs = args.train_epochs or sg.TRAIN_EPOCHS
+    budget = args.train_step_budget or sg.TRAIN_STEP_BUDGET
     t0 = time.perf_counter()
     probes = sg.sample_probes(sg.TRAIN_PROBES, dom, seed=11)
-    log(f"surrogate: {sg.TRAIN_PROBES} x {sg.TRAIN_PER_PROBE} samples (sub-walks and exact in-cell laws)")
-    data = sg.generate_mixed(probes, sg.TRAIN_PER_PROBE, dom, seed=12, step_budget=sg.TRAIN_STEP_BUDGET)
+    log(f"surrogate: {sg.TRAIN_PROBES} x {per_probe} samples (sub-walks up to {budget:g} expected steps, "
+        f"the exact in-cell law above)")
+    data = sg.generate_mixed(probes, per_probe, dom, seed=12, step_budget=budget)
     torch.cuda.synchronize()
     t_data = time.perf_counter() - t0
+    n_walked = int((data.steps > 0).sum())
+    log(f"surrogate: {data.n} samples in {t_data:.1f} s ({n_walked} walked)")
+    held = sg.generate_mixed(sg.sample_probes(512, dom, seed=13), 128, dom, seed=14, step_budget=budget)
     net = rddmc.Mdn(max_batch=4096, seed=0)
     t1 = time.perf_counter()
-    log(f"surrogate: training on {data.n} samples")
-    hist = sg.train(net, data, epochs=sg.TRAIN_EPOCHS, lr=2e-3, lr_final=1e-4)
+    log(f"surrogate: training on {data.n} samples, {epochs} epochs")
+    hist = sg.train(net, data, epochs=epochs, lr=2e-3, lr_final=1e-4,
+                    log=log if data.n * epochs > (1 << 26) else None)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t1
+    nll_held = sg.mean_nll(net, held)
+    log(f"surrogate: trained in {t_train:.1f} s; final training NLL {hist[-1]:.4f}, held-out NLL {nll_held:.4f} "
+        f"({held.n} samples of 512 other probe media)")
     clouds = [media.sweep_cloud_medium(c) for c in media.sweep_parameters()]
     ids = [i for i in SURROGATE_CLOUDS if sg.window(clouds[i], use)[1] >= sg.window(clouds[i], use)[0]]
     meds = [clouds[i].with_packets(args.surrogate_packets) for i in ids]
@@ -433,6 +467,10 @@ def bench_surrogate(args):
     rp = plain.results()
     ns, npl = sum(r.launched for r in rs), sum(r.launched for r in rp)
     v_s, v_p = ns / ts, npl / tp
+    agree = [spectrum_agreement(a, b) for a, b in zip(rs, rp)]
+    l1s = [a for a, _ in agree]
+    noise = [b for _, b in agree]
+    log(f"surrogate vs plain spectra (40 groups): mean L1 {sum(l1s) / len(l1s):.4f}, noise {sum(noise) / len(noise):.4f}")
     out = base_line(
         args, v_s, ts, "bf16 network (f32 accumulate), f32 walk",
         {"workload": f"{len(ids)} sweep clouds with cells in the surrogate's domain (used at tau_c {use.tau_min:g}-"
@@ -443,7 +481,11 @@ def bench_surrogate(args):
          "surrogate_calls_per_packet": sum(r.surrogate_calls for r in rs) / ns,
          "steps_per_packet_surrogate": sum(r.steps_total for r in rs) / ns,
          "steps_per_packet_plain": sum(r.steps_total for r in rp) / npl,
-         "data_s": t_data, "train_s": t_train, "train_samples": data.n, "final_nll": hist[-1]},
+         "data_s": t_data, "train_s": t_train, "train_samples": data.n, "walked_samples": n_walked,
+         "train_epochs": epochs, "step_budget": budget, "final_nll": hist[-1], "heldout_nll": nll_held,
+         "spectrum_l1_vs_plain_40_groups": {"mean": sum(l1s) / len(l1s), "max": max(l1s),
+                                            "noise_mean": sum(noise) / len(noise),
+                                            "max_ratio_to_noise": max(a / b for a, b in agree)}},
         plain_packets_per_s=v_p, speedup=v_s / v_p)
     out["roofline"] = None
     return out

@@ -27,13 +27,13 @@ from . import media, rddmc
 _A_1E4 = 4.702e-4
 _VTH_1E4 = 12.85
 
-# Training recipe: probe media, samples per probe, epochs (Adam, cosine-decayed rate), the step
-# budget above which a probe's samples come from the exact in-cell law instead of run
-# sub-walks.
+# Training recipe: probe media, samples per probe (8192 x 12208 = 1.0e8 samples), epochs
+# (Adam, cosine-decayed rate), the step budget above which a probe's samples come from the
+# exact in-cell law instead of run sub-walks (about 38 % of the samples are run sub-walks).
 TRAIN_PROBES = 8192
-TRAIN_PER_PROBE = 128
-TRAIN_EPOCHS = 40
-TRAIN_STEP_BUDGET = 2.0e6
+TRAIN_PER_PROBE = 12208
+TRAIN_EPOCHS = 4
+TRAIN_STEP_BUDGET = 2.0e5
 
 
 @dataclasses.dataclass
@@ -263,6 +263,17 @@ def train(net: rddmc.Mdn, data: Data, epochs=30, batch=4096, lr=2e-3, lr_final=2
         if log:
             log(f"epoch {ep}: loss {hist[-1]:.4f}")
     return hist
+
+
+def mean_nll(net: rddmc.Mdn, data: Data, batch=4096) -> float:
+    """Mean negative log-likelihood of the network over a data set (in minibatches; the
+    parameters are left unchanged, the gradient slot is overwritten)."""
+    import torch
+    acc = torch.zeros(1, dtype=torch.float64, device="cuda")
+    for a in range(0, data.n, batch):
+        b = min(data.n, a + batch)
+        acc += net.loss_grad(data.x[a:b].contiguous(), data.y[a:b].contiguous()).double() * (b - a)
+    return float(acc.cpu()[0]) / max(data.n, 1)
 
 
 class Attached:

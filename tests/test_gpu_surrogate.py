@@ -136,12 +136,12 @@ def _mixture_sample(o, n, rng):
 
 def test_training_converged(trained):
     """The final epoch's mean loss is at least 1 nat below the untrained network's loss on the
-    data (the reference: an epoch's mean already contains that epoch's learning), and the
-    last epochs are flat."""
+    data (the reference: an epoch's mean already contains that epoch's learning), no epoch's
+    loss rises by more than 0.02, and the last two differ by less than 0.02."""
     _, hist = trained
     loss0, ep = hist[0], hist[1:]
     assert ep[-1] < loss0 - 1.0
-    assert all(b <= a + 0.02 for a, b in zip(ep[5:], ep[6:]))
+    assert all(b <= a + 0.02 for a, b in zip(ep, ep[1:]))
     assert abs(ep[-1] - ep[-2]) < 0.02
 
 
