@@ -121,6 +121,8 @@ def parse():
                     help="sphere workloads: walk with the exact per-cell exit kernel (built untimed)")
     ap.add_argument("--ek-min-steps", type=float, default=64.0, help="exit-kernel window: shortest expected sub-walk")
     ap.add_argument("--sweep-scale", type=float, default=1.0, help="sweep-full: fraction of the stated packet counts")
+    ap.add_argument("--census-packets", type=int, default=0,
+                    help="census: packets per leg (0 = the slab's 2^16)")
     ap.add_argument("--methods-tau0", type=float, nargs="*", default=[1e3, 1e4, 1e5, 1e6],
                     help="methods: the slabs' line-centre depths")
     ap.add_argument("--methods-legs", nargs="*", default=["rddmc", "rddmc_efficient", "groups", "mcrt", "mcrt_cs"],
@@ -569,7 +571,7 @@ def bench_methods(args):
 
 def bench_census(args):
     """The cost of the census estimators (eq. 17 bin and path, eq. 18) on the config slab: the
-    same 2^16 packet ids walked whole by the pure walk, by the hybrid walk (forced by a zero
+    same packet ids (2^16 unless --census-packets) walked whole by the pure walk, by the hybrid walk (forced by a zero
     emission window, which is the same flash) without estimators, and by the hybrid walk with
     16 census intervals spanning 0..3 mean escape times.  The two hybrid legs draw the same
     random words, so their escape tallies are identical."""
@@ -577,6 +579,8 @@ def bench_census(args):
     import torch
     from paper_1709_10187_amd import media, rddmc
     m = media.config_slab()
+    if args.census_packets:
+        m = m.with_packets(args.census_packets)
     n = int(m.n_packets)
     legs, tmean = {}, None
     for leg in ("pure", "hybrid", "census"):
@@ -604,7 +608,7 @@ def bench_census(args):
         del v["spectrum"]
     out = base_line(
         args, legs["census"]["packets_per_s"], legs["census"]["seconds"], "f32",
-        {"workload": "static slab tau0 = 1e5, T = 1e4 K, 64 cells x 128 bins, 2^16 packets, walked whole by the "
+        {"workload": f"static slab tau0 = 1e5, T = 1e4 K, 64 cells x 128 bins, {n} packets, walked whole by the "
                      "pure 1D walk, the hybrid 1D walk without estimators and the hybrid walk with 16 census "
                      "intervals over 0..3 mean escape times (eq. 17 bin and path, eq. 18); value = the census leg",
          "legs": legs, "hybrid_spectra_identical": bool(same),
