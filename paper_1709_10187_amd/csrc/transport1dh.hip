@@ -61,9 +61,7 @@ struct Pk1 {
     float x;
     double t;
     double lw;         // -ln(weight): optical depth of dust absorption so far (continuous weights)
-    uint64_t ck[4];    // census 'path' sums held by the packet: (interval, state) keys ...
-    uint64_t ca[4];    // ... and their fixed-point residences, added to the tallies on eviction
-    uint32_t cn;       // next way to evict (round robin)
+    uint32_t cn;       // next way of the packet's census path cache to evict (round robin)
     int ci;            // first census time at or after the packet's clock (its clock only grows)
     uint64_t steps;
     uint32_t mcs, tomc, toddmc, refl;
@@ -191,38 +189,52 @@ __device__ __forceinline__ double weight_integral(double a, double b, double t0,
 }
 
 constexpr uint64_t kNoKey = ~0ull;
+constexpr int kWays = 8;         // ways of a lane's census path cache
+constexpr int kBlockMax = 256;   // lanes per block of the walk
 
-// The 'path' estimator's sums go through a four-way cache in the packet: a walk returns to the
-// states it has just left (a frequency move and back), so most of its per-step residences add
-// to a held sum instead of a device atomic.  Integer sums make the tallies identical to adding
-// every residence at once, whatever the evictions.
+// The 'path' estimator's sums go through an eight-way cache per lane, held in LDS (way-major,
+// so a wave's accesses to one way are 64 consecutive words): a walk returns to the states it
+// has just left (a frequency move and back), so most of its per-step residences add to a held
+// sum instead of a device atomic.  Integer sums make the tallies identical to adding every
+// residence at once, whatever the evictions.  Each lane touches only its own slots.
+__shared__ uint64_t s_path_key[kWays * kBlockMax];
+__shared__ uint64_t s_path_sum[kWays * kBlockMax];
+
+__device__ __forceinline__ void path_init()
+{
+#pragma unroll
+    for (int q = 0; q < kWays; ++q) {
+        s_path_key[q * kBlockMax + threadIdx.x] = kNoKey;
+        s_path_sum[q * kBlockMax + threadIdx.x] = 0ull;
+    }
+}
+
 __device__ __forceinline__ void path_add(Pk1 &p, unsigned long long *__restrict__ wpath, uint64_t key, uint64_t v)
 {
-    bool hit = false;
+    const int l = threadIdx.x;
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-        if (p.ck[q] == key) {
-            p.ca[q] += v;
-            hit = true;
+    for (int q = 0; q < kWays; ++q)
+        if (s_path_key[q * kBlockMax + l] == key) {
+            s_path_sum[q * kBlockMax + l] += v;
+            return;
         }
-    if (hit) return;
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-        if ((uint32_t)q == p.cn) {
-            if (p.ck[q] != kNoKey && p.ca[q]) atomicAdd(&wpath[p.ck[q]], (unsigned long long)p.ca[q]);
-            p.ck[q] = key;
-            p.ca[q] = v;
-        }
-    p.cn = (p.cn + 1) & 3u;
+    const int e = (int)p.cn * kBlockMax + l;
+    const uint64_t k0 = s_path_key[e], v0 = s_path_sum[e];
+    if (k0 != kNoKey && v0) atomicAdd(&wpath[k0], (unsigned long long)v0);
+    s_path_key[e] = key;
+    s_path_sum[e] = v;
+    p.cn = (p.cn + 1) & (kWays - 1);
 }
 
 __device__ __forceinline__ void path_flush(Pk1 &p, unsigned long long *__restrict__ wpath)
 {
+    const int l = threadIdx.x;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        if (p.ck[q] != kNoKey && p.ca[q]) atomicAdd(&wpath[p.ck[q]], (unsigned long long)p.ca[q]);
-        p.ck[q] = kNoKey;
-        p.ca[q] = 0;
+    for (int q = 0; q < kWays; ++q) {
+        const uint64_t k0 = s_path_key[q * kBlockMax + l], v0 = s_path_sum[q * kBlockMax + l];
+        if (k0 != kNoKey && v0) atomicAdd(&wpath[k0], (unsigned long long)v0);
+        s_path_key[q * kBlockMax + l] = kNoKey;
+        s_path_sum[q * kBlockMax + l] = 0ull;
     }
     p.cn = 0;
 }
@@ -710,11 +722,7 @@ __global__ __launch_bounds__(256) void walk1dh(const uint8_t *__restrict__ tb, M
     p.x = 0.f;
     p.t = 0.0;
     p.lw = 0.0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        p.ck[q] = kNoKey;
-        p.ca[q] = 0;
-    }
+    if (CEN) path_init();
     p.cn = 0;
     p.ci = 0;
     p.steps = 0;
