@@ -63,6 +63,7 @@ struct Pk1 {
     double lw;         // -ln(weight): optical depth of dust absorption so far (continuous weights)
     uint32_t cn;       // next way of the packet's census path cache to evict (round robin)
     int ci;            // first census time at or after the packet's clock (its clock only grows)
+    double tn;         // that census time (-inf until the first full update)
     uint64_t steps;
     uint32_t mcs, tomc, toddmc, refl;
     Rng r;
@@ -247,13 +248,22 @@ __device__ __forceinline__ void census_add(Pk1 &p, const DevCloud &c, const uint
                                            unsigned long long *__restrict__ tally, int64_t s, double t0, double t1,
                                            double lw0, double ka)
 {
-    const double *ct = reinterpret_cast<const double *>(tb + c.off_census);
     const int n = c.n_census;
+    if (p.ci > n) return;   // past the last census time: nothing to count
+    unsigned long long *w = tally + c.tally_off;
+    const uint64_t ns = c.n_states;
+    if (t1 <= p.tn) {   // no census time in [t0, t1): the whole residence in interval ci - 1
+        if (p.ci > 0 && t1 > t0) {
+            const double r = (WGT && c.dust_weight) ? weight_integral(t0, t1, t0, lw0, ka) : t1 - t0;
+            path_add(p, w + c.census_path_off, (uint64_t)(p.ci - 1) * ns + s, (uint64_t)rint(r * kPathFix));
+        }
+        return;
+    }
+    const double *ct = reinterpret_cast<const double *>(tb + c.off_census);
     int lo = p.ci;   // first census time >= t0: the packet's clock never goes back
     while (lo <= n && ct[lo] < t0) ++lo;
     p.ci = lo;
-    unsigned long long *w = tally + c.tally_off;
-    const uint64_t ns = c.n_states;
+    p.tn = lo <= n ? ct[lo] : 0.0;
     for (int e = lo; e <= n && ct[e] < t1; ++e)
         atomicAdd(&w[c.census_bin_off + (uint64_t)e * ns + s],
                   (WGT && c.dust_weight) ? (unsigned long long)rint(exp(-(lw0 + ka * (ct[e] - t0))) * kPathFix) : 1ull);
@@ -269,17 +279,14 @@ __device__ __forceinline__ void census_add(Pk1 &p, const DevCloud &c, const uint
 // Eq. 18: a leak of a step that stayed over [t0, t1) adds v times its residence in each census
 // interval to `cell` (signed fixed point, 2^-24); with continuous dust weights, v times the
 // weight's integral over the residence (the path correction).
+// lo is the first census index whose time is >= t0 (the packet's index after census_add of
+// the same residence).
 template <bool WGT>
 __device__ __forceinline__ void accel_add(const DevCloud &c, const uint8_t *__restrict__ tb, unsigned long long *__restrict__ tally,
-                          int cell, double t0, double t1, double v, double lw0, double ka)
+                          int cell, double t0, double t1, double v, double lw0, double ka, int lo)
 {
     const double *ct = reinterpret_cast<const double *>(tb + c.off_census);
     const int n = c.n_census;
-    int lo = 0, hi = n + 1;   // first census time >= t0
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (ct[mid] < t0) lo = mid + 1; else hi = mid;
-    }
     unsigned long long *w = tally + c.tally_off + c.census_accel_off;
     for (int i = lo > 0 ? lo - 1 : 0; i < n && ct[i] < t1; ++i) {
         const double a0 = fmax(t0, ct[i]), b0 = fmin(t1, ct[i + 1]);
@@ -415,7 +422,7 @@ __device__ __forceinline__ void ddmc_step1(Pk1 &p, const DevCloud &c, const uint
     const int f = v >= reinterpret_cast<const uint32_t *>(tb + c.off_face_split)[s] ? 1 : 0;
     const double *kt = reinterpret_cast<const double *>(tb + c.off_k);
     const double dir = f ? 1.0 : -1.0;
-    if (CEN && c.n_census > 0) accel_add<WGT>(c, tb, tally, p.cell, t0, p.t, dir * kt[s], lw0, ka);   // outward leakage (eq. 18)
+    if (CEN && c.n_census > 0) accel_add<WGT>(c, tb, tally, p.cell, t0, p.t, dir * kt[s], lw0, ka, p.ci);   // outward leakage (eq. 18)
     const float xin = bin_x(c, tb, p.j, uf(draw(p.r, a)));
     const int nbc = neighbour1(c, p.cell, f);
     const float4 *mcell = reinterpret_cast<const float4 *>(tb + c.off_mcell);
@@ -463,7 +470,7 @@ __device__ __forceinline__ void ddmc_step1(Pk1 &p, const DevCloud &c, const uint
         }
     }
     if (CEN && c.n_census > 0 && ddmc_in)   // inward leakage into a DDMC state (eq. 18)
-        accel_add<WGT>(c, tb, tally, p.cell, t0, p.t, dir * kt[(int64_t)p.cell * nb + p.j], lw0, ka);
+        accel_add<WGT>(c, tb, tally, p.cell, t0, p.t, dir * kt[(int64_t)p.cell * nb + p.j], lw0, ka, p.ci);
 }
 
 // One continuous-MC event (a scattering or a boundary crossing) of a packet in a thin state.
@@ -725,6 +732,7 @@ __global__ __launch_bounds__(256) void walk1dh(const uint8_t *__restrict__ tb, M
     if (CEN) path_init();
     p.cn = 0;
     p.ci = 0;
+    p.tn = -__builtin_inf();
     p.steps = 0;
     p.mcs = p.tomc = p.toddmc = p.refl = 0u;
     p.r = Rng{0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 4u, false, 0u, 0u, 0u, 0u};
@@ -771,6 +779,7 @@ __global__ __launch_bounds__(256) void walk1dh(const uint8_t *__restrict__ tb, M
                         p.t = 0.0;
                         p.lw = 0.0;
                         p.ci = 0;
+                        p.tn = -__builtin_inf();
                         if (c.off_src_t) {   // emission uniform over the source's window
                             const double *tw = reinterpret_cast<const double *>(tb + c.off_src_t) + 2 * lo;
                             p.t = tw[0] + (tw[1] - tw[0]) * ud(draw(p.r, a));
