@@ -113,7 +113,7 @@ def run(m, n_packets=None, seed=0, first_id=0, max_steps=(1 << 62), n_threads=No
     th = np.zeros(TIME_BINS + 2, dtype=np.int64)
     sh = np.zeros(STEP_BINS, dtype=np.int64)
     R = _Result(spec.ctypes.data, th.ctypes.data, sh.ctypes.data, 0.0, 0.0, 0.0, 0.0, 0, 0, 0)
-    nthr = n_threads or min(16, os.cpu_count() or 1)   # at most the 16 cores a one-GPU machine shares
+    nthr = n_threads or min(16, os.cpu_count() or 1)   # at most 16 threads
     rc = lib.o1_run(C.byref(P), first_id, n, seed, max_steps, nthr, C.byref(R))
     if rc != 0:
         raise RuntimeError("o1_run failed")
