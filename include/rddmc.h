@@ -48,7 +48,7 @@ typedef enum {
     RDDMC_OK = 0,
     RDDMC_EINVAL = -1,        /* malformed grid, non-finite or negative input, tau_threshold in (0,2) */
     RDDMC_ESIZE = -2,         /* a caller buffer is smaller than the *_bytes query requires */
-    RDDMC_EUNSUPPORTED = -3,  /* a feature combination this build does not implement */
+    RDDMC_EUNSUPPORTED = -3,  /* a feature combination the library does not implement */
     RDDMC_ENUMERIC = -4,      /* a table entry came out non-finite or non-positive */
     RDDMC_EHIP = -5           /* a HIP runtime call failed */
 } rddmc_status;
