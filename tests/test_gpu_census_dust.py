@@ -1,6 +1,7 @@
 """GPU time-dependent estimators (eq. 17: 'bin' counts at census times, 'path' residence
 times per census interval), emission windows and dust (Sec. 2.4) against the exact chain's
-transient law and absorption channel, the oracle walker, and exponential-integral transmission.
+transient law and absorption channel, the oracle walker, and exponential-integral transmission;
+census tallies bit-identical across launch shapes and shard splits.
 
 Bars: census counts are binomial (the 3 sigma rule per state and time); a residence-time
 average lies in [0, 1] so its variance is at most its mean (5 such sigmas); fractions of
